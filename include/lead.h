@@ -1,0 +1,177 @@
+/*
+ * liblead -- LEAD decoding of quantum Tanner codes on AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The method is LEAD (arXiv 2605.17796): project the syndrome onto the local
+ * views of the vertices of the left-right Cayley complex, decode every local
+ * view in parallel, aggregate the local soft outputs with the
+ * alpha-regularisation, and run the global decoder with that prior
+ * (Algorithm 1).  Both the local and the global decoder here are flooding
+ * min-sum belief propagation.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Bit packing: bit i of a packed row is bit (i % 64) of 64-bit word i / 64.
+ *  * Check types: LEAD_CHECK_Z are the Z-type generators C_A (x) C_B on the
+ *    vertex set V0 and detect X errors; LEAD_CHECK_X are the X-type
+ *    generators C_A^perp (x) C_B^perp on V1 and detect Z errors (Sec. II-B).
+ *  * Numbering: check (g, rho) of type t is global check g * r_t + rho, where
+ *    rho = rho_A * k_B + rho_B enumerates the reduced-echelon bases of the
+ *    two local codes (their duals for X checks); local variable (i, j) of a
+ *    view is i * Delta + j, i indexing A and j indexing B (Appendix A,
+ *    eq. (product) is this layout).  Qubit ids rank the squares by their
+ *    lexicographically smallest V0 description (g, i, j).
+ *  * Status codes: every call returns lead_status; on failure
+ *    lead_last_error() returns a message (thread-local, valid until the next
+ *    call on the same thread).
+ *  * Device pointers are HIP device addresses (for example the data_ptr of a
+ *    torch tensor on the GPU); `stream` is a hipStream_t (NULL = the default
+ *    stream).  Device work is enqueued asynchronously on that stream and the
+ *    call returns without waiting; device faults surface on a later call.
+ *  * Ownership: callers own every buffer they pass.  Code objects own host
+ *    tables; decoders own their device tables and workspace.  A code may be
+ *    shared between threads; a decoder must be used by one host thread at a
+ *    time and must outlive the device work it enqueued.
+ */
+#ifndef LEAD_H
+#define LEAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LEAD_OK = 0,
+    LEAD_E_ARG = -1,          /* NULL pointer, size out of range, bad enum      */
+    LEAD_E_GROUP = -2,        /* table is not a group                           */
+    LEAD_E_SYMMETRY = -3,     /* A or B not inverse-closed, repeated, identity  */
+    LEAD_E_TNC = -4,          /* Total No-Conjugacy condition fails             */
+    LEAD_E_LOCALCODE = -5,    /* local code rank/distance, or CSS fails         */
+    LEAD_E_NOMEM = -6,        /* host or device allocation failed               */
+    LEAD_E_DEVICE = -7,       /* HIP runtime error (message has the HIP string) */
+    LEAD_E_CAPACITY = -8,     /* batch larger than the decoder was sized for    */
+    LEAD_E_UNSUPPORTED = -9   /* shape the compiled kernels do not cover        */
+} lead_status;
+
+typedef enum { LEAD_CHECK_Z = 0, LEAD_CHECK_X = 1 } lead_check_type;
+typedef enum { LEAD_PRIOR_PER_SHOT = 0, LEAD_PRIOR_SHARED = 1, LEAD_PRIOR_FULL = 2 } lead_prior_mode;
+typedef enum { LEAD_STAGE_FULL = 0, LEAD_STAGE_LOCAL = 1 } lead_stage;
+
+typedef struct lead_code lead_code;
+typedef struct lead_decoder lead_decoder;
+
+const char *lead_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Code construction (host only; no device work).  Sec. II-A, II-B.          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t order;            /* |G|, 1..65535                                   */
+    const uint16_t *mul;      /* order*order, mul[g*order + h] = index of g*h    */
+    int32_t delta;            /* |A| = |B|, 2..8                                 */
+    const int32_t *A;         /* delta element indices; order = local coords     */
+    const int32_t *B;
+    int32_t kA, kB;           /* local code dimensions, 1..delta-1               */
+    const uint64_t *GA;       /* kA generator rows of C_A, bit c = coordinate c  */
+    const uint64_t *GB;       /* kB generator rows of C_B                        */
+} lead_code_desc;
+
+typedef struct {
+    int32_t order, delta, n;  /* n = order * delta^2 / 2 qubits                  */
+    int32_t r[2];             /* checks per vertex, indexed by lead_check_type   */
+    int32_t m[2];             /* global checks = order * r[t]                    */
+    int32_t rank[2];          /* GF(2) rank of H_Z, H_X                          */
+    int32_t k;                /* logical qubits n - rank[0] - rank[1]            */
+    int32_t eloc[2];          /* edges of one local Tanner graph                 */
+} lead_code_info;
+
+/* Validates (group axioms, A = A^-1, B = B^-1, identity excluded, TNC,
+ * full-rank local codes with distance >= 2 and dual distance >= 2, CSS) and
+ * builds the code.  The descriptor's arrays are copied. */
+lead_status lead_code_create(const lead_code_desc *desc, lead_code **out);
+lead_status lead_code_query(const lead_code *code, lead_code_info *out);
+/* Host CSR of H_t: indptr has m[t]+1 entries, indices one per edge (row
+ * order, columns ascending).  Pass indices = NULL to get only indptr. */
+lead_status lead_code_get_H(const lead_code *code, lead_check_type t, int32_t *indptr, int32_t *indices);
+/* Host view table of type t: order x delta^2 qubit ids (V0 for Z, V1 for X). */
+lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_t *view);
+void lead_code_destroy(lead_code *code);
+
+/* ------------------------------------------------------------------------ */
+/* Decoding (Algorithm 1).                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    float alpha;              /* regularisation scale, (0, 1]  (Alg. 1 Phase 2)   */
+    float ms_scale;           /* min-sum scale beta, (0, 1]                       */
+    int32_t max_iter_local;   /* local BP iteration cap, 1..1000                  */
+    int32_t max_iter_global;  /* global BP iteration cap, 1..1000                 */
+    float llr_clamp;          /* |mu|, |L|, |lambda'| clamped to this, > 0        */
+    int32_t early_exit;       /* 1: stop a BP run at the first H e = s            */
+    int32_t stage;            /* lead_stage: FULL, or LOCAL (Phases 1-2 only)      */
+    int32_t boost;            /* 1: Phase-1 confidence boost (Alg. 1)             */
+} lead_params;
+
+/* Per-shot statistics (32 bytes). */
+typedef struct {
+    int32_t converged;              /* global H e = s reached (0 in LOCAL stage)   */
+    int32_t global_iters;           /* global BP iterations run                    */
+    int32_t local_iters_sum;        /* sum over vertices of local iterations       */
+    int32_t local_iters_max;
+    int32_t local_converged_views;  /* vertices whose local BP reached H_v e_v = s_v */
+    int32_t reserved[3];
+} lead_shot_stats;
+
+/* Creates a decoder for the checks of type `t` and uploads the device tables
+ * of the code to the current HIP device.  `max_shots` bounds the batch size
+ * of every later call (it sizes the per-round workspace of
+ * lead_decode_plain). */
+lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const lead_params *params,
+                                int64_t max_shots, lead_decoder **out);
+lead_status lead_decoder_set_params(lead_decoder *dec, const lead_params *params);
+void lead_decoder_destroy(lead_decoder *dec);
+
+/* LEAD decode of `shots` syndromes in one fused launch: every shot runs
+ * Phase 1 (local BP on each vertex view), Phase 2 (aggregation) and, in the
+ * FULL stage, Phase 3 (global BP) inside one workgroup, with all messages
+ * kept on chip.
+ *   d_synd      shots x synd_words packed syndromes, synd_words >= ceil(m/64)
+ *   d_prior     channel LLRs ln((1-p)/p): PER_SHOT: shots floats; SHARED: n
+ *               floats; FULL: shots x n floats
+ *   d_ehat      shots x ehat_words packed estimates (FULL stage; may be NULL
+ *               in the LOCAL stage), ehat_words >= ceil(n/64)
+ *   d_post      shots x n posterior LLRs of global BP, or NULL
+ *   d_prior_llr shots x n regularised priors lambda' (Phase 2 output), or NULL;
+ *               required in the LOCAL stage
+ *   d_stats     shots lead_shot_stats, or NULL
+ * A shot that does not converge is not an error: its estimate and
+ * posteriors are still written and stats.converged is 0. */
+lead_status lead_decode(lead_decoder *dec, int64_t shots, const uint64_t *d_synd, int64_t synd_words,
+                        const float *d_prior, lead_prior_mode mode, uint64_t *d_ehat, int64_t ehat_words,
+                        float *d_post, float *d_prior_llr, lead_shot_stats *d_stats, void *stream);
+
+/* The same decode as a plain sequence of launches: one launch for Phases 1-2
+ * (lambda' written to HBM), then one launch per global BP round with the
+ * message state in HBM, and a host-visible convergence count after every
+ * round (the call synchronises `stream` once per round).  Outputs are
+ * identical to lead_decode's. */
+lead_status lead_decode_plain(lead_decoder *dec, int64_t shots, const uint64_t *d_synd, int64_t synd_words,
+                              const float *d_prior, lead_prior_mode mode, uint64_t *d_ehat,
+                              int64_t ehat_words, float *d_post, float *d_prior_llr,
+                              lead_shot_stats *d_stats, void *stream);
+
+/* s = H_t e for `shots` packed error rows (device pointers). */
+lead_status lead_syndrome(const lead_decoder *dec, int64_t shots, const uint64_t *d_err, int64_t err_words,
+                          uint64_t *d_synd, int64_t synd_words, void *stream);
+
+/* Launch geometry of lead_decode: shots handled per workgroup (0 = the
+ * library's choice).  Results do not depend on it. */
+lead_status lead_decoder_set_schedule(lead_decoder *dec, int32_t shots_per_workgroup);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

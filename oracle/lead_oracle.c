@@ -473,7 +473,22 @@ void oracle_syndrome(const oracle_code *c, int type, int shots, const uint64_t *
 /* belief propagation (the LocalDecoder / GlobalDecoder of Alg. 1)      */
 /* ------------------------------------------------------------------ */
 
-typedef struct { double *msg, *mu; } bp_work;
+typedef struct { double *msg, *mu; uint64_t rng; } bp_work;
+
+/* SplitMix64 (Steele, Lea, Flood 2014): the perturbation stream. */
+static uint64_t splitmix64(uint64_t *state) {
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* x * (1 + eps * xi), xi uniform in [-1, 1); identity when eps == 0. */
+static double perturbed(double x, double eps, uint64_t *state) {
+    if (eps == 0.0) return x;
+    double xi = (double)(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    return x * (1.0 + eps * xi);
+}
 
 /* Flooding BP on Tanner graph t.
  *   mu_{j->c} = clamp(lam_j + sum_{c' ni j, c' != c} m_{c'->j})
@@ -497,7 +512,7 @@ static int bp_run(const tanner *t, const uint8_t *s, const double *lam, const or
                 double acc = lam[j];
                 for (int y = t->col_ptr[j]; y < t->col_ptr[j + 1]; y++)
                     if (t->col_edge[y] != x) acc += w->msg[t->col_edge[y]];
-                w->mu[x] = clampd(acc, lim);
+                w->mu[x] = clampd(perturbed(acc, p->perturb, &w->rng), lim);
                 if (margin && fabs(w->mu[x]) < *margin) *margin = fabs(w->mu[x]);
             }
         /* check-to-variable messages, each excluding its own variable */
@@ -521,13 +536,13 @@ static int bp_run(const tanner *t, const uint8_t *s, const double *lam, const or
                     }
                     out = 2.0 * atanh(prod);
                 }
-                w->msg[x] = out;
+                w->msg[x] = perturbed(out, p->perturb, &w->rng);
             }
         /* posteriors and hard decisions */
         for (int j = 0; j < t->cols; j++) {
             double acc = lam[j];
             for (int y = t->col_ptr[j]; y < t->col_ptr[j + 1]; y++) acc += w->msg[t->col_edge[y]];
-            L[j] = clampd(acc, lim);
+            L[j] = clampd(perturbed(acc, p->perturb, &w->rng), lim);
             if (margin && fabs(L[j]) < *margin) *margin = fabs(L[j]);
             e[j] = L[j] < 0 ? 1 : 0;
         }
@@ -553,6 +568,7 @@ static int bp_run(const tanner *t, const uint8_t *s, const double *lam, const or
 }
 
 static void work_alloc(bp_work *w, int nedges) {
+    w->rng = 0;
     w->msg = (double *)malloc(sizeof(double) * (size_t)(nedges > 0 ? nedges : 1));
     w->mu = (double *)malloc(sizeof(double) * (size_t)(nedges > 0 ? nedges : 1));
 }
@@ -623,6 +639,8 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
         const double *lam = prior + (size_t)shot * n;
         for (int i = 0; i < m; i++) s[i] = (uint8_t)get_bit(sw, i);
         double margin = INFINITY;
+        wl.rng = p->perturb_seed * 0x100000001B3ull + (uint64_t)shot * 2;
+        wg.rng = p->perturb_seed * 0x100000001B3ull + (uint64_t)shot * 2 + 1;
 
         int it_sum = 0, it_max = 0, nconv = 0;
 
@@ -651,6 +669,8 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
 
         /* Phase 2: p_i = alpha * Average(S_i), converted back to an LLR */
         oracle_aggregate(n, N, D2, view, pall, p->alpha, p->llr_clamp, NULL, lamp);
+        if (p->perturb > 0.0)
+            for (int i = 0; i < n; i++) lamp[i] = clampd(perturbed(lamp[i], p->perturb, &wl.rng), p->llr_clamp);
         if (lam_out)
             for (int i = 0; i < n; i++) lam_out[(size_t)shot * n + i] = lamp[i];
 

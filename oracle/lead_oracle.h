@@ -49,6 +49,14 @@ typedef struct {
     int    early_exit;   /* stop a BP run as soon as H e = s            */
     int    stage;        /* OR_STAGE_FULL or OR_STAGE_LOCAL             */
     int    boost;        /* apply Phase-1 confidence boost (1) or not (0) */
+    /* Rounding-sensitivity probe (Monte Carlo arithmetic): when perturb > 0,
+     * every computed mu, message, posterior sum and lambda' is multiplied by
+     * (1 + perturb * xi), xi uniform in [-1, 1) from a SplitMix64 stream
+     * keyed by perturb_seed.  perturb = 0 is the plain oracle.  Used by the
+     * tests to tell well-conditioned shots from ones whose result is not
+     * determined to the tolerance by FP32-sized rounding. */
+    double perturb;
+    uint64_t perturb_seed;
 } oracle_params;
 
 /* info[] layout for oracle_info */

@@ -24,13 +24,13 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("bp", C.c_int), ("ms_scale", C.c_double),
                 ("max_iter_local", C.c_int), ("max_iter_global", C.c_int),
                 ("llr_clamp", C.c_double), ("early_exit", C.c_int), ("stage", C.c_int),
-                ("boost", C.c_int)]
+                ("boost", C.c_int), ("perturb", C.c_double), ("perturb_seed", C.c_uint64)]
 
 
 def params(alpha=1.0, bp=MINSUM, ms_scale=0.75, max_iter_local=32, max_iter_global=32,
-           llr_clamp=30.0, early_exit=1, stage=FULL, boost=1) -> Params:
+           llr_clamp=30.0, early_exit=1, stage=FULL, boost=1, perturb=0.0, perturb_seed=0) -> Params:
     return Params(alpha, bp, ms_scale, max_iter_local, max_iter_global, llr_clamp,
-                  early_exit, stage, boost)
+                  early_exit, stage, boost, perturb, perturb_seed)
 
 
 _lib = None

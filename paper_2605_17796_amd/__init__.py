@@ -1,0 +1,324 @@
+"""LEAD decoding of quantum Tanner codes on MI355X.
+
+Thin binding over the C ABI of ``liblead.so`` (declared in include/lead.h).
+Every step of decoding runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch provides device memory and streams.
+
+Low-level functions carry the C names (``lead_code_create``,
+``lead_decode`` ...).  ``Code`` and ``Decoder`` wrap them for torch tensors.
+Loading fails loudly if the library has not been built
+(``python -m paper_2605_17796_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblead.so")
+
+LEAD_OK = 0
+LEAD_CHECK_Z, LEAD_CHECK_X = 0, 1
+LEAD_PRIOR_PER_SHOT, LEAD_PRIOR_SHARED, LEAD_PRIOR_FULL = 0, 1, 2
+LEAD_STAGE_FULL, LEAD_STAGE_LOCAL = 0, 1
+STATUS_NAMES = {0: "LEAD_OK", -1: "LEAD_E_ARG", -2: "LEAD_E_GROUP", -3: "LEAD_E_SYMMETRY", -4: "LEAD_E_TNC",
+                -5: "LEAD_E_LOCALCODE", -6: "LEAD_E_NOMEM", -7: "LEAD_E_DEVICE", -8: "LEAD_E_CAPACITY",
+                -9: "LEAD_E_UNSUPPORTED"}
+
+
+class LeadError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class lead_code_desc(C.Structure):
+    _fields_ = [("order", C.c_int32), ("mul", C.c_void_p), ("delta", C.c_int32), ("A", C.c_void_p),
+                ("B", C.c_void_p), ("kA", C.c_int32), ("kB", C.c_int32), ("GA", C.c_void_p),
+                ("GB", C.c_void_p)]
+
+
+class lead_code_info(C.Structure):
+    _fields_ = [("order", C.c_int32), ("delta", C.c_int32), ("n", C.c_int32), ("r", C.c_int32 * 2),
+                ("m", C.c_int32 * 2), ("rank", C.c_int32 * 2), ("k", C.c_int32), ("eloc", C.c_int32 * 2)]
+
+
+class lead_params(C.Structure):
+    _fields_ = [("alpha", C.c_float), ("ms_scale", C.c_float), ("max_iter_local", C.c_int32),
+                ("max_iter_global", C.c_int32), ("llr_clamp", C.c_float), ("early_exit", C.c_int32),
+                ("stage", C.c_int32), ("boost", C.c_int32)]
+
+
+STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views")
+
+SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
+           "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
+           "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule"]
+
+_lib = None
+
+
+def lib():
+    """The loaded liblead.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_17796_amd.build`")
+        # torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it
+        # first makes liblead.so bind to that same runtime instead of pulling a
+        # second copy from /opt/rocm into the process.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        L.lead_last_error.restype = C.c_char_p
+        L.lead_code_create.argtypes = [C.POINTER(lead_code_desc), C.POINTER(P)]
+        L.lead_code_query.argtypes = [P, C.POINTER(lead_code_info)]
+        L.lead_code_get_H.argtypes = [P, I32, P, P]
+        L.lead_code_get_views.argtypes = [P, I32, P]
+        L.lead_code_destroy.argtypes = [P]
+        L.lead_code_destroy.restype = None
+        L.lead_decoder_create.argtypes = [P, I32, C.POINTER(lead_params), I64, C.POINTER(P)]
+        L.lead_decoder_set_params.argtypes = [P, C.POINTER(lead_params)]
+        L.lead_decoder_set_schedule.argtypes = [P, I32]
+        L.lead_decoder_destroy.argtypes = [P]
+        L.lead_decoder_destroy.restype = None
+        dec_args = [P, I64, P, I64, P, I32, P, I64, P, P, P, P]
+        L.lead_decode.argtypes = dec_args
+        L.lead_decode_plain.argtypes = dec_args
+        L.lead_syndrome.argtypes = [P, I64, P, I64, P, I64, P]
+        for name in SYMBOLS:
+            fn = getattr(L, name)
+            if name not in ("lead_code_destroy", "lead_decoder_destroy", "lead_last_error"):
+                fn.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LEAD_OK:
+        raise LeadError(status, lib().lead_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# C-named wrappers (argument marshalling only)
+# ---------------------------------------------------------------------------
+
+def lead_code_create(mul, delta, A, B, GA, GB):
+    mul = np.ascontiguousarray(mul, dtype=np.uint16)
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    B = np.ascontiguousarray(B, dtype=np.int32)
+    GA = np.ascontiguousarray([int(x) for x in GA], dtype=np.uint64)
+    GB = np.ascontiguousarray([int(x) for x in GB], dtype=np.uint64)
+    desc = lead_code_desc(mul.shape[0], _np_ptr(mul), delta, _np_ptr(A), _np_ptr(B), len(GA), len(GB),
+                          _np_ptr(GA), _np_ptr(GB))
+    h = C.c_void_p()
+    _check(lib().lead_code_create(C.byref(desc), C.byref(h)))
+    return h
+
+
+def lead_code_query(code) -> lead_code_info:
+    info = lead_code_info()
+    _check(lib().lead_code_query(code, C.byref(info)))
+    return info
+
+
+def lead_code_get_H(code, t, m):
+    indptr = np.zeros(m + 1, dtype=np.int32)
+    _check(lib().lead_code_get_H(code, t, _np_ptr(indptr), None))
+    indices = np.zeros(int(indptr[-1]), dtype=np.int32)
+    _check(lib().lead_code_get_H(code, t, _np_ptr(indptr), _np_ptr(indices)))
+    return indptr, indices
+
+
+def lead_code_get_views(code, t, order, d2):
+    view = np.zeros((order, d2), dtype=np.int32)
+    _check(lib().lead_code_get_views(code, t, _np_ptr(view)))
+    return view
+
+
+def lead_code_destroy(code):
+    lib().lead_code_destroy(code)
+
+
+def lead_params_make(alpha=1.0, ms_scale=0.75, max_iter_local=32, max_iter_global=32, llr_clamp=30.0,
+                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1) -> lead_params:
+    return lead_params(alpha, ms_scale, max_iter_local, max_iter_global, llr_clamp, early_exit, stage, boost)
+
+
+def lead_decoder_create(code, t, params: lead_params, max_shots: int):
+    h = C.c_void_p()
+    _check(lib().lead_decoder_create(code, t, C.byref(params), max_shots, C.byref(h)))
+    return h
+
+
+def lead_decoder_set_params(dec, params: lead_params):
+    _check(lib().lead_decoder_set_params(dec, C.byref(params)))
+
+
+def lead_decoder_set_schedule(dec, shots_per_workgroup: int):
+    _check(lib().lead_decoder_set_schedule(dec, shots_per_workgroup))
+
+
+def lead_decoder_destroy(dec):
+    lib().lead_decoder_destroy(dec)
+
+
+def lead_decode(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream):
+    _check(lib().lead_decode(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats,
+                             stream))
+
+
+def lead_decode_plain(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream):
+    _check(lib().lead_decode_plain(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam,
+                                   stats, stream))
+
+
+def lead_syndrome(dec, shots, err, err_words, synd, synd_words, stream):
+    _check(lib().lead_syndrome(dec, shots, err, err_words, synd, synd_words, stream))
+
+
+# ---------------------------------------------------------------------------
+# torch-facing wrappers
+# ---------------------------------------------------------------------------
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, name, shape, dtype, optional=False):
+    """Check a device tensor before its pointer crosses the C ABI (the
+    library cannot see buffer sizes)."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    if str(t.dtype) != "torch." + dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous GPU tensor")
+    if len(t.shape) != len(shape) or any(w is not None and w != g for w, g in zip(shape, t.shape)):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Code:
+    """A quantum Tanner code built by the library from (G, A, B, C_A, C_B)."""
+
+    def __init__(self, mul, delta, A, B, GA, GB):
+        self._h = lead_code_create(mul, delta, A, B, GA, GB)
+        self.info = lead_code_query(self._h)
+
+    @classmethod
+    def from_spec(cls, spec):
+        return cls(spec.mul, spec.delta, spec.A, spec.B, spec.GA, spec.GB)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.lead_code_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def n(self):
+        return self.info.n
+
+    def m(self, t=LEAD_CHECK_Z):
+        return self.info.m[t]
+
+    def H(self, t=LEAD_CHECK_Z) -> np.ndarray:
+        indptr, indices = lead_code_get_H(self._h, t, self.info.m[t])
+        H = np.zeros((self.info.m[t], self.info.n), dtype=np.uint8)
+        rows = np.repeat(np.arange(self.info.m[t]), np.diff(indptr))
+        H[rows, indices] = 1
+        return H
+
+    def views(self, t=LEAD_CHECK_Z) -> np.ndarray:
+        return lead_code_get_views(self._h, t, self.info.order, self.info.delta ** 2)
+
+
+class Decoder:
+    """LEAD decoder for one check type of a code, on the current device."""
+
+    def __init__(self, code: Code, t=LEAD_CHECK_Z, max_shots=1 << 20, **params):
+        self.code = code
+        self.t = t
+        self.params = lead_params_make(**params)
+        self.max_shots = max_shots
+        self._h = lead_decoder_create(code._h, t, self.params, max_shots)
+        self.n = code.info.n
+        self.m = code.info.m[t]
+        self.synd_words = (self.m + 63) // 64
+        self.ehat_words = (self.n + 63) // 64
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.lead_decoder_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def set_params(self, **params):
+        self.params = lead_params_make(**params)
+        lead_decoder_set_params(self._h, self.params)
+
+    def set_schedule(self, shots_per_workgroup: int):
+        lead_decoder_set_schedule(self._h, shots_per_workgroup)
+
+    def alloc_outputs(self, shots, device="cuda", post=True, lam=False, stats=True):
+        import torch
+        out = dict(ehat=torch.empty((shots, self.ehat_words), dtype=torch.int64, device=device))
+        out["post"] = torch.empty((shots, self.n), dtype=torch.float32, device=device) if post else None
+        out["lam"] = torch.empty((shots, self.n), dtype=torch.float32, device=device) if lam else None
+        out["stats"] = torch.empty((shots, 8), dtype=torch.int32, device=device) if stats else None
+        return out
+
+    def decode(self, synd, prior, mode=LEAD_PRIOR_PER_SHOT, out=None, post=True, lam=False, stream=None,
+               plain=False):
+        """synd: int64 tensor [S, W] of packed syndromes on the GPU; prior:
+        float32 LLRs ([S] PER_SHOT, [n] SHARED, [S, n] FULL).  Returns the
+        dict of output tensors (ehat packed int64, post, lam, stats [S, 8])."""
+        shots = int(synd.shape[0])
+        _need(synd, "synd", (shots, None), "int64")
+        if synd.shape[1] < self.synd_words:
+            raise ValueError(f"synd has {synd.shape[1]} words per shot, need {self.synd_words}")
+        want = {LEAD_PRIOR_PER_SHOT: (shots,), LEAD_PRIOR_SHARED: (self.n,), LEAD_PRIOR_FULL: (shots, self.n)}
+        if mode not in want:
+            raise ValueError("bad prior mode")
+        _need(prior, "prior", want[mode], "float32")
+        if out is None:
+            out = self.alloc_outputs(shots, synd.device, post=post, lam=lam)
+        _need(out["ehat"], "ehat", (shots, self.ehat_words), "int64", optional=True)
+        _need(out["post"], "post", (shots, self.n), "float32", optional=True)
+        _need(out["lam"], "lam", (shots, self.n), "float32", optional=True)
+        _need(out["stats"], "stats", (shots, 8), "int32", optional=True)
+        fn = lead_decode_plain if plain else lead_decode
+        fn(self._h, shots, _ptr(synd), int(synd.shape[1]), _ptr(prior), mode, _ptr(out["ehat"]),
+           self.ehat_words if out["ehat"] is not None else 0, _ptr(out["post"]), _ptr(out["lam"]),
+           _ptr(out["stats"]), _stream(stream))
+        return out
+
+    def syndrome(self, err, stream=None):
+        import torch
+        shots = int(err.shape[0])
+        _need(err, "err", (shots, None), "int64")
+        if err.shape[1] < self.ehat_words:
+            raise ValueError(f"err has {err.shape[1]} words per shot, need {self.ehat_words}")
+        synd = torch.empty((shots, self.synd_words), dtype=torch.int64, device=err.device)
+        lead_syndrome(self._h, shots, _ptr(err), int(err.shape[1]), _ptr(synd), self.synd_words, _stream(stream))
+        return synd

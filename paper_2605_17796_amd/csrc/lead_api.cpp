@@ -1,0 +1,312 @@
+// C ABI of liblead: code construction, decoder objects, decode entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lead.h"
+#include "code_build.hpp"
+#include "lead_kernels.hpp"
+
+struct lead_code {
+    lead::Code c;
+};
+
+struct lead_decoder {
+    lead::Code const *code = nullptr;
+    std::shared_ptr<lead::Code> keep;       // decoders keep their own copy of the tables
+    int type = 0;
+    lead_params params{};
+    int64_t max_shots = 0;
+    int device = 0;
+    int D = 0, N = 0, n = 0, r = 0, m = 0, own_max = 0, spw = 1;
+    uint64_t mask[lead::kMaxChecks] = {};
+    int32_t *d_view = nullptr;
+    uint32_t *d_own = nullptr;
+    // per-round state of lead_decode_plain (allocated on first use)
+    float *d_S = nullptr, *d_cst = nullptr, *d_lamp = nullptr;
+    int32_t *d_status = nullptr, *d_active = nullptr, *h_active = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+lead_status fail(lead_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+lead_status hip_fail(hipError_t e, const char *what) {
+    return fail(LEAD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+lead_status check_params(const lead_params *p) {
+    if (!p) return fail(LEAD_E_ARG, "params is NULL");
+    if (!(p->alpha > 0.f && p->alpha <= 1.f)) return fail(LEAD_E_ARG, "alpha must be in (0, 1]");
+    if (!(p->ms_scale > 0.f && p->ms_scale <= 1.f)) return fail(LEAD_E_ARG, "ms_scale must be in (0, 1]");
+    if (p->max_iter_local < 1 || p->max_iter_local > 1000 || p->max_iter_global < 1 || p->max_iter_global > 1000)
+        return fail(LEAD_E_ARG, "iteration caps must be in 1..1000");
+    if (!(p->llr_clamp > 0.f) || !std::isfinite(p->llr_clamp)) return fail(LEAD_E_ARG, "llr_clamp must be > 0");
+    if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL) return fail(LEAD_E_ARG, "bad stage");
+    return LEAD_OK;
+}
+
+void free_plain(lead_decoder *d) {
+    (void)hipFree(d->d_S);
+    (void)hipFree(d->d_cst);
+    (void)hipFree(d->d_lamp);
+    (void)hipFree(d->d_status);
+    (void)hipFree(d->d_active);
+    if (d->h_active) (void)hipHostFree(d->h_active);
+    d->d_S = d->d_cst = d->d_lamp = nullptr;
+    d->d_status = d->d_active = d->h_active = nullptr;
+}
+
+lead::DecodeArgs base_args(const lead_decoder *d) {
+    lead::DecodeArgs a{};
+    a.view = d->d_view;
+    a.own = d->d_own;
+    a.N = d->N;
+    a.n = d->n;
+    a.r = d->r;
+    a.own_max = d->own_max;
+    a.spw = d->spw;
+    a.alpha = d->params.alpha;
+    a.beta = d->params.ms_scale;
+    a.clampv = d->params.llr_clamp;
+    a.Tl = d->params.max_iter_local;
+    a.Tg = d->params.max_iter_global;
+    a.early_exit = d->params.early_exit ? 1 : 0;
+    a.stage = d->params.stage;
+    a.boost = d->params.boost ? 1 : 0;
+    for (int c = 0; c < lead::kMaxChecks; ++c) a.mask[c] = c < d->r ? d->mask[c] : 0;
+    return a;
+}
+
+lead_status check_decode_args(const lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
+                              const float *prior, lead_prior_mode mode, const uint64_t *ehat,
+                              int64_t ehat_words, const float *lam) {
+    if (!d) return fail(LEAD_E_ARG, "decoder is NULL");
+    if (shots < 0) return fail(LEAD_E_ARG, "shots < 0");
+    if (shots > d->max_shots) return fail(LEAD_E_CAPACITY, "shots exceeds the decoder's max_shots");
+    if (shots == 0) return LEAD_OK;
+    if (!synd || !prior) return fail(LEAD_E_ARG, "syndrome or prior pointer is NULL");
+    if (synd_words < (d->m + 63) / 64) return fail(LEAD_E_ARG, "synd_words < ceil(m/64)");
+    if (mode != LEAD_PRIOR_PER_SHOT && mode != LEAD_PRIOR_SHARED && mode != LEAD_PRIOR_FULL)
+        return fail(LEAD_E_ARG, "bad prior mode");
+    if (ehat && ehat_words < (d->n + 63) / 64) return fail(LEAD_E_ARG, "ehat_words < ceil(n/64)");
+    if (d->params.stage == LEAD_STAGE_LOCAL && !lam) return fail(LEAD_E_ARG, "LOCAL stage needs d_prior_llr");
+    return LEAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lead_last_error(void) { return g_err.c_str(); }
+
+lead_status lead_code_create(const lead_code_desc *desc, lead_code **out) {
+    if (!desc || !out) return fail(LEAD_E_ARG, "NULL argument");
+    *out = nullptr;
+    lead_code *c = new (std::nothrow) lead_code();
+    if (!c) return fail(LEAD_E_NOMEM, "out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = lead::build_code(desc->order, desc->mul, desc->delta, desc->A, desc->B, desc->kA, desc->GA,
+                              desc->kB, desc->GB, c->c, err);
+    } catch (const std::bad_alloc &) {
+        delete c;
+        return fail(LEAD_E_NOMEM, "out of host memory");
+    }
+    if (rc != 0) {
+        delete c;
+        return fail((lead_status)rc, err);
+    }
+    *out = c;
+    return LEAD_OK;
+}
+
+lead_status lead_code_query(const lead_code *code, lead_code_info *o) {
+    if (!code || !o) return fail(LEAD_E_ARG, "NULL argument");
+    const lead::Code &c = code->c;
+    o->order = c.order;
+    o->delta = c.delta;
+    o->n = c.n;
+    for (int t = 0; t < 2; ++t) {
+        o->r[t] = c.t[t].r;
+        o->m[t] = c.order * c.t[t].r;
+        o->rank[t] = c.t[t].rank;
+        o->eloc[t] = c.t[t].eloc;
+    }
+    o->k = c.k;
+    return LEAD_OK;
+}
+
+lead_status lead_code_get_H(const lead_code *code, lead_check_type t, int32_t *indptr, int32_t *indices) {
+    if (!code || !indptr || (t != LEAD_CHECK_Z && t != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad argument");
+    const lead::TypeTables &tt = code->c.t[t];
+    std::copy(tt.csr_ptr.begin(), tt.csr_ptr.end(), indptr);
+    if (indices) std::copy(tt.csr_idx.begin(), tt.csr_idx.end(), indices);
+    return LEAD_OK;
+}
+
+lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_t *view) {
+    if (!code || !view || (t != LEAD_CHECK_Z && t != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad argument");
+    std::copy(code->c.t[t].view.begin(), code->c.t[t].view.end(), view);
+    return LEAD_OK;
+}
+
+void lead_code_destroy(lead_code *code) { delete code; }
+
+lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const lead_params *params,
+                                int64_t max_shots, lead_decoder **out) {
+    if (!code || !out || (t != LEAD_CHECK_Z && t != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad argument");
+    *out = nullptr;
+    if (max_shots < 0) return fail(LEAD_E_ARG, "max_shots < 0");
+    lead_status st = check_params(params);
+    if (st != LEAD_OK) return st;
+    const lead::Code &c = code->c;
+    const lead::TypeTables &tt = c.t[t];
+    const int D = c.delta, D2 = D * D;
+    if (!lead::kernel_supported(D, tt.r))
+        return fail(LEAD_E_UNSUPPORTED, "no kernel for delta=" + std::to_string(D) + " with " +
+                                            std::to_string(tt.r) + " checks per vertex");
+    for (uint64_t mk : tt.mask)
+        if (__builtin_popcountll(mk) > 32 || __builtin_popcountll(mk) < 2)
+            return fail(LEAD_E_UNSUPPORTED, "local check weight outside 2..32");
+    if (c.order > lead::kMaxWorkgroup)
+        return fail(LEAD_E_UNSUPPORTED, "group order above " + std::to_string(lead::kMaxWorkgroup));
+    std::unique_ptr<lead_decoder> d(new (std::nothrow) lead_decoder());
+    if (!d) return fail(LEAD_E_NOMEM, "out of host memory");
+    d->keep = std::make_shared<lead::Code>(c);
+    d->code = d->keep.get();
+    d->type = t;
+    d->params = *params;
+    d->max_shots = max_shots;
+    d->D = D;
+    d->N = c.order;
+    d->n = c.n;
+    d->r = tt.r;
+    d->m = c.order * tt.r;
+    d->own_max = tt.own_max;
+    for (int i = 0; i < tt.r; ++i) d->mask[i] = tt.mask[i];
+    d->spw = std::max(1, 64 / d->N);
+    hipError_t e = hipGetDevice(&d->device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    // owner lists: per view, owned local positions in increasing order
+    std::vector<uint32_t> own((size_t)d->N * d->own_max, lead::kNoOwn);
+    for (int v = 0; v < d->N; ++v) {
+        int k = 0;
+        for (int j = 0; j < D2; ++j) {
+            const int s = v * D2 + j;
+            if (!tt.owned[s]) continue;
+            const int p = tt.partner[s];
+            own[(size_t)v * d->own_max + k++] =
+                (uint32_t)j | ((uint32_t)(p % D2) << 8) | ((uint32_t)(p / D2) << 16);
+        }
+    }
+    if ((e = hipMalloc(&d->d_view, sizeof(int32_t) * tt.view.size())) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = hipMalloc(&d->d_own, sizeof(uint32_t) * own.size())) != hipSuccess) {
+        (void)hipFree(d->d_view);
+        return hip_fail(e, "hipMalloc");
+    }
+    e = hipMemcpy(d->d_view, tt.view.data(), sizeof(int32_t) * tt.view.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d->d_own, own.data(), sizeof(uint32_t) * own.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d->d_view);
+        (void)hipFree(d->d_own);
+        return hip_fail(e, "hipMemcpy");
+    }
+    *out = d.release();
+    return LEAD_OK;
+}
+
+lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) {
+    if (!d) return fail(LEAD_E_ARG, "decoder is NULL");
+    lead_status st = check_params(params);
+    if (st != LEAD_OK) return st;
+    d->params = *params;
+    return LEAD_OK;
+}
+
+lead_status lead_decoder_set_schedule(lead_decoder *d, int32_t spw) {
+    if (!d || spw < 0) return fail(LEAD_E_ARG, "bad argument");
+    if (spw == 0) spw = std::max(1, 64 / d->N);
+    if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup)
+        return fail(LEAD_E_UNSUPPORTED, "shots_per_workgroup too large for the workgroup limit");
+    if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, spw), spw, d->n) > 65536)
+        return fail(LEAD_E_UNSUPPORTED, "shots_per_workgroup needs more than 64 KiB of LDS");
+    d->spw = spw;
+    return LEAD_OK;
+}
+
+void lead_decoder_destroy(lead_decoder *d) {
+    if (!d) return;
+    (void)hipFree(d->d_view);
+    (void)hipFree(d->d_own);
+    free_plain(d);
+    delete d;
+}
+
+lead_status lead_decode(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
+                        const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post,
+                        float *lam, lead_shot_stats *stats, void *stream) {
+    lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
+    if (st != LEAD_OK || shots == 0) return st;
+    if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, d->spw), d->spw, d->n) > 65536)
+        return fail(LEAD_E_UNSUPPORTED, "workgroup needs more than 64 KiB of LDS");
+    lead::DecodeArgs a = base_args(d);
+    a.synd = synd;
+    a.synd_words = synd_words;
+    a.prior = prior;
+    a.prior_mode = mode;
+    a.ehat = ehat;
+    a.ehat_words = ehat_words;
+    a.post = post;
+    a.lam_out = lam;
+    a.stats = stats;
+    a.shots = shots;
+    hipError_t e = lead::launch_decode(d->D, d->r, a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "decode launch");
+    return LEAD_OK;
+}
+
+lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
+                              const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words,
+                              float *post, float *lam, lead_shot_stats *stats, void *stream) {
+    lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
+    if (st != LEAD_OK || shots == 0) return st;
+    return fail(LEAD_E_UNSUPPORTED, "lead_decode_plain is not available in this build");
+}
+
+lead_status lead_syndrome(const lead_decoder *d, int64_t shots, const uint64_t *err, int64_t err_words,
+                          uint64_t *synd, int64_t synd_words, void *stream) {
+    if (!d || shots < 0) return fail(LEAD_E_ARG, "bad argument");
+    if (shots == 0) return LEAD_OK;
+    if (!err || !synd) return fail(LEAD_E_ARG, "NULL buffer");
+    if (err_words < (d->n + 63) / 64 || synd_words < (d->m + 63) / 64) return fail(LEAD_E_ARG, "row too short");
+    lead::SyndArgs a{};
+    a.err = err;
+    a.synd = synd;
+    a.view = d->d_view;
+    a.shots = shots;
+    a.err_words = err_words;
+    a.synd_words = synd_words;
+    a.N = d->N;
+    a.D2 = d->D * d->D;
+    a.r = d->r;
+    a.m = d->m;
+    for (int c = 0; c < lead::kMaxChecks; ++c) a.mask[c] = c < d->r ? d->mask[c] : 0;
+    hipError_t e = lead::launch_syndrome(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "syndrome launch");
+    return LEAD_OK;
+}
+
+}  // extern "C"

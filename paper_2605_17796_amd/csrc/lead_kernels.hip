@@ -1,0 +1,468 @@
+// LEAD decoding kernels for gfx950 (CDNA4).
+//
+// Mapping.  One workgroup decodes `spw` shots; lane v of a shot holds the
+// local view of vertex v (the Delta^2 qubits of Q(v), Sec. II-B).  Phase 1 of
+// Algorithm 1 (local BP on the view) runs entirely inside the lane: the check
+// states live in VGPRs (a compressed min-sum state per check: smallest and
+// second-smallest |mu|, position of the smallest, and the sign of every
+// outgoing message), and the variable sums S_j of the view live in LDS at
+// buf[j * WG + lane] (WG the compile-time workgroup size), so every access of the uniform edge loop is
+// conflict-free.  The check masks are kernel arguments (scalar registers), so
+// the edge loops are uniform scalar loops.
+//
+// Phase 2 (alpha-regularised aggregation) and Phase 3 (global BP with the
+// aggregated prior) couple the two views of each qubit through LDS.  Every
+// qubit is owned by one of its two occurrences (an Euler-tour orientation
+// computed on the host, at most ceil(Delta^2/2) per view); the owner computes
+// the shared quantities and writes them to both occurrences, so no two lanes
+// ever touch the same LDS word between barriers.
+//
+// A global check is a local check of one vertex (the global check matrix is
+// the union of the placed local matrices), so the global check update is the
+// same per-lane routine as the local one; only the variable update differs:
+// S_i = lambda'_i + (messages of the owner's checks) + (messages of the
+// partner's checks).
+#include "lead_kernels.hpp"
+
+namespace lead {
+namespace {
+
+constexpr float kBig = 1e30f;
+
+__device__ __forceinline__ float clampf(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
+
+// Message of check state (m1, m2, am, q) to its k-th variable:
+// (-1)^{q_k} * (k == am ? m2 : m1), with m1, m2 already scaled by beta.  The
+// sign bit is moved to bit 31 and merged into the (non-negative) magnitude.
+__device__ __forceinline__ float msg_of(float m1, float m2, uint32_t am, uint32_t q, uint32_t k) {
+    const float mag = (k == am) ? m2 : m1;
+    return __uint_as_float(__float_as_uint(mag) | ((q << (31u - k)) & 0x80000000u));
+}
+
+// Compressed min-sum state of the checks of one vertex: beta * smallest and
+// beta * second-smallest |mu|, edge position of the smallest, and the sign
+// bit of every outgoing message.
+template <int RMAX>
+struct CheckState {
+    float m1[RMAX], m2[RMAX];
+    uint32_t am[RMAX], q[RMAX];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
+    }
+};
+
+// Sign tests use the IEEE sign bit: no variable sum or mu is ever -0 (every
+// sum starts from a prior canonicalised to +0 and x + (-x) rounds to +0), so
+// signbit(x) == (x < 0) throughout.
+__device__ __forceinline__ uint32_t signbit_of(float x) { return __float_as_uint(x) >> 31; }
+
+// Check update of every check of the lane's vertex.  Reads S_j (the variable
+// sums of the previous iteration), forms mu_{j->c} = clamp(S_j - m_{c->j}),
+// and replaces each check state by the min-sum state of the new messages
+//   m_{c->j} = beta (-1)^{s_c} prod_{j' != j} sgn(mu_{j'}) min_{j' != j} |mu_{j'}|.
+// Also returns whether the hard decisions [S_j < 0] satisfy every check.
+template <int WG, int RMAX>
+__device__ __forceinline__ bool check_pass(const DecodeArgs &a, const float *bl, uint64_t sv,
+                                           CheckState<RMAX> &st) {
+    bool sat = true;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+        if (c < a.r) {
+            uint64_t mk = a.mask[c];
+            float n1 = kBig, n2 = kBig;
+            uint32_t nam = 0u, sg = 0u, par = 0u, k = 0u;
+            while (mk) {
+                const int j = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                const float S = bl[j * WG];
+                par ^= __float_as_uint(S);
+                const float mu = clampf(S - msg_of(st.m1[c], st.m2[c], st.am[c], st.q[c], k), a.clampv);
+                const float ab = fabsf(mu);
+                sg |= signbit_of(mu) << k;
+                n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
+                const bool lt = ab < n1;
+                nam = lt ? k : nam;
+                n1 = lt ? ab : n1;
+                ++k;
+            }
+            const uint32_t sc = (uint32_t)(sv >> c) & 1u;
+            sat = sat && ((par >> 31) == sc);
+            const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
+            const uint32_t all = (uint32_t)((1ull << k) - 1ull);
+            st.q[c] = flip ? (sg ^ all) : sg;
+            st.m1[c] = a.beta * n1;
+            st.m2[c] = a.beta * n2;
+            st.am[c] = nam;
+        }
+    }
+    return sat;
+}
+
+template <int WG, int RMAX>
+__device__ __forceinline__ bool parity_pass(const DecodeArgs &a, const float *bl, uint64_t sv) {
+    bool sat = true;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+        if (c < a.r) {
+            uint64_t mk = a.mask[c];
+            uint32_t par = 0u;
+            while (mk) {
+                const int j = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                par ^= __float_as_uint(bl[j * WG]);
+            }
+            sat = sat && ((par >> 31) == ((uint32_t)(sv >> c) & 1u));
+        }
+    }
+    return sat;
+}
+
+// S_j += m_{c->j} over the lane's checks, in check order.
+template <int WG, int RMAX>
+__device__ __forceinline__ void accumulate(const DecodeArgs &a, float *bl, const CheckState<RMAX> &st) {
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+        if (c < a.r) {
+            uint64_t mk = a.mask[c];
+            uint32_t k = 0u;
+            while (mk) {
+                const int j = __builtin_ctzll(mk);
+                mk &= mk - 1;
+                bl[j * WG] += msg_of(st.m1[c], st.m2[c], st.am[c], st.q[c], k);
+                ++k;
+            }
+        }
+    }
+}
+
+struct Lane {
+    int tid, sl, v;
+    bool lane_ok, live;
+    int64_t shot;
+};
+
+__device__ __forceinline__ Lane lane_of(const DecodeArgs &a, int64_t shot_base) {
+    Lane L;
+    L.tid = threadIdx.x;
+    L.sl = L.tid / a.N;
+    L.v = L.tid - L.sl * a.N;
+    L.lane_ok = L.sl < a.spw;
+    L.shot = shot_base + L.sl;
+    L.live = L.lane_ok && L.shot < a.shots;
+    return L;
+}
+
+// r syndrome bits of vertex v: bits v*r .. v*r + r - 1 of the shot's row.
+__device__ __forceinline__ uint64_t local_syndrome(const DecodeArgs &a, int64_t shot, int v) {
+    const uint64_t *row = a.synd + shot * a.synd_words;
+    const int b0 = v * a.r;
+    const int w0 = b0 >> 6, off = b0 & 63;
+    uint64_t x = row[w0] >> off;
+    if (off + a.r > 64) x |= row[w0 + 1] << (64 - off);
+    return (a.r >= 64) ? x : (x & ((1ull << a.r) - 1ull));
+}
+
+// Owned-qubit entry k of a lane: LDS word offsets of its two occurrences.
+template <int WG>
+__device__ __forceinline__ void occurrences(uint32_t e, const Lane &L, int N, int &own, int &other) {
+    own = (int)(e & 0xffu) * WG + L.tid;
+    other = (int)((e >> 8) & 0xffu) * WG + L.sl * N + (int)(e >> 16);
+}
+
+// LDS layout of the fused kernel:
+//   buf   float [D2][WG]    variable sums / exchanged values
+//   convf int   [WG]        local convergence of each lane's view
+//   shf   int   [spw][8]    per shot: unsat flags (2), final flag, it_sum, it_max, n_conv
+//   ebits u32   [spw][ew32] packed hard decisions
+enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5 };
+
+// PM = 0: one prior per shot; PM = 1: one prior per qubit (SHARED or FULL).
+template <int D, int RMAX, int WG, int PM>
+__global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
+    constexpr int D2 = D * D;
+    constexpr int OWN = (D2 + 1) / 2;
+    extern __shared__ float lds[];
+    const Lane L = lane_of(a, (int64_t)blockIdx.x * a.spw);
+    const int tid = L.tid;
+    float *buf = lds;
+    int *convf = reinterpret_cast<int *>(buf + D2 * WG);
+    int *shf = convf + WG;
+    const int ew32 = (a.n + 31) >> 5;
+    uint32_t *ebits = reinterpret_cast<uint32_t *>(shf + a.spw * 8);
+    for (int i = tid; i < a.spw * 8; i += WG) shf[i] = 0;
+    for (int i = tid; i < a.spw * ew32; i += WG) ebits[i] = 0u;
+    float *bl = buf + tid;
+
+    // ---- Phase 1: local BP on the view of vertex v --------------------------
+    uint64_t sv = 0;
+    float lamv[PM == 0 ? 1 : D2];
+#pragma unroll
+    for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = 0.f;
+    if (L.live) {
+        sv = local_syndrome(a, L.shot, L.v);
+        if (PM == 0) {
+            lamv[0] = a.prior[L.shot] + 0.f;          // + 0 maps -0 to +0
+        } else {
+            const int64_t base = a.prior_mode == LEAD_PRIOR_FULL ? L.shot * a.n : 0;
+#pragma unroll
+            for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = a.prior[base + a.view[L.v * D2 + j]] + 0.f;
+        }
+    }
+    CheckState<RMAX> st;
+    st.clear();
+#pragma unroll
+    for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
+    int it_v = 0, conv_v = 0;
+    if (L.live) {
+        for (int t = 1; t <= a.Tl; ++t) {
+            const bool sat = check_pass<WG, RMAX>(a, bl, sv, st);
+            if (t > 1 && sat && a.early_exit) {
+                conv_v = 1;
+                it_v = t - 1;
+                break;
+            }
+#pragma unroll
+            for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
+            accumulate<WG, RMAX>(a, bl, st);
+        }
+        if (!conv_v) {
+            conv_v = parity_pass<WG, RMAX>(a, bl, sv) ? 1 : 0;
+            it_v = a.Tl;
+        }
+    }
+    convf[tid] = conv_v;
+    __syncthreads();
+    if (L.live) {
+        atomicAdd(&shf[L.sl * 8 + SF_ITSUM], it_v);
+        atomicMax(&shf[L.sl * 8 + SF_ITMAX], it_v);
+        atomicAdd(&shf[L.sl * 8 + SF_NCONV], conv_v);
+    }
+
+    // ---- Phase 2: regularised aggregation of the owned qubits --------------
+    // p = sigma(-L) and q = sigma(L) of both views (after the confidence
+    // boost), p_hat = alpha * mean(p), 1 - p_hat = (1 - alpha) + alpha * mean(q),
+    // lambda' = ln(1 - p_hat) - ln(p_hat).
+    uint32_t ent[OWN];
+    float lamp[OWN];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        ent[k] = (L.live && k < a.own_max) ? a.own[L.v * a.own_max + k] : kNoOwn;
+        lamp[k] = 0.f;
+        if (ent[k] != kNoOwn) {
+            int oa, ob;
+            occurrences<WG>(ent[k], L, a.N, oa, ob);
+            float La = clampf(buf[oa], a.clampv);
+            float Lb = clampf(buf[ob], a.clampv);
+            if (a.boost) {
+                // p <- max(p, 0.5) on bits a locally consistent view decided
+                // as errors; in LLR form L <- min(L, 0) where L < 0.
+                if (conv_v && La < 0.f) La = fminf(La, 0.f);
+                if (convf[ob % WG] && Lb < 0.f) Lb = fminf(Lb, 0.f);
+            }
+            const float pa = 1.f / (1.f + expf(La)), pb = 1.f / (1.f + expf(Lb));
+            const float qa = 1.f / (1.f + expf(-La)), qb = 1.f / (1.f + expf(-Lb));
+            const float ph = a.alpha * (0.5f * (pa + pb));
+            const float qh = (1.f - a.alpha) + a.alpha * (0.5f * (qa + qb));
+            lamp[k] = clampf(logf(qh) - logf(ph), a.clampv) + 0.f;
+        }
+    }
+    if (a.lam_out) {
+#pragma unroll
+        for (int k = 0; k < OWN; ++k)
+            if (ent[k] != kNoOwn) a.lam_out[L.shot * a.n + a.view[L.v * D2 + (ent[k] & 0xff)]] = lamp[k];
+    }
+    if (a.stage == LEAD_STAGE_LOCAL) {
+        __syncthreads();
+        if (L.live && L.v == 0 && a.stats) {
+            lead_shot_stats s = {};
+            s.local_iters_sum = shf[L.sl * 8 + SF_ITSUM];
+            s.local_iters_max = shf[L.sl * 8 + SF_ITMAX];
+            s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
+            a.stats[L.shot] = s;
+        }
+        return;
+    }
+
+    // ---- Phase 3: global BP with prior lambda' ------------------------------
+    // S_i <- lambda'_i on both occurrences (no messages yet).  Each owned pair
+    // is read above and written here by its owner only.
+#pragma unroll
+    for (int k = 0; k < OWN; ++k)
+        if (ent[k] != kNoOwn) {
+            int oa, ob;
+            occurrences<WG>(ent[k], L, a.N, oa, ob);
+            buf[oa] = lamp[k];
+            buf[ob] = lamp[k];
+        }
+    st.clear();
+    __syncthreads();
+    bool done = !L.live;
+    int itg = 0, gconv = 0;
+    for (int t = 1; t <= a.Tg; ++t) {
+        bool sat = true;
+        if (!done) sat = check_pass<WG, RMAX>(a, bl, sv, st);
+        if (!done && !sat) shf[L.sl * 8 + (t & 1)] = 1;
+        __syncthreads();
+        if (!done && t > 1 && a.early_exit && shf[L.sl * 8 + (t & 1)] == 0) {
+            done = true;
+            gconv = 1;
+            itg = t - 1;
+        }
+        if (!__syncthreads_or(done ? 0 : 1)) break;
+        if (L.lane_ok && L.v == 0) shf[L.sl * 8 + ((t + 1) & 1)] = 0;
+        if (!done) {
+            // partial sums of this view: lambda' on owned occurrences, then
+            // the messages of this vertex's checks
+#pragma unroll
+            for (int j = 0; j < D2; ++j) bl[j * WG] = 0.f;
+#pragma unroll
+            for (int k = 0; k < OWN; ++k)
+                if (ent[k] != kNoOwn) bl[(ent[k] & 0xff) * WG] = lamp[k];
+            accumulate<WG, RMAX>(a, bl, st);
+        }
+        __syncthreads();
+        if (!done) {
+#pragma unroll
+            for (int k = 0; k < OWN; ++k)
+                if (ent[k] != kNoOwn) {
+                    int oa, ob;
+                    occurrences<WG>(ent[k], L, a.N, oa, ob);
+                    const float s = buf[oa] + buf[ob];
+                    buf[oa] = s;
+                    buf[ob] = s;
+                }
+        }
+        __syncthreads();
+    }
+    const bool ran_out = !done;
+    if (ran_out && !parity_pass<WG, RMAX>(a, bl, sv)) shf[L.sl * 8 + SF_FINAL] = 1;
+    __syncthreads();
+    if (ran_out) {
+        gconv = shf[L.sl * 8 + SF_FINAL] == 0 ? 1 : 0;
+        itg = a.Tg;
+    }
+
+    // ---- outputs ------------------------------------------------------------
+    if (L.live) {
+#pragma unroll
+        for (int k = 0; k < OWN; ++k)
+            if (ent[k] != kNoOwn) {
+                const int j = ent[k] & 0xff;
+                const float S = buf[j * WG + tid];
+                const int qd = a.view[L.v * D2 + j];
+                if (a.post) a.post[L.shot * a.n + qd] = clampf(S, a.clampv);
+                if (signbit_of(S)) atomicOr(&ebits[L.sl * ew32 + (qd >> 5)], 1u << (qd & 31));
+            }
+    }
+    __syncthreads();
+    if (L.live) {
+        if (a.ehat)
+            for (int w = L.v; w < a.ehat_words; w += a.N) {
+                const uint64_t lo = (2 * w < ew32) ? ebits[L.sl * ew32 + 2 * w] : 0u;
+                const uint64_t hi = (2 * w + 1 < ew32) ? ebits[L.sl * ew32 + 2 * w + 1] : 0u;
+                a.ehat[L.shot * a.ehat_words + w] = lo | (hi << 32);
+            }
+        if (L.v == 0 && a.stats) {
+            lead_shot_stats s = {};
+            s.converged = gconv;
+            s.global_iters = itg;
+            s.local_iters_sum = shf[L.sl * 8 + SF_ITSUM];
+            s.local_iters_max = shf[L.sl * 8 + SF_ITMAX];
+            s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
+            a.stats[L.shot] = s;
+        }
+    }
+}
+
+// s = H e: one thread per (shot, 64-bit syndrome word).
+__global__ void __launch_bounds__(256) syndrome_kernel(SyndArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.shots * a.synd_words) return;
+    const int64_t shot = gid / a.synd_words;
+    const int w = (int)(gid - shot * a.synd_words);
+    const uint64_t *e = a.err + shot * a.err_words;
+    uint64_t out = 0;
+    for (int b = 0; b < 64; ++b) {
+        const int c = w * 64 + b;
+        if (c >= a.m) break;
+        const int v = c / a.r, rho = c - v * a.r;
+        uint64_t mk = a.mask[rho];
+        uint64_t par = 0;
+        while (mk) {
+            const int j = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const int q = a.view[v * a.D2 + j];
+            par ^= (e[q >> 6] >> (q & 63)) & 1ull;
+        }
+        out |= par << b;
+    }
+    a.synd[gid] = out;
+}
+
+template <int D, int RMAX, int WG>
+hipError_t launch_decode_t(const DecodeArgs &a, hipStream_t s) {
+    const size_t lds = decode_lds_bytes(D, WG, a.spw, a.n);
+    const int64_t grid = (a.shots + a.spw - 1) / a.spw;
+    if (a.prior_mode == LEAD_PRIOR_PER_SHOT)
+        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 0>), dim3((unsigned)grid), dim3(WG), lds, s, a);
+    else
+        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 1>), dim3((unsigned)grid), dim3(WG), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int D, int RMAX>
+hipError_t launch_decode_d(int wg, const DecodeArgs &a, hipStream_t s) {
+    switch (wg) {
+        case 64: return launch_decode_t<D, RMAX, 64>(a, s);
+        case 128: return launch_decode_t<D, RMAX, 128>(a, s);
+        case 192: return launch_decode_t<D, RMAX, 192>(a, s);
+        case 256: return launch_decode_t<D, RMAX, 256>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int workgroup_size(int N, int spw) { return ((N * spw + 63) / 64) * 64; }
+
+size_t decode_lds_bytes(int D, int wg, int spw, int n) {
+    const int ew32 = (n + 31) / 32;
+    return sizeof(float) * (size_t)D * D * wg + sizeof(int) * (size_t)wg + sizeof(int) * (size_t)spw * 8 +
+           sizeof(uint32_t) * (size_t)spw * ew32;
+}
+
+// Compiled shapes: (Delta, maximum checks per vertex).
+bool kernel_supported(int D, int r) {
+    switch (D) {
+        case 3: return r <= 4;
+        case 4: return r <= 9;
+        case 6: return r <= 9;
+        case 8: return r <= 16;
+        default: return false;
+    }
+}
+
+hipError_t launch_decode(int D, int, const DecodeArgs &a, hipStream_t s) {
+    if (a.shots <= 0) return hipSuccess;
+    const int wg = workgroup_size(a.N, a.spw);
+    switch (D) {
+        case 3: return launch_decode_d<3, 4>(wg, a, s);
+        case 4: return launch_decode_d<4, 9>(wg, a, s);
+        case 6: return launch_decode_d<6, 9>(wg, a, s);
+        case 8: return launch_decode_d<8, 16>(wg, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_round(int, int, const RoundArgs &, hipStream_t) { return hipErrorNotSupported; }
+
+hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s) {
+    const int64_t total = a.shots * a.synd_words;
+    if (total <= 0) return hipSuccess;
+    const int64_t grid = (total + 255) / 256;
+    hipLaunchKernelGGL(syndrome_kernel, dim3((unsigned)grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lead

@@ -1,0 +1,62 @@
+// Kernel-side argument blocks and launchers of liblead (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "../../include/lead.h"
+
+namespace lead {
+
+constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
+constexpr int kMaxWorkgroup = 256;   // threads per workgroup
+constexpr uint32_t kNoOwn = 0xFFFFFFFFu;
+
+// Everything a decode launch needs, passed by value in the kernel argument
+// segment (so the check masks live in scalar registers).
+struct DecodeArgs {
+    const uint64_t *synd;
+    const float *prior;
+    uint64_t *ehat;
+    float *post;
+    float *lam_out;
+    lead_shot_stats *stats;
+    const int32_t *view;       // [N][D2] qubit ids
+    const uint32_t *own;       // [N][own_max] packed j | j' << 8 | v' << 16
+    int64_t shots;
+    int64_t synd_words, ehat_words;
+    int32_t prior_mode, spw, N, n, r, own_max;
+    float alpha, beta, clampv;
+    int32_t Tl, Tg, early_exit, stage, boost;
+    uint64_t mask[kMaxChecks];
+};
+
+struct SyndArgs {
+    const uint64_t *err;
+    uint64_t *synd;
+    const int32_t *view;
+    int64_t shots, err_words, synd_words;
+    int32_t N, D2, r, m;
+    uint64_t mask[kMaxChecks];
+};
+
+// Plain (one launch per round) decode state kept in HBM.
+struct RoundArgs {
+    DecodeArgs d;
+    float *S;                  // [shots][D2][N] variable sums
+    float *cst;                // [shots][r][3][N] check states (m1, m2, packed am|signs)
+    float *lamp;               // [shots][n] lambda'
+    int32_t *status;           // [shots][4] done, conv, iters, unused
+    int32_t *active;           // device counter of shots still iterating
+    int32_t phase;             // 0 init, 1 round, 2 finalize
+    int32_t round;             // 1-based round index for phase 1
+};
+
+size_t decode_lds_bytes(int D, int wg, int spw, int n);
+int workgroup_size(int N, int spw);
+
+hipError_t launch_decode(int D, int rmax_needed, const DecodeArgs &a, hipStream_t s);
+hipError_t launch_round(int D, int rmax_needed, const RoundArgs &a, hipStream_t s);
+hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s);
+bool kernel_supported(int D, int r);
+
+}  // namespace lead

