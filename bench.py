@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--shots", type=int, default=SHOTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3200)
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="steps of the plain per-round-launch form timed for comparison (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -177,6 +179,20 @@ def main():
         roof = {"bound": "alu", "achieved": round(valu_gops / 1000, 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
                 "unit": "TOP/s", "frac": round(valu_frac, 4), "traffic": traffic}
 
+    plain = None
+    if args.plain_steps > 0:
+        dec.decode(synd_pool[0], lam, out=out, plain=True)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for i in range(args.plain_steps):
+            dec.decode(synd_pool[i % pool_batches], lam, out=out, plain=True)
+        torch.cuda.synchronize()
+        pw = (time.perf_counter() - tp) / args.plain_steps
+        plain = {"shots_per_s": round(shots / pw, 1), "ms_per_step": round(pw * 1000, 3),
+                 "form": "lead_decode_plain: Phases 1-2 launch, one launch per global round with state in HBM "
+                         "and a host-visible convergence count, finalize launch",
+                 "fused_over_plain": round(value * pw / shots, 3)}
+
     cpu = None
     if not args.no_cpu_baseline:
         workers = max(1, min(16, os.cpu_count() or 1))
@@ -209,6 +225,7 @@ def main():
         "decode_stats": {"converged": round(float((st[:, 0] == 1).mean()), 4),
                          "mean_global_iters": round(float(st[:, 1].mean()), 2),
                          "mean_local_iters": round(float(st[:, 2].mean() / 60.0), 2)},
+        "plain_form": plain,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

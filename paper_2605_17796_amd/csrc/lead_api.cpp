@@ -283,7 +283,63 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
                               float *post, float *lam, lead_shot_stats *stats, void *stream) {
     lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
     if (st != LEAD_OK || shots == 0) return st;
-    return fail(LEAD_E_UNSUPPORTED, "lead_decode_plain is not available in this build");
+    if (d->params.stage == LEAD_STAGE_LOCAL)
+        return lead_decode(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    const int D2 = d->D * d->D;
+    if (!d->d_S) {
+        const size_t ms = (size_t)std::max<int64_t>(d->max_shots, 1);
+        e = hipMalloc(&d->d_S, sizeof(float) * ms * D2 * d->N);
+        if (e == hipSuccess) e = hipMalloc(&d->d_cst, sizeof(float) * ms * d->r * 4 * d->N);
+        if (e == hipSuccess) e = hipMalloc(&d->d_lamp, sizeof(float) * ms * d->n);
+        if (e == hipSuccess) e = hipMalloc(&d->d_status, sizeof(int32_t) * ms * 4);
+        if (e == hipSuccess) e = hipMalloc(&d->d_active, sizeof(int32_t));
+        if (e == hipSuccess) e = hipHostMalloc(&d->h_active, sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            free_plain(d);
+            return hip_fail(e, "plain-form workspace allocation");
+        }
+    }
+    // Phases 1-2: lambda' to HBM (and to the caller's buffer if given)
+    lead::DecodeArgs a = base_args(d);
+    a.synd = synd;
+    a.synd_words = synd_words;
+    a.prior = prior;
+    a.prior_mode = mode;
+    a.ehat = ehat;
+    a.ehat_words = ehat_words;
+    a.post = post;
+    a.lam_out = lam ? lam : d->d_lamp;
+    a.stats = stats;
+    a.shots = shots;
+    a.stage = LEAD_STAGE_LOCAL;
+    e = lead::launch_decode(d->D, d->r, a, s);
+    if (e != hipSuccess) return hip_fail(e, "local-stage launch");
+    a.stage = LEAD_STAGE_FULL;
+    lead::RoundArgs ra{};
+    ra.d = a;
+    ra.S = d->d_S;
+    ra.cst = d->d_cst;
+    ra.lamp = a.lam_out;
+    ra.status = d->d_status;
+    ra.active = d->d_active;
+    ra.phase = 0;
+    e = lead::launch_round(d->D, d->r, ra, s);
+    if (e != hipSuccess) return hip_fail(e, "round launch");
+    ra.phase = 1;
+    for (int t = 1; t <= d->params.max_iter_global; ++t) {
+        if ((e = hipMemsetAsync(d->d_active, 0, sizeof(int32_t), s)) != hipSuccess) return hip_fail(e, "memset");
+        ra.round = t;
+        if ((e = lead::launch_round(d->D, d->r, ra, s)) != hipSuccess) return hip_fail(e, "round launch");
+        if ((e = hipMemcpyAsync(d->h_active, d->d_active, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "memcpy");
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "synchronize");
+        if (*d->h_active == 0) break;
+    }
+    ra.phase = 2;
+    if ((e = lead::launch_round(d->D, d->r, ra, s)) != hipSuccess) return hip_fail(e, "finalize launch");
+    return LEAD_OK;
 }
 
 lead_status lead_syndrome(const lead_decoder *d, int64_t shots, const uint64_t *err, int64_t err_words,

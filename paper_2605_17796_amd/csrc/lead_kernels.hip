@@ -400,6 +400,180 @@ __global__ void __launch_bounds__(256) syndrome_kernel(SyndArgs a) {
     a.synd[gid] = out;
 }
 
+
+// ---------------------------------------------------------------------------
+// Plain form: Phase 3 one round per launch, state in HBM.
+//   S      [shots][D2][N]     variable sums
+//   cst    [shots][r][4][N]   check states (m1, m2, am, q)
+//   status [shots][4]         done, converged, global iterations
+// phase 0 initialises S = lambda' and zero messages, phase 1 runs round
+// `round` of every shot still active (counting them in *active), phase 2
+// finalises (syndrome test of shots that ran out of rounds, outputs).  The
+// arithmetic is the fused kernel's, in the same order, so outputs are
+// bit-identical to lead_decode.
+// ---------------------------------------------------------------------------
+template <int D, int RMAX, int WG>
+__global__ void __launch_bounds__(WG) round_kernel(RoundArgs ra) {
+    constexpr int D2 = D * D;
+    constexpr int OWN = (D2 + 1) / 2;
+    const DecodeArgs &a = ra.d;
+    extern __shared__ float lds[];
+    const Lane L = lane_of(a, (int64_t)blockIdx.x * a.spw);
+    const int tid = L.tid;
+    float *buf = lds;
+    int *shf = reinterpret_cast<int *>(buf + D2 * WG);
+    const int ew32 = (a.n + 31) >> 5;
+    uint32_t *ebits = reinterpret_cast<uint32_t *>(shf + a.spw * 8);
+    float *bl = buf + tid;
+    for (int i = tid; i < a.spw * 8; i += WG) shf[i] = 0;
+    for (int i = tid; i < a.spw * ew32; i += WG) ebits[i] = 0u;
+    __syncthreads();
+    const int N = a.N;
+    float *Sg = L.live ? ra.S + (L.shot * D2) * N + L.v : nullptr;
+    float *Cg = L.live ? ra.cst + (L.shot * a.r) * 4 * N + L.v : nullptr;
+    int32_t *stat = L.live ? ra.status + L.shot * 4 : nullptr;
+    const float *lamp_row = L.live ? ra.lamp + L.shot * a.n : nullptr;
+
+    if (ra.phase == 0) {
+        if (L.live) {
+#pragma unroll
+            for (int j = 0; j < D2; ++j) Sg[j * N] = lamp_row[a.view[L.v * D2 + j]];
+            for (int c = 0; c < a.r; ++c)
+#pragma unroll
+                for (int f = 0; f < 4; ++f) Cg[(c * 4 + f) * N] = 0.f;
+            if (L.v == 0) { stat[0] = 0; stat[1] = 0; stat[2] = 0; stat[3] = 0; }
+        }
+        return;
+    }
+
+    uint32_t ent[OWN];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) ent[k] = (L.live && k < a.own_max) ? a.own[L.v * a.own_max + k] : kNoOwn;
+    bool done = !L.live || stat[0] != 0;
+    uint64_t sv = 0;
+    if (L.live) {
+        sv = local_syndrome(a, L.shot, L.v);
+#pragma unroll
+        for (int j = 0; j < D2; ++j) bl[j * WG] = Sg[j * N];
+    }
+
+    if (ra.phase == 1) {
+        const int t = ra.round;
+        CheckState<RMAX> st;
+        st.clear();
+        if (!done) {
+#pragma unroll
+            for (int c = 0; c < RMAX; ++c)
+                if (c < a.r) {
+                    st.m1[c] = Cg[(c * 4 + 0) * N];
+                    st.m2[c] = Cg[(c * 4 + 1) * N];
+                    st.am[c] = __float_as_uint(Cg[(c * 4 + 2) * N]);
+                    st.q[c] = __float_as_uint(Cg[(c * 4 + 3) * N]);
+                }
+        }
+        bool sat = true;
+        if (!done) sat = check_pass<WG, RMAX>(a, bl, sv, st);
+        if (!done && !sat) shf[L.sl * 8 + SF_FLAG0] = 1;
+        __syncthreads();
+        if (!done && t > 1 && a.early_exit && shf[L.sl * 8 + SF_FLAG0] == 0) {
+            done = true;
+            if (L.v == 0) { stat[0] = 1; stat[1] = 1; stat[2] = t - 1; }
+        }
+        if (!done) {
+#pragma unroll
+            for (int j = 0; j < D2; ++j) bl[j * WG] = 0.f;
+#pragma unroll
+            for (int k = 0; k < OWN; ++k)
+                if (ent[k] != kNoOwn) bl[(ent[k] & 0xff) * WG] = lamp_row[a.view[L.v * D2 + (ent[k] & 0xff)]];
+            accumulate<WG, RMAX>(a, bl, st);
+        }
+        __syncthreads();
+        if (!done) {
+#pragma unroll
+            for (int k = 0; k < OWN; ++k)
+                if (ent[k] != kNoOwn) {
+                    int oa, ob;
+                    occurrences<WG>(ent[k], L, a.N, oa, ob);
+                    const float s = buf[oa] + buf[ob];
+                    buf[oa] = s;
+                    buf[ob] = s;
+                }
+        }
+        __syncthreads();
+        if (!done) {
+#pragma unroll
+            for (int j = 0; j < D2; ++j) Sg[j * N] = bl[j * WG];
+#pragma unroll
+            for (int c = 0; c < RMAX; ++c)
+                if (c < a.r) {
+                    Cg[(c * 4 + 0) * N] = st.m1[c];
+                    Cg[(c * 4 + 1) * N] = st.m2[c];
+                    Cg[(c * 4 + 2) * N] = __uint_as_float(st.am[c]);
+                    Cg[(c * 4 + 3) * N] = __uint_as_float(st.q[c]);
+                }
+            if (L.v == 0) atomicAdd(ra.active, 1);
+        }
+        return;
+    }
+
+    // phase 2: shots that ran out of rounds take the syndrome test of S^{Tg}
+    const bool ran_out = !done;
+    if (ran_out && !parity_pass<WG, RMAX>(a, bl, sv)) shf[L.sl * 8 + SF_FINAL] = 1;
+    __syncthreads();
+    int gconv = 0, itg = 0;
+    if (L.live) {
+        if (ran_out) {
+            gconv = shf[L.sl * 8 + SF_FINAL] == 0 ? 1 : 0;
+            itg = a.Tg;
+        } else {
+            gconv = stat[1];
+            itg = stat[2];
+        }
+#pragma unroll
+        for (int k = 0; k < OWN; ++k)
+            if (ent[k] != kNoOwn) {
+                const int j = ent[k] & 0xff;
+                const float S = buf[j * WG + tid];
+                const int qd = a.view[L.v * D2 + j];
+                if (a.post) a.post[L.shot * a.n + qd] = clampf(S, a.clampv);
+                if (signbit_of(S)) atomicOr(&ebits[L.sl * ew32 + (qd >> 5)], 1u << (qd & 31));
+            }
+    }
+    __syncthreads();
+    if (L.live) {
+        if (a.ehat)
+            for (int w = L.v; w < a.ehat_words; w += a.N) {
+                const uint64_t lo = (2 * w < ew32) ? ebits[L.sl * ew32 + 2 * w] : 0u;
+                const uint64_t hi = (2 * w + 1 < ew32) ? ebits[L.sl * ew32 + 2 * w + 1] : 0u;
+                a.ehat[L.shot * a.ehat_words + w] = lo | (hi << 32);
+            }
+        if (L.v == 0 && a.stats) {
+            a.stats[L.shot].converged = gconv;
+            a.stats[L.shot].global_iters = itg;
+        }
+    }
+}
+
+template <int D, int RMAX, int WG>
+hipError_t launch_round_t(const RoundArgs &ra, hipStream_t s) {
+    const DecodeArgs &a = ra.d;
+    const size_t lds = decode_lds_bytes(D, WG, a.spw, a.n);
+    const int64_t grid = (a.shots + a.spw - 1) / a.spw;
+    hipLaunchKernelGGL((round_kernel<D, RMAX, WG>), dim3((unsigned)grid), dim3(WG), lds, s, ra);
+    return hipGetLastError();
+}
+
+template <int D, int RMAX>
+hipError_t launch_round_d(int wg, const RoundArgs &ra, hipStream_t s) {
+    switch (wg) {
+        case 64: return launch_round_t<D, RMAX, 64>(ra, s);
+        case 128: return launch_round_t<D, RMAX, 128>(ra, s);
+        case 192: return launch_round_t<D, RMAX, 192>(ra, s);
+        case 256: return launch_round_t<D, RMAX, 256>(ra, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int D, int RMAX, int WG>
 hipError_t launch_decode_t(const DecodeArgs &a, hipStream_t s) {
     const size_t lds = decode_lds_bytes(D, WG, a.spw, a.n);
@@ -455,7 +629,17 @@ hipError_t launch_decode(int D, int, const DecodeArgs &a, hipStream_t s) {
     }
 }
 
-hipError_t launch_round(int, int, const RoundArgs &, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_round(int D, int, const RoundArgs &ra, hipStream_t s) {
+    if (ra.d.shots <= 0) return hipSuccess;
+    const int wg = workgroup_size(ra.d.N, ra.d.spw);
+    switch (D) {
+        case 3: return launch_round_d<3, 4>(wg, ra, s);
+        case 4: return launch_round_d<4, 9>(wg, ra, s);
+        case 6: return launch_round_d<6, 9>(wg, ra, s);
+        case 8: return launch_round_d<8, 16>(wg, ra, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s) {
     const int64_t total = a.shots * a.synd_words;

@@ -43,9 +43,9 @@ struct SyndArgs {
 struct RoundArgs {
     DecodeArgs d;
     float *S;                  // [shots][D2][N] variable sums
-    float *cst;                // [shots][r][3][N] check states (m1, m2, packed am|signs)
-    float *lamp;               // [shots][n] lambda'
-    int32_t *status;           // [shots][4] done, conv, iters, unused
+    float *cst;                // [shots][r][4][N] check states (m1, m2, am, q)
+    const float *lamp;         // [shots][n] lambda'
+    int32_t *status;           // [shots][4] done, converged, iterations, unused
     int32_t *active;           // device counter of shots still iterating
     int32_t phase;             // 0 init, 1 round, 2 finalize
     int32_t round;             // 1-based round index for phase 1

@@ -225,3 +225,23 @@ def test_argument_errors():
         dec.decode(torch.zeros((2, 0), dtype=torch.int64, device="cuda"), lam[:2])
     with pytest.raises(P.LeadError):
         P.Decoder(code, alpha=0.0)
+
+
+@pytest.mark.parametrize("name,shots,p,T", [("T", 301, 0.05, 32), ("M", 97, 0.05, 50), ("M", 64, 0.02, 50),
+                                            ("L", 5, 0.02, 16)])
+def test_plain_form_bit_identical(name, shots, p, T):
+    """lead_decode_plain (one launch per global round, state in HBM, host
+    convergence check) returns exactly what the fused lead_decode returns."""
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, max_iter_local=T, max_iter_global=T)
+    e, _, lamv = bitflip_inputs(oc, shots, p, seed=71)
+    s = _gpu_syndrome(dec, e)
+    torch = torch_dev()
+    synd = torch.from_numpy(s.view(np.int64)).cuda()
+    lam = torch.from_numpy(lamv).cuda()
+    a = dec.decode(synd, lam, lam=True)
+    b = dec.decode(synd, lam, lam=True, plain=True)
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam", "stats"):
+        assert torch.equal(a[k], b[k]), k
+    log(f"[plain] {name}: {shots} shots bit-identical, conv={float((a['stats'][:, 0] == 1).float().mean()):.3f}")
