@@ -113,6 +113,11 @@ typedef struct {
     int32_t early_exit;       /* 1: stop a BP run at the first H e = s            */
     int32_t stage;            /* lead_stage: FULL, or LOCAL (Phases 1-2 only)      */
     int32_t boost;            /* 1: Phase-1 confidence boost (Alg. 1)             */
+    int32_t fixed_point_stop; /* 1: end a BP run whose messages reproduce
+                                 themselves bit for bit (every later iteration
+                                 would repeat it); results and reported
+                                 iteration counts are identical to running to
+                                 the cap                                       */
 } lead_params;
 
 /* Per-shot statistics (32 bytes). */
@@ -122,13 +127,18 @@ typedef struct {
     int32_t local_iters_sum;        /* sum over vertices of local iterations       */
     int32_t local_iters_max;
     int32_t local_converged_views;  /* vertices whose local BP reached H_v e_v = s_v */
-    int32_t reserved[3];
+    int32_t local_fixed_views;      /* local runs ended at a message fixed point   */
+    int32_t global_fixed_iter;      /* iteration at which global BP reached a fixed
+                                       point (0: it did not)                       */
+    int32_t reserved;
 } lead_shot_stats;
 
 /* Creates a decoder for the checks of type `t` and uploads the device tables
  * of the code to the current HIP device.  `max_shots` bounds the batch size
- * of every later call (it sizes the per-round workspace of
- * lead_decode_plain). */
+ * of every later call.  The decoder allocates a workspace for min(max_shots,
+ * 32768) shots (local posteriors: order * delta^2 floats per shot); larger
+ * batches are decoded chunk by chunk on the same stream.  lead_decode_plain
+ * allocates its per-round state (for max_shots shots) on first use. */
 lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const lead_params *params,
                                 int64_t max_shots, lead_decoder **out);
 lead_status lead_decoder_set_params(lead_decoder *dec, const lead_params *params);
@@ -167,9 +177,19 @@ lead_status lead_decode_plain(lead_decoder *dec, int64_t shots, const uint64_t *
 lead_status lead_syndrome(const lead_decoder *dec, int64_t shots, const uint64_t *d_err, int64_t err_words,
                           uint64_t *d_synd, int64_t synd_words, void *stream);
 
-/* Launch geometry of lead_decode: shots handled per workgroup (0 = the
- * library's choice).  Results do not depend on it. */
-lead_status lead_decoder_set_schedule(lead_decoder *dec, int32_t shots_per_workgroup);
+/* Launch geometry of lead_decode.  Results never depend on it (every shot's
+ * arithmetic is the same under every schedule); zeros select the library's
+ * defaults. */
+typedef struct {
+    int32_t shots_per_workgroup;  /* shots per workgroup of the per-shot kernel     */
+    int32_t fused;                /* 1: Phase 1 runs inside the per-shot kernel (a
+                                     wave waits for its slowest view); 0: Phase 1
+                                     runs in a work-queue kernel first           */
+    int32_t local_chunk;          /* queue items a wave takes at a time            */
+    int32_t local_waves;          /* waves of the work-queue kernel                 */
+} lead_schedule;
+lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
+lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);
 
 #ifdef __cplusplus
 }

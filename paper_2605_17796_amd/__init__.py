@@ -48,14 +48,21 @@ class lead_code_info(C.Structure):
 class lead_params(C.Structure):
     _fields_ = [("alpha", C.c_float), ("ms_scale", C.c_float), ("max_iter_local", C.c_int32),
                 ("max_iter_global", C.c_int32), ("llr_clamp", C.c_float), ("early_exit", C.c_int32),
-                ("stage", C.c_int32), ("boost", C.c_int32)]
+                ("stage", C.c_int32), ("boost", C.c_int32), ("fixed_point_stop", C.c_int32)]
 
 
-STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views")
+class lead_schedule(C.Structure):
+    _fields_ = [("shots_per_workgroup", C.c_int32), ("fused", C.c_int32), ("local_chunk", C.c_int32),
+                ("local_waves", C.c_int32)]
+
+
+STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views",
+                "local_fixed_views", "global_fixed_iter")
 
 SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
            "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
-           "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule"]
+           "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
+           "lead_decoder_get_schedule"]
 
 _lib = None
 
@@ -81,7 +88,8 @@ def lib():
         L.lead_code_destroy.restype = None
         L.lead_decoder_create.argtypes = [P, I32, C.POINTER(lead_params), I64, C.POINTER(P)]
         L.lead_decoder_set_params.argtypes = [P, C.POINTER(lead_params)]
-        L.lead_decoder_set_schedule.argtypes = [P, I32]
+        L.lead_decoder_set_schedule.argtypes = [P, C.POINTER(lead_schedule)]
+        L.lead_decoder_get_schedule.argtypes = [P, C.POINTER(lead_schedule)]
         L.lead_decoder_destroy.argtypes = [P]
         L.lead_decoder_destroy.restype = None
         dec_args = [P, I64, P, I64, P, I32, P, I64, P, P, P, P]
@@ -147,8 +155,9 @@ def lead_code_destroy(code):
 
 
 def lead_params_make(alpha=1.0, ms_scale=0.75, max_iter_local=32, max_iter_global=32, llr_clamp=30.0,
-                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1) -> lead_params:
-    return lead_params(alpha, ms_scale, max_iter_local, max_iter_global, llr_clamp, early_exit, stage, boost)
+                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1, fixed_point_stop=1) -> lead_params:
+    return lead_params(alpha, ms_scale, max_iter_local, max_iter_global, llr_clamp, early_exit, stage, boost,
+                       fixed_point_stop)
 
 
 def lead_decoder_create(code, t, params: lead_params, max_shots: int):
@@ -161,8 +170,14 @@ def lead_decoder_set_params(dec, params: lead_params):
     _check(lib().lead_decoder_set_params(dec, C.byref(params)))
 
 
-def lead_decoder_set_schedule(dec, shots_per_workgroup: int):
-    _check(lib().lead_decoder_set_schedule(dec, shots_per_workgroup))
+def lead_decoder_set_schedule(dec, schedule: lead_schedule):
+    _check(lib().lead_decoder_set_schedule(dec, C.byref(schedule)))
+
+
+def lead_decoder_get_schedule(dec) -> lead_schedule:
+    sc = lead_schedule()
+    _check(lib().lead_decoder_get_schedule(dec, C.byref(sc)))
+    return sc
 
 
 def lead_decoder_destroy(dec):
@@ -277,8 +292,12 @@ class Decoder:
         self.params = lead_params_make(**params)
         lead_decoder_set_params(self._h, self.params)
 
-    def set_schedule(self, shots_per_workgroup: int):
-        lead_decoder_set_schedule(self._h, shots_per_workgroup)
+    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0):
+        lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves))
+
+    def get_schedule(self) -> dict:
+        sc = lead_decoder_get_schedule(self._h)
+        return {f: getattr(sc, f) for f, _ in lead_schedule._fields_}
 
     def alloc_outputs(self, shots, device="cuda", post=True, lam=False, stats=True):
         import torch

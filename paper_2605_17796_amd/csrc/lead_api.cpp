@@ -28,6 +28,14 @@ struct lead_decoder {
     uint64_t mask[lead::kMaxChecks] = {};
     int32_t *d_view = nullptr;
     uint32_t *d_own = nullptr;
+    // schedule and split-path workspace (for ws_shots shots)
+    lead_schedule sched{};
+    int64_t ws_shots = 0;
+    int cus = 0;
+    int waves_per_cu[2] = {4, 4};
+    float *d_Lv = nullptr;
+    uint32_t *d_vflag = nullptr;
+    int64_t *d_counter = nullptr;
     // per-round state of lead_decode_plain (allocated on first use)
     float *d_S = nullptr, *d_cst = nullptr, *d_lamp = nullptr;
     int32_t *d_status = nullptr, *d_active = nullptr, *h_active = nullptr;
@@ -55,6 +63,24 @@ lead_status check_params(const lead_params *p) {
     if (!(p->llr_clamp > 0.f) || !std::isfinite(p->llr_clamp)) return fail(LEAD_E_ARG, "llr_clamp must be > 0");
     if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL) return fail(LEAD_E_ARG, "bad stage");
     return LEAD_OK;
+}
+
+constexpr int64_t kChunkShots = 32768;
+
+int default_spw(int N) { return std::max(1, 64 / N); }
+
+lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode mode) {
+    lead::LocalArgs w{};
+    w.Lv = d->d_Lv;
+    w.vflag = d->d_vflag;
+    w.counter = d->d_counter;
+    w.items = shots * d->N;
+    w.chunk = d->sched.local_chunk;
+    const int64_t per_cu = d->waves_per_cu[mode == LEAD_PRIOR_PER_SHOT ? 0 : 1];
+    int64_t waves = d->sched.local_waves > 0 ? d->sched.local_waves : per_cu * d->cus;
+    const int64_t need = (w.items + w.chunk - 1) / w.chunk;
+    w.waves = (int32_t)std::max<int64_t>(1, std::min(waves, need));
+    return w;
 }
 
 void free_plain(lead_decoder *d) {
@@ -85,6 +111,7 @@ lead::DecodeArgs base_args(const lead_decoder *d) {
     a.early_exit = d->params.early_exit ? 1 : 0;
     a.stage = d->params.stage;
     a.boost = d->params.boost ? 1 : 0;
+    a.fixed_stop = d->params.fixed_point_stop ? 1 : 0;
     for (int c = 0; c < lead::kMaxChecks; ++c) a.mask[c] = c < d->r ? d->mask[c] : 0;
     return a;
 }
@@ -103,6 +130,34 @@ lead_status check_decode_args(const lead_decoder *d, int64_t shots, const uint64
     if (ehat && ehat_words < (d->n + 63) / 64) return fail(LEAD_E_ARG, "ehat_words < ceil(n/64)");
     if (d->params.stage == LEAD_STAGE_LOCAL && !lam) return fail(LEAD_E_ARG, "LOCAL stage needs d_prior_llr");
     return LEAD_OK;
+}
+
+// Launches the decode of `shots` shots (in workspace-sized chunks for the
+// split path) on stream s.
+hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
+                         const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post,
+                         float *lam, lead_shot_stats *stats, int stage, hipStream_t s) {
+    const bool split = !d->sched.fused;
+    const int64_t step = split ? d->ws_shots : shots;
+    for (int64_t off = 0; off < shots; off += step) {
+        const int64_t cnt = std::min(step, shots - off);
+        lead::DecodeArgs a = base_args(d);
+        a.synd = synd + off * synd_words;
+        a.synd_words = synd_words;
+        a.prior = prior + (mode == LEAD_PRIOR_PER_SHOT ? off : mode == LEAD_PRIOR_FULL ? off * d->n : 0);
+        a.prior_mode = mode;
+        a.ehat = ehat ? ehat + off * ehat_words : nullptr;
+        a.ehat_words = ehat_words;
+        a.post = post ? post + off * d->n : nullptr;
+        a.lam_out = lam ? lam + off * d->n : nullptr;
+        a.stats = stats ? stats + off : nullptr;
+        a.shots = cnt;
+        a.stage = stage;
+        const lead::LocalArgs w = local_args(d, cnt, mode);
+        hipError_t e = lead::launch_decode(d->D, d->r, a, w, split, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -197,9 +252,18 @@ lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const 
     d->m = c.order * tt.r;
     d->own_max = tt.own_max;
     for (int i = 0; i < tt.r; ++i) d->mask[i] = tt.mask[i];
-    d->spw = std::max(1, 64 / d->N);
+    d->spw = default_spw(d->N);
+    d->sched.shots_per_workgroup = d->spw;
+    d->sched.fused = 0;
+    d->sched.local_chunk = 256;
+    d->sched.local_waves = 0;
     hipError_t e = hipGetDevice(&d->device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    e = hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, d->device);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    d->ws_shots = std::min<int64_t>(std::max<int64_t>(max_shots, 1), kChunkShots);
+    d->waves_per_cu[0] = lead::local_waves_per_cu(D, 0);
+    d->waves_per_cu[1] = lead::local_waves_per_cu(D, 1);
     // owner lists: per view, owned local positions in increasing order
     std::vector<uint32_t> own((size_t)d->N * d->own_max, lead::kNoOwn);
     for (int v = 0; v < d->N; ++v) {
@@ -219,10 +283,16 @@ lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const 
     }
     e = hipMemcpy(d->d_view, tt.view.data(), sizeof(int32_t) * tt.view.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d->d_own, own.data(), sizeof(uint32_t) * own.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&d->d_Lv, sizeof(float) * (size_t)d->ws_shots * d->N * D2);
+    if (e == hipSuccess) e = hipMalloc(&d->d_vflag, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
+    if (e == hipSuccess) e = hipMalloc(&d->d_counter, sizeof(int64_t));
     if (e != hipSuccess) {
         (void)hipFree(d->d_view);
         (void)hipFree(d->d_own);
-        return hip_fail(e, "hipMemcpy");
+        (void)hipFree(d->d_Lv);
+        (void)hipFree(d->d_vflag);
+        (void)hipFree(d->d_counter);
+        return hip_fail(e, "device allocation");
     }
     *out = d.release();
     return LEAD_OK;
@@ -236,14 +306,26 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
     return LEAD_OK;
 }
 
-lead_status lead_decoder_set_schedule(lead_decoder *d, int32_t spw) {
-    if (!d || spw < 0) return fail(LEAD_E_ARG, "bad argument");
-    if (spw == 0) spw = std::max(1, 64 / d->N);
+lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) {
+    if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
+    if (sc->shots_per_workgroup < 0 || sc->local_chunk < 0 || sc->local_waves < 0)
+        return fail(LEAD_E_ARG, "negative schedule field");
+    const int spw = sc->shots_per_workgroup ? sc->shots_per_workgroup : default_spw(d->N);
     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup)
         return fail(LEAD_E_UNSUPPORTED, "shots_per_workgroup too large for the workgroup limit");
     if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, spw), spw, d->n) > 65536)
         return fail(LEAD_E_UNSUPPORTED, "shots_per_workgroup needs more than 64 KiB of LDS");
     d->spw = spw;
+    d->sched.shots_per_workgroup = spw;
+    d->sched.fused = sc->fused ? 1 : 0;
+    d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
+    d->sched.local_waves = sc->local_waves;
+    return LEAD_OK;
+}
+
+lead_status lead_decoder_get_schedule(const lead_decoder *d, lead_schedule *sc) {
+    if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
+    *sc = d->sched;
     return LEAD_OK;
 }
 
@@ -251,6 +333,9 @@ void lead_decoder_destroy(lead_decoder *d) {
     if (!d) return;
     (void)hipFree(d->d_view);
     (void)hipFree(d->d_own);
+    (void)hipFree(d->d_Lv);
+    (void)hipFree(d->d_vflag);
+    (void)hipFree(d->d_counter);
     free_plain(d);
     delete d;
 }
@@ -262,18 +347,8 @@ lead_status lead_decode(lead_decoder *d, int64_t shots, const uint64_t *synd, in
     if (st != LEAD_OK || shots == 0) return st;
     if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, d->spw), d->spw, d->n) > 65536)
         return fail(LEAD_E_UNSUPPORTED, "workgroup needs more than 64 KiB of LDS");
-    lead::DecodeArgs a = base_args(d);
-    a.synd = synd;
-    a.synd_words = synd_words;
-    a.prior = prior;
-    a.prior_mode = mode;
-    a.ehat = ehat;
-    a.ehat_words = ehat_words;
-    a.post = post;
-    a.lam_out = lam;
-    a.stats = stats;
-    a.shots = shots;
-    hipError_t e = lead::launch_decode(d->D, d->r, a, (hipStream_t)stream);
+    hipError_t e = decode_chunks(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats,
+                                 d->params.stage, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "decode launch");
     return LEAD_OK;
 }
@@ -302,6 +377,10 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
         }
     }
     // Phases 1-2: lambda' to HBM (and to the caller's buffer if given)
+    float *lam_hbm = lam ? lam : d->d_lamp;
+    e = decode_chunks(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam_hbm, stats,
+                      LEAD_STAGE_LOCAL, s);
+    if (e != hipSuccess) return hip_fail(e, "local-stage launch");
     lead::DecodeArgs a = base_args(d);
     a.synd = synd;
     a.synd_words = synd_words;
@@ -310,12 +389,9 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
     a.ehat = ehat;
     a.ehat_words = ehat_words;
     a.post = post;
-    a.lam_out = lam ? lam : d->d_lamp;
+    a.lam_out = lam_hbm;
     a.stats = stats;
     a.shots = shots;
-    a.stage = LEAD_STAGE_LOCAL;
-    e = lead::launch_decode(d->D, d->r, a, s);
-    if (e != hipSuccess) return hip_fail(e, "local-stage launch");
     a.stage = LEAD_STAGE_FULL;
     lead::RoundArgs ra{};
     ra.d = a;

@@ -61,11 +61,14 @@ __device__ __forceinline__ uint32_t signbit_of(float x) { return __float_as_uint
 // sums of the previous iteration), forms mu_{j->c} = clamp(S_j - m_{c->j}),
 // and replaces each check state by the min-sum state of the new messages
 //   m_{c->j} = beta (-1)^{s_c} prod_{j' != j} sgn(mu_{j'}) min_{j' != j} |mu_{j'}|.
-// Also returns whether the hard decisions [S_j < 0] satisfy every check.
+// Returns whether the hard decisions [S_j < 0] satisfy every check, and sets
+// `same` when every new check state equals the previous one bit for bit (the
+// message state is then a fixed point of the iteration).
 template <int WG, int RMAX>
 __device__ __forceinline__ bool check_pass(const DecodeArgs &a, const float *bl, uint64_t sv,
-                                           CheckState<RMAX> &st) {
+                                           CheckState<RMAX> &st, bool &same) {
     bool sat = true;
+    same = true;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
         if (c < a.r) {
@@ -90,9 +93,13 @@ __device__ __forceinline__ bool check_pass(const DecodeArgs &a, const float *bl,
             sat = sat && ((par >> 31) == sc);
             const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
             const uint32_t all = (uint32_t)((1ull << k) - 1ull);
-            st.q[c] = flip ? (sg ^ all) : sg;
-            st.m1[c] = a.beta * n1;
-            st.m2[c] = a.beta * n2;
+            const uint32_t nq = flip ? (sg ^ all) : sg;
+            const float b1 = a.beta * n1, b2 = a.beta * n2;
+            same = same && nq == st.q[c] && nam == st.am[c] && __float_as_uint(b1) == __float_as_uint(st.m1[c]) &&
+                   __float_as_uint(b2) == __float_as_uint(st.m2[c]);
+            st.q[c] = nq;
+            st.m1[c] = b1;
+            st.m2[c] = b2;
             st.am[c] = nam;
         }
     }
@@ -173,13 +180,144 @@ __device__ __forceinline__ void occurrences(uint32_t e, const Lane &L, int N, in
 // LDS layout of the fused kernel:
 //   buf   float [D2][WG]    variable sums / exchanged values
 //   convf int   [WG]        local convergence of each lane's view
-//   shf   int   [spw][8]    per shot: unsat flags (2), final flag, it_sum, it_max, n_conv
+//   shf   int   [spw][8]    per shot: unsat flags (2), final flag, it_sum, it_max, n_conv,
+//                           changed flag, local fixed-point count
 //   ebits u32   [spw][ew32] packed hard decisions
-enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5 };
+enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5, SF_CHG = 6, SF_NFIX = 7 };
 
-// PM = 0: one prior per shot; PM = 1: one prior per qubit (SHARED or FULL).
+// Priors of the lane's view: one per shot (PM = 0) or one per qubit (PM = 1,
+// SHARED or FULL).  "+ 0.f" maps a -0 prior to +0.
+template <int D, int PM>
+__device__ __forceinline__ void load_priors(const DecodeArgs &a, int64_t shot, int v, float (&lamv)[PM == 0 ? 1 : D * D]) {
+    constexpr int D2 = D * D;
+    if (PM == 0) {
+        lamv[0] = a.prior[shot] + 0.f;
+    } else {
+        const int64_t base = a.prior_mode == LEAD_PRIOR_FULL ? shot * a.n : 0;
+#pragma unroll
+        for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = a.prior[base + a.view[v * D2 + j]] + 0.f;
+    }
+}
+
+// One step of the local BP run of a view (Phase 1): the check update of
+// iteration t (which also tests S^{t-1}) and, unless the run ends, the
+// variable update S^t.  A run ends at the first t > 1 whose S^{t-1} satisfies
+// the local syndrome (early exit), when the messages stop changing (a fixed
+// point: every later iteration repeats S^{t-1}), or at t = Tl + 1 (the cap,
+// where the test is the final syndrome test).  On return `fin` tells whether
+// the run ended; conv, it, fixed describe it.
 template <int D, int RMAX, int WG, int PM>
-__global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
+__device__ __forceinline__ bool local_step(const DecodeArgs &a, float *bl, uint64_t sv, const float (&lamv)[PM == 0 ? 1 : D * D],
+                                           CheckState<RMAX> &st, int t, int &conv, int &it, int &fixed) {
+    constexpr int D2 = D * D;
+    bool same;
+    const bool sat = check_pass<WG, RMAX>(a, bl, sv, st, same);
+    if (t > a.Tl) {
+        conv = sat ? 1 : 0;
+        it = a.Tl;
+        return true;
+    }
+    if (t > 1 && sat && a.early_exit) {
+        conv = 1;
+        it = t - 1;
+        return true;
+    }
+    if (t > 1 && same && a.fixed_stop) {
+        conv = sat ? 1 : 0;
+        it = a.Tl;
+        fixed = 1;
+        return true;
+    }
+#pragma unroll
+    for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
+    accumulate<WG, RMAX>(a, bl, st);
+    return false;
+}
+
+// Phase 1 as its own kernel: every lane of a 64-lane wave runs the local BP
+// of one (shot, vertex) item at a time and takes the next item from the
+// queue as soon as its run ends, so a wave is never held by its slowest
+// view.  Items are numbered shot * N + v; waves take chunks of them from a
+// global counter.  Outputs per item: the clamped local posteriors
+// (w.Lv[item][j]) and w.vflag[item] = iterations | converged << 16 |
+// fixed point << 17.
+template <int D, int RMAX, int PM>
+__global__ void __launch_bounds__(64) local_kernel(DecodeArgs a, LocalArgs w) {
+    constexpr int D2 = D * D;
+    constexpr int WG = 64;
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x;
+    float *bl = lds + lane;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t cur = 0, end = 0;
+    bool queue_open = true, valid = false;
+    int64_t item = 0;
+    int t = 0;
+    uint64_t sv = 0;
+    float lamv[PM == 0 ? 1 : D2];
+#pragma unroll
+    for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = 0.f;
+    CheckState<RMAX> st;
+    st.clear();
+    for (;;) {
+        // hand the next items to lanes without a view, in lane order
+        uint64_t need = __ballot(!valid);
+        while (need && queue_open) {
+            if (cur >= end) {
+                unsigned long long c0 = 0;
+                if (lane == 0) c0 = atomicAdd(reinterpret_cast<unsigned long long *>(w.counter),
+                                              (unsigned long long)w.chunk);
+                c0 = __shfl(c0, 0);
+                if ((int64_t)c0 >= w.items) {
+                    queue_open = false;
+                    break;
+                }
+                cur = (int64_t)c0;
+                end = cur + w.chunk < w.items ? cur + w.chunk : w.items;
+            }
+            const int rank = __popcll(need & below);
+            const int64_t avail = end - cur;
+            if (!valid && rank < avail) {
+                item = cur + rank;
+                valid = true;
+                const int64_t shot = item / a.N;
+                const int v = (int)(item - shot * a.N);
+                sv = local_syndrome(a, shot, v);
+                load_priors<D, PM>(a, shot, v, lamv);
+                st.clear();
+#pragma unroll
+                for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
+                t = 1;
+            }
+            const int64_t taken = __popcll(need) < avail ? __popcll(need) : avail;
+            cur += taken;
+            need = __ballot(!valid);
+        }
+        if (__ballot(valid) == 0ull) break;
+        if (valid) {
+            int conv = 0, it = 0, fixed = 0;
+            if (local_step<D, RMAX, WG, PM>(a, bl, sv, lamv, st, t, conv, it, fixed)) {
+                float *out = w.Lv + item * D2;
+#pragma unroll
+                for (int j = 0; j < D2; ++j) out[j] = clampf(bl[j * WG], a.clampv);
+                w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
+                valid = false;
+            } else {
+                ++t;
+            }
+        }
+    }
+}
+
+// Work queue reset before a local_kernel launch (a kernel rather than a
+// memset, so that the launch sequence can be captured in a graph).
+__global__ void reset_counter_kernel(int64_t *counter) { *counter = 0; }
+
+// Phases 2-3 of a shot group (and, for SPLIT = false, Phase 1 as well: every
+// lane runs its view's local BP in place, and the wave waits for its slowest
+// view).  One workgroup decodes spw shots; lane v holds vertex v.
+template <int D, int RMAX, int WG, int PM, bool SPLIT>
+__global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
     constexpr int D2 = D * D;
     constexpr int OWN = (D2 + 1) / 2;
     extern __shared__ float lds[];
@@ -196,40 +334,32 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
 
     // ---- Phase 1: local BP on the view of vertex v --------------------------
     uint64_t sv = 0;
-    float lamv[PM == 0 ? 1 : D2];
+    int it_v = 0, conv_v = 0, fixed_v = 0;
+    if (L.live) sv = local_syndrome(a, L.shot, L.v);
+    if (SPLIT) {
+        // outputs of local_kernel
+        if (L.live) {
+            const int64_t item = L.shot * a.N + L.v;
+            const float *in = w.Lv + item * D2;
 #pragma unroll
-    for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = 0.f;
-    if (L.live) {
-        sv = local_syndrome(a, L.shot, L.v);
-        if (PM == 0) {
-            lamv[0] = a.prior[L.shot] + 0.f;          // + 0 maps -0 to +0
-        } else {
-            const int64_t base = a.prior_mode == LEAD_PRIOR_FULL ? L.shot * a.n : 0;
-#pragma unroll
-            for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = a.prior[base + a.view[L.v * D2 + j]] + 0.f;
+            for (int j = 0; j < D2; ++j) bl[j * WG] = in[j];
+            const uint32_t f = w.vflag[item];
+            it_v = (int)(f & 0xffffu);
+            conv_v = (int)((f >> 16) & 1u);
+            fixed_v = (int)((f >> 17) & 1u);
         }
-    }
-    CheckState<RMAX> st;
-    st.clear();
+    } else {
+        float lamv[PM == 0 ? 1 : D2];
 #pragma unroll
-    for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
-    int it_v = 0, conv_v = 0;
-    if (L.live) {
-        for (int t = 1; t <= a.Tl; ++t) {
-            const bool sat = check_pass<WG, RMAX>(a, bl, sv, st);
-            if (t > 1 && sat && a.early_exit) {
-                conv_v = 1;
-                it_v = t - 1;
-                break;
-            }
+        for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = 0.f;
+        if (L.live) load_priors<D, PM>(a, L.shot, L.v, lamv);
+        CheckState<RMAX> st;
+        st.clear();
 #pragma unroll
-            for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
-            accumulate<WG, RMAX>(a, bl, st);
-        }
-        if (!conv_v) {
-            conv_v = parity_pass<WG, RMAX>(a, bl, sv) ? 1 : 0;
-            it_v = a.Tl;
-        }
+        for (int j = 0; j < D2; ++j) bl[j * WG] = lamv[PM == 0 ? 0 : j];
+        if (L.live)
+            for (int t = 1;; ++t)
+                if (local_step<D, RMAX, WG, PM>(a, bl, sv, lamv, st, t, conv_v, it_v, fixed_v)) break;
     }
     convf[tid] = conv_v;
     __syncthreads();
@@ -237,7 +367,9 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
         atomicAdd(&shf[L.sl * 8 + SF_ITSUM], it_v);
         atomicMax(&shf[L.sl * 8 + SF_ITMAX], it_v);
         atomicAdd(&shf[L.sl * 8 + SF_NCONV], conv_v);
+        if (fixed_v) atomicAdd(&shf[L.sl * 8 + SF_NFIX], 1);
     }
+    CheckState<RMAX> st;
 
     // ---- Phase 2: regularised aggregation of the owned qubits --------------
     // p = sigma(-L) and q = sigma(L) of both views (after the confidence
@@ -279,6 +411,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
             s.local_iters_sum = shf[L.sl * 8 + SF_ITSUM];
             s.local_iters_max = shf[L.sl * 8 + SF_ITMAX];
             s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
+            s.local_fixed_views = shf[L.sl * 8 + SF_NFIX];
             a.stats[L.shot] = s;
         }
         return;
@@ -298,16 +431,32 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
     st.clear();
     __syncthreads();
     bool done = !L.live;
-    int itg = 0, gconv = 0;
+    int itg = 0, gconv = 0, gfix = 0;
     for (int t = 1; t <= a.Tg; ++t) {
-        bool sat = true;
-        if (!done) sat = check_pass<WG, RMAX>(a, bl, sv, st);
+        // The owner entries are re-materialised every iteration, so the
+        // compiler recomputes their LDS offsets (a few VALU ops) instead of
+        // keeping 2 * OWN precomputed offsets live across the loop.
+#pragma unroll
+        for (int k = 0; k < OWN; ++k) asm volatile("" : "+v"(ent[k]));
+        bool sat = true, same = true;
+        if (!done) sat = check_pass<WG, RMAX>(a, bl, sv, st, same);
         if (!done && !sat) shf[L.sl * 8 + (t & 1)] = 1;
+        if (!done && !same) shf[L.sl * 8 + SF_CHG] = t;
         __syncthreads();
-        if (!done && t > 1 && a.early_exit && shf[L.sl * 8 + (t & 1)] == 0) {
-            done = true;
-            gconv = 1;
-            itg = t - 1;
+        if (!done && t > 1) {
+            const bool shot_sat = shf[L.sl * 8 + (t & 1)] == 0;
+            if (shot_sat && a.early_exit) {
+                done = true;
+                gconv = 1;
+                itg = t - 1;
+            } else if (a.fixed_stop && shf[L.sl * 8 + SF_CHG] != t) {
+                // no check state of the shot changed: S stays S^{t-1} for
+                // every remaining iteration
+                done = true;
+                gconv = shot_sat ? 1 : 0;
+                itg = a.Tg;
+                gfix = t;
+            }
         }
         if (!__syncthreads_or(done ? 0 : 1)) break;
         if (L.lane_ok && L.v == 0) shf[L.sl * 8 + ((t + 1) & 1)] = 0;
@@ -370,6 +519,8 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a) {
             s.local_iters_sum = shf[L.sl * 8 + SF_ITSUM];
             s.local_iters_max = shf[L.sl * 8 + SF_ITMAX];
             s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
+            s.local_fixed_views = shf[L.sl * 8 + SF_NFIX];
+            s.global_fixed_iter = gfix;
             a.stats[L.shot] = s;
         }
     }
@@ -471,13 +622,20 @@ __global__ void __launch_bounds__(WG) round_kernel(RoundArgs ra) {
                     st.q[c] = __float_as_uint(Cg[(c * 4 + 3) * N]);
                 }
         }
-        bool sat = true;
-        if (!done) sat = check_pass<WG, RMAX>(a, bl, sv, st);
+        bool sat = true, same = true;
+        if (!done) sat = check_pass<WG, RMAX>(a, bl, sv, st, same);
         if (!done && !sat) shf[L.sl * 8 + SF_FLAG0] = 1;
+        if (!done && !same) shf[L.sl * 8 + SF_CHG] = 1;
         __syncthreads();
-        if (!done && t > 1 && a.early_exit && shf[L.sl * 8 + SF_FLAG0] == 0) {
-            done = true;
-            if (L.v == 0) { stat[0] = 1; stat[1] = 1; stat[2] = t - 1; }
+        if (!done && t > 1) {
+            const bool shot_sat = shf[L.sl * 8 + SF_FLAG0] == 0;
+            if (shot_sat && a.early_exit) {
+                done = true;
+                if (L.v == 0) { stat[0] = 1; stat[1] = 1; stat[2] = t - 1; }
+            } else if (a.fixed_stop && shf[L.sl * 8 + SF_CHG] == 0) {
+                done = true;
+                if (L.v == 0) { stat[0] = 1; stat[1] = shot_sat ? 1 : 0; stat[2] = a.Tg; stat[3] = t; }
+            }
         }
         if (!done) {
 #pragma unroll
@@ -550,6 +708,7 @@ __global__ void __launch_bounds__(WG) round_kernel(RoundArgs ra) {
         if (L.v == 0 && a.stats) {
             a.stats[L.shot].converged = gconv;
             a.stats[L.shot].global_iters = itg;
+            a.stats[L.shot].global_fixed_iter = ran_out ? 0 : stat[3];
         }
     }
 }
@@ -575,23 +734,34 @@ hipError_t launch_round_d(int wg, const RoundArgs &ra, hipStream_t s) {
 }
 
 template <int D, int RMAX, int WG>
-hipError_t launch_decode_t(const DecodeArgs &a, hipStream_t s) {
+hipError_t launch_decode_t(const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s) {
     const size_t lds = decode_lds_bytes(D, WG, a.spw, a.n);
     const int64_t grid = (a.shots + a.spw - 1) / a.spw;
-    if (a.prior_mode == LEAD_PRIOR_PER_SHOT)
-        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 0>), dim3((unsigned)grid), dim3(WG), lds, s, a);
-    else
-        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 1>), dim3((unsigned)grid), dim3(WG), lds, s, a);
+    const bool pm0 = a.prior_mode == LEAD_PRIOR_PER_SHOT;
+    if (split) {
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
+        const int waves = w.waves;
+        const size_t llds = sizeof(float) * D * D * 64;
+        if (pm0)
+            hipLaunchKernelGGL((local_kernel<D, RMAX, 0>), dim3(waves), dim3(64), llds, s, a, w);
+        else
+            hipLaunchKernelGGL((local_kernel<D, RMAX, 1>), dim3(waves), dim3(64), llds, s, a, w);
+        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 0, true>), dim3((unsigned)grid), dim3(WG), lds, s, a, w);
+    } else if (pm0) {
+        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 0, false>), dim3((unsigned)grid), dim3(WG), lds, s, a, w);
+    } else {
+        hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 1, false>), dim3((unsigned)grid), dim3(WG), lds, s, a, w);
+    }
     return hipGetLastError();
 }
 
 template <int D, int RMAX>
-hipError_t launch_decode_d(int wg, const DecodeArgs &a, hipStream_t s) {
+hipError_t launch_decode_d(int wg, const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s) {
     switch (wg) {
-        case 64: return launch_decode_t<D, RMAX, 64>(a, s);
-        case 128: return launch_decode_t<D, RMAX, 128>(a, s);
-        case 192: return launch_decode_t<D, RMAX, 192>(a, s);
-        case 256: return launch_decode_t<D, RMAX, 256>(a, s);
+        case 64: return launch_decode_t<D, RMAX, 64>(a, w, split, s);
+        case 128: return launch_decode_t<D, RMAX, 128>(a, w, split, s);
+        case 192: return launch_decode_t<D, RMAX, 192>(a, w, split, s);
+        case 256: return launch_decode_t<D, RMAX, 256>(a, w, split, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -606,6 +776,26 @@ size_t decode_lds_bytes(int D, int wg, int spw, int n) {
            sizeof(uint32_t) * (size_t)spw * ew32;
 }
 
+// Resident 64-lane waves of local_kernel per CU (occupancy of the
+// instantiation used for this shape and prior mode).
+int local_waves_per_cu(int D, int pm) {
+    int nb = 0;
+    const size_t lds = sizeof(float) * D * D * 64;
+    hipError_t e = hipErrorInvalidValue;
+    switch (D) {
+        case 3: e = pm ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<3, 4, 1>, 64, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<3, 4, 0>, 64, lds); break;
+        case 4: e = pm ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<4, 9, 1>, 64, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<4, 9, 0>, 64, lds); break;
+        case 6: e = pm ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<6, 9, 1>, 64, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<6, 9, 0>, 64, lds); break;
+        case 8: e = pm ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<8, 16, 1>, 64, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, local_kernel<8, 16, 0>, 64, lds); break;
+        default: break;
+    }
+    return (e == hipSuccess && nb > 0) ? nb : 4;
+}
+
 // Compiled shapes: (Delta, maximum checks per vertex).
 bool kernel_supported(int D, int r) {
     switch (D) {
@@ -617,14 +807,14 @@ bool kernel_supported(int D, int r) {
     }
 }
 
-hipError_t launch_decode(int D, int, const DecodeArgs &a, hipStream_t s) {
+hipError_t launch_decode(int D, int, const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s) {
     if (a.shots <= 0) return hipSuccess;
     const int wg = workgroup_size(a.N, a.spw);
     switch (D) {
-        case 3: return launch_decode_d<3, 4>(wg, a, s);
-        case 4: return launch_decode_d<4, 9>(wg, a, s);
-        case 6: return launch_decode_d<6, 9>(wg, a, s);
-        case 8: return launch_decode_d<8, 16>(wg, a, s);
+        case 3: return launch_decode_d<3, 4>(wg, a, w, split, s);
+        case 4: return launch_decode_d<4, 9>(wg, a, w, split, s);
+        case 6: return launch_decode_d<6, 9>(wg, a, w, split, s);
+        case 8: return launch_decode_d<8, 16>(wg, a, w, split, s);
         default: return hipErrorInvalidValue;
     }
 }

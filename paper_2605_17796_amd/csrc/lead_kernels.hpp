@@ -26,8 +26,18 @@ struct DecodeArgs {
     int64_t synd_words, ehat_words;
     int32_t prior_mode, spw, N, n, r, own_max;
     float alpha, beta, clampv;
-    int32_t Tl, Tg, early_exit, stage, boost;
+    int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
     uint64_t mask[kMaxChecks];
+};
+
+// Workspace of the split path (Phase 1 in its own work-queue kernel).
+struct LocalArgs {
+    float *Lv;                 // [shots][N][D2] clamped local posteriors
+    uint32_t *vflag;           // [shots][N] iterations | converged << 16 | fixed point << 17
+    int64_t *counter;          // work-queue head
+    int64_t items;             // shots * N
+    int32_t chunk;             // items a wave takes at a time
+    int32_t waves;             // waves launched
 };
 
 struct SyndArgs {
@@ -54,9 +64,11 @@ struct RoundArgs {
 size_t decode_lds_bytes(int D, int wg, int spw, int n);
 int workgroup_size(int N, int spw);
 
-hipError_t launch_decode(int D, int rmax_needed, const DecodeArgs &a, hipStream_t s);
+hipError_t launch_decode(int D, int rmax_needed, const DecodeArgs &a, const LocalArgs &w, bool split,
+                         hipStream_t s);
 hipError_t launch_round(int D, int rmax_needed, const RoundArgs &a, hipStream_t s);
 hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s);
 bool kernel_supported(int D, int r);
+int local_waves_per_cu(int D, int pm);
 
 }  // namespace lead

@@ -156,19 +156,40 @@ def test_zero_syndrome_and_ragged_batches():
     assert out["ehat"].shape[0] == 0
 
 
-@pytest.mark.parametrize("spw", [1, 2, 3, 4])
-def test_schedule_does_not_change_results(spw):
-    """Shots per workgroup only changes the launch geometry; outputs are
-    bit-identical (M: 60 lanes per shot, up to 4 shots per 256-lane group)."""
+@pytest.mark.parametrize("sched", [dict(shots_per_workgroup=2), dict(shots_per_workgroup=3),
+                                   dict(shots_per_workgroup=4), dict(fused=1), dict(fused=1, shots_per_workgroup=4),
+                                   dict(local_chunk=64), dict(local_chunk=4096, local_waves=7)])
+def test_schedule_does_not_change_results(sched):
+    """Launch geometry (shots per workgroup, Phase 1 fused into the per-shot
+    kernel or run from a work queue, queue chunk, wave count) leaves every
+    output bit-identical (M: 60 lanes per shot, up to 4 shots per 256-lane
+    group)."""
     spec, oc = code_pair("M")
     code, dec = gpu_decoder(spec, max_iter_local=50, max_iter_global=50)
     e, s, lamv = bitflip_inputs(oc, 50, 0.05, seed=41)
     s = _gpu_syndrome(dec, e)
     ref = run_gpu(dec, s, lamv, 0, lam=True)
-    dec.set_schedule(spw)
+    dec.set_schedule(**sched)
     got = run_gpu(dec, s, lamv, 0, lam=True)
     for k in ("ehat", "post", "lam", "stats"):
         assert np.array_equal(got[k], ref[k]), k
+
+
+def test_chunked_large_batch():
+    """Batches above the workspace (32768 shots) are decoded chunk by chunk
+    with the same results as shot-by-shot sub-batches."""
+    torch = torch_dev()
+    spec, oc = code_pair("T")
+    code, dec = gpu_decoder(spec, max_shots=70000)
+    e = bitflip_packed(70000, oc.n, 0.05, seed=77)
+    synd = torch.from_numpy(_gpu_syndrome(dec, e).view(np.int64)).cuda()
+    lam = torch.full((70000,), float(channel_llr(0.05)), dtype=torch.float32, device="cuda")
+    big = dec.decode(synd, lam, lam=True)
+    idx = [0, 1, 32767, 32768, 32769, 65535, 65536, 69999]
+    part = dec.decode(synd[idx].contiguous(), lam[idx].contiguous(), lam=True)
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam", "stats"):
+        assert torch.equal(big[k][idx], part[k]), k
 
 
 def _wilson(k, n, z=1.96):
@@ -245,3 +266,30 @@ def test_plain_form_bit_identical(name, shots, p, T):
     for k in ("ehat", "post", "lam", "stats"):
         assert torch.equal(a[k], b[k]), k
     log(f"[plain] {name}: {shots} shots bit-identical, conv={float((a['stats'][:, 0] == 1).float().mean()):.3f}")
+
+
+@pytest.mark.parametrize("name,shots,p,T", [("T", 500, 0.05, 32), ("M", 300, 0.05, 50), ("M", 300, 0.02, 50),
+                                            ("L", 8, 0.02, 64)])
+def test_fixed_point_stop_is_exact(name, shots, p, T):
+    """Ending a BP run whose message state reproduces itself gives exactly the
+    outputs and reported counts of running every iteration to the cap."""
+    spec, oc = code_pair(name)
+    torch = torch_dev()
+    code, dec = gpu_decoder(spec, max_iter_local=T, max_iter_global=T, fixed_point_stop=1)
+    e, _, lamv = bitflip_inputs(oc, shots, p, seed=73)
+    synd = torch.from_numpy(_gpu_syndrome(dec, e).view(np.int64)).cuda()
+    lam = torch.from_numpy(lamv).cuda()
+    a = dec.decode(synd, lam, lam=True)
+    pa = dec.decode(synd, lam, lam=True, plain=True)
+    dec.set_params(max_iter_local=T, max_iter_global=T, fixed_point_stop=0)
+    b = dec.decode(synd, lam, lam=True)
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam"):
+        assert torch.equal(a[k], b[k]), k
+        assert torch.equal(pa[k], b[k]), k
+    assert torch.equal(a["stats"][:, :5], b["stats"][:, :5])
+    assert torch.equal(pa["stats"][:, :5], b["stats"][:, :5])
+    st = a["stats"].cpu().numpy()
+    log(f"[fixed] {name} p={p}: local views stopped at a fixed point {st[:, 5].sum() / (shots * code.info.order):.3f}, "
+        f"shots with a global fixed point {(st[:, 6] > 0).mean():.3f} (mean iteration "
+        f"{st[st[:, 6] > 0, 6].mean() if (st[:, 6] > 0).any() else 0:.1f})")
