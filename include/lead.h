@@ -191,6 +191,49 @@ typedef struct {
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);
 
+/* Times candidate schedules (fused / work-queue Phase 1, shots per
+ * workgroup, queue chunk) on the caller's batch (at most 16384 of its shots)
+ * and keeps the fastest; `best` (may be NULL) receives it.  Synchronises
+ * `stream`; allocates temporary output buffers for the trials. */
+lead_status lead_decoder_autotune(lead_decoder *dec, int64_t shots, const uint64_t *d_synd, int64_t synd_words,
+                                  const float *d_prior, lead_prior_mode mode, void *stream, lead_schedule *best);
+
+/* ------------------------------------------------------------------------ */
+/* Batched decoding: several decode requests, possibly of different codes,   */
+/* check types, shot counts and priors, in one call.                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    lead_decoder *decoder;        /* decoder of this item's code and check type  */
+    int64_t shots;
+    const uint64_t *d_synd;       /* as for lead_decode                          */
+    int64_t synd_words;
+    const float *d_prior;
+    lead_prior_mode mode;
+    uint64_t *d_ehat;
+    int64_t ehat_words;
+    float *d_post;                /* nullable                                    */
+    float *d_prior_llr;           /* nullable (required in the LOCAL stage)      */
+    lead_shot_stats *d_stats;     /* nullable                                    */
+} lead_batch_item;
+
+/* Decodes every item with lead_decode semantics.  Items of different
+ * decoders run concurrently on library streams forked from `stream` and
+ * joined back to it; items sharing a decoder run in order (they share its
+ * workspace).  Returns after enqueueing; completion is ordered on `stream`. */
+lead_status lead_batch_decode(const lead_batch_item *items, int32_t n_items, void *stream);
+
+/* The same work captured once into a HIP graph and replayed by
+ * lead_batch_graph_launch (one launch for the whole batch).  The graph
+ * reads and writes the buffers named in `items` at capture time; callers
+ * refill those buffers between launches.  A graph must not be launched
+ * concurrently with other work that uses the same decoders. */
+typedef struct lead_batch_graph lead_batch_graph;
+lead_status lead_batch_graph_create(const lead_batch_item *items, int32_t n_items, void *stream,
+                                    lead_batch_graph **out);
+lead_status lead_batch_graph_launch(lead_batch_graph *graph, void *stream);
+void lead_batch_graph_destroy(lead_batch_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,13 +56,20 @@ class lead_schedule(C.Structure):
                 ("local_waves", C.c_int32)]
 
 
+class lead_batch_item(C.Structure):
+    _fields_ = [("decoder", C.c_void_p), ("shots", C.c_int64), ("d_synd", C.c_void_p), ("synd_words", C.c_int64),
+                ("d_prior", C.c_void_p), ("mode", C.c_int32), ("d_ehat", C.c_void_p), ("ehat_words", C.c_int64),
+                ("d_post", C.c_void_p), ("d_prior_llr", C.c_void_p), ("d_stats", C.c_void_p)]
+
+
 STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views",
                 "local_fixed_views", "global_fixed_iter")
 
 SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
            "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
            "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
-           "lead_decoder_get_schedule"]
+           "lead_decoder_get_schedule", "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
+           "lead_batch_graph_launch", "lead_batch_graph_destroy"]
 
 _lib = None
 
@@ -96,9 +103,16 @@ def lib():
         L.lead_decode.argtypes = dec_args
         L.lead_decode_plain.argtypes = dec_args
         L.lead_syndrome.argtypes = [P, I64, P, I64, P, I64, P]
+        L.lead_decoder_autotune.argtypes = [P, I64, P, I64, P, I32, P, C.POINTER(lead_schedule)]
+        L.lead_batch_decode.argtypes = [C.POINTER(lead_batch_item), I32, P]
+        L.lead_batch_graph_create.argtypes = [C.POINTER(lead_batch_item), I32, P, C.POINTER(P)]
+        L.lead_batch_graph_launch.argtypes = [P, P]
+        L.lead_batch_graph_destroy.argtypes = [P]
+        L.lead_batch_graph_destroy.restype = None
         for name in SYMBOLS:
             fn = getattr(L, name)
-            if name not in ("lead_code_destroy", "lead_decoder_destroy", "lead_last_error"):
+            if name not in ("lead_code_destroy", "lead_decoder_destroy", "lead_last_error",
+                            "lead_batch_graph_destroy"):
                 fn.restype = C.c_int
         _lib = L
     return _lib
@@ -196,6 +210,32 @@ def lead_decode_plain(dec, shots, synd, synd_words, prior, mode, ehat, ehat_word
 
 def lead_syndrome(dec, shots, err, err_words, synd, synd_words, stream):
     _check(lib().lead_syndrome(dec, shots, err, err_words, synd, synd_words, stream))
+
+
+def lead_decoder_autotune(dec, shots, synd, synd_words, prior, mode, stream) -> lead_schedule:
+    best = lead_schedule()
+    _check(lib().lead_decoder_autotune(dec, shots, synd, synd_words, prior, mode, stream, C.byref(best)))
+    return best
+
+
+def lead_batch_decode(items, stream):
+    arr = (lead_batch_item * len(items))(*items)
+    _check(lib().lead_batch_decode(arr, len(items), stream))
+
+
+def lead_batch_graph_create(items, stream):
+    arr = (lead_batch_item * len(items))(*items)
+    g = C.c_void_p()
+    _check(lib().lead_batch_graph_create(arr, len(items), stream, C.byref(g)))
+    return g
+
+
+def lead_batch_graph_launch(graph, stream):
+    _check(lib().lead_batch_graph_launch(graph, stream))
+
+
+def lead_batch_graph_destroy(graph):
+    lib().lead_batch_graph_destroy(graph)
 
 
 # ---------------------------------------------------------------------------
@@ -332,6 +372,27 @@ class Decoder:
            _ptr(out["stats"]), _stream(stream))
         return out
 
+    def autotune(self, synd, prior, mode=LEAD_PRIOR_PER_SHOT, stream=None) -> dict:
+        """Time the candidate schedules on this batch and keep the fastest."""
+        shots = int(synd.shape[0])
+        _need(synd, "synd", (shots, None), "int64")
+        best = lead_decoder_autotune(self._h, shots, _ptr(synd), int(synd.shape[1]), _ptr(prior), mode,
+                                     _stream(stream))
+        return {f: getattr(best, f) for f, _ in lead_schedule._fields_}
+
+    def batch_item(self, synd, prior, out, mode=LEAD_PRIOR_PER_SHOT) -> lead_batch_item:
+        shots = int(synd.shape[0])
+        _need(synd, "synd", (shots, None), "int64")
+        _need(out["ehat"], "ehat", (shots, self.ehat_words), "int64", optional=True)
+        _need(out["post"], "post", (shots, self.n), "float32", optional=True)
+        _need(out["lam"], "lam", (shots, self.n), "float32", optional=True)
+        _need(out["stats"], "stats", (shots, 8), "int32", optional=True)
+        return lead_batch_item(self._h.value, shots, synd.data_ptr(), int(synd.shape[1]), prior.data_ptr(), mode,
+                               out["ehat"].data_ptr() if out["ehat"] is not None else None, self.ehat_words,
+                               out["post"].data_ptr() if out["post"] is not None else None,
+                               out["lam"].data_ptr() if out["lam"] is not None else None,
+                               out["stats"].data_ptr() if out["stats"] is not None else None)
+
     def syndrome(self, err, stream=None):
         import torch
         shots = int(err.shape[0])
@@ -341,3 +402,36 @@ class Decoder:
         synd = torch.empty((shots, self.synd_words), dtype=torch.int64, device=err.device)
         lead_syndrome(self._h, shots, _ptr(err), int(err.shape[1]), _ptr(synd), self.synd_words, _stream(stream))
         return synd
+
+
+class Batch:
+    """Several decode requests (possibly of different codes) decoded by one
+    call, or captured once into a graph and replayed.  Each entry is
+    (decoder, synd, prior, out, mode); the tensors must stay alive."""
+
+    def __init__(self, entries):
+        self.entries = list(entries)
+        self.items = [dec.batch_item(synd, prior, out, mode) for dec, synd, prior, out, mode in self.entries]
+        self._graph = None
+
+    def run(self, stream=None):
+        lead_batch_decode(self.items, _stream(stream))
+
+    def capture(self, stream=None):
+        if self._graph is None:
+            self._graph = lead_batch_graph_create(self.items, _stream(stream))
+        return self
+
+    def replay(self, stream=None):
+        if self._graph is None:
+            self.capture(stream)
+        lead_batch_graph_launch(self._graph, _stream(stream))
+
+    def __del__(self):
+        g = getattr(self, "_graph", None)
+        if g and _lib is not None:
+            try:
+                _lib.lead_batch_graph_destroy(g)
+            except Exception:
+                pass
+            self._graph = None

@@ -17,6 +17,11 @@ struct lead_code {
     lead::Code c;
 };
 
+struct lead_batch_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct lead_decoder {
     lead::Code const *code = nullptr;
     std::shared_ptr<lead::Code> keep;       // decoders keep their own copy of the tables
@@ -158,6 +163,84 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Library streams (default priority) used to run batch items concurrently.
+struct StreamPool {
+    int device = -1;
+    std::vector<hipStream_t> streams;
+};
+thread_local StreamPool g_pool;
+
+hipError_t pool_streams(int count, std::vector<hipStream_t> &out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (g_pool.device != dev) {
+        g_pool.streams.clear();   // streams of another device are left to the runtime
+        g_pool.device = dev;
+    }
+    while ((int)g_pool.streams.size() < count) {
+        hipStream_t st = nullptr;
+        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
+        g_pool.streams.push_back(st);
+    }
+    out.assign(g_pool.streams.begin(), g_pool.streams.begin() + count);
+    return hipSuccess;
+}
+
+lead_status check_item(const lead_batch_item &it) {
+    return check_decode_args(it.decoder, it.shots, it.d_synd, it.synd_words, it.d_prior, it.mode, it.d_ehat,
+                             it.ehat_words, it.d_prior_llr);
+}
+
+// Groups items by decoder (items sharing a decoder share its workspace and
+// must run in order).
+int group_items(const lead_batch_item *items, int32_t n, std::vector<int> &group) {
+    std::vector<lead_decoder *> decs;
+    group.resize(n);
+    for (int i = 0; i < n; ++i) {
+        auto it = std::find(decs.begin(), decs.end(), items[i].decoder);
+        group[i] = (int)(it - decs.begin());
+        if (it == decs.end()) decs.push_back(items[i].decoder);
+    }
+    return (int)decs.size();
+}
+
+// Fork from `stream`, run each decoder's items in order on its own library
+// stream, join back into `stream`.  The events used are appended to `events`
+// (the caller destroys them, after the end of a capture when capturing).
+lead_status enqueue_batch(const lead_batch_item *items, int32_t n, hipStream_t stream,
+                          const std::vector<hipStream_t> &streams, const std::vector<int> &group, int ngroups,
+                          std::vector<hipEvent_t> &events) {
+    hipError_t e;
+    hipEvent_t start = nullptr;
+    if ((e = hipEventCreateWithFlags(&start, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    events.push_back(start);
+    if ((e = hipEventRecord(start, stream)) != hipSuccess) return hip_fail(e, "event record");
+    for (int g = 0; g < ngroups; ++g)
+        if ((e = hipStreamWaitEvent(streams[g], start, 0)) != hipSuccess) return hip_fail(e, "stream wait");
+    for (int i = 0; i < n; ++i) {
+        const lead_batch_item &it = items[i];
+        if (it.shots == 0) continue;
+        e = decode_chunks(it.decoder, it.shots, it.d_synd, it.synd_words, it.d_prior, it.mode, it.d_ehat,
+                          it.ehat_words, it.d_post, it.d_prior_llr, it.d_stats, it.decoder->params.stage,
+                          streams[group[i]]);
+        if (e != hipSuccess) return hip_fail(e, "batch launch");
+    }
+    for (int g = 0; g < ngroups; ++g) {
+        hipEvent_t done = nullptr;
+        if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+        events.push_back(done);
+        if ((e = hipEventRecord(done, streams[g])) != hipSuccess) return hip_fail(e, "event record");
+        if ((e = hipStreamWaitEvent(stream, done, 0)) != hipSuccess) return hip_fail(e, "stream wait");
+    }
+    return LEAD_OK;
+}
+
+void destroy_events(std::vector<hipEvent_t> &events) {
+    for (auto ev : events) (void)hipEventDestroy(ev);
+    events.clear();
 }
 
 }  // namespace
@@ -415,6 +498,154 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
     }
     ra.phase = 2;
     if ((e = lead::launch_round(d->D, d->r, ra, s)) != hipSuccess) return hip_fail(e, "finalize launch");
+    return LEAD_OK;
+}
+
+lead_status lead_batch_decode(const lead_batch_item *items, int32_t n, void *stream) {
+    if (n < 0 || (n > 0 && !items)) return fail(LEAD_E_ARG, "bad item list");
+    for (int i = 0; i < n; ++i) {
+        lead_status st = check_item(items[i]);
+        if (st != LEAD_OK) return fail(st, "item " + std::to_string(i) + ": " + g_err);
+    }
+    if (n == 0) return LEAD_OK;
+    std::vector<int> group;
+    const int ng = group_items(items, n, group);
+    std::vector<hipStream_t> streams;
+    hipError_t e = pool_streams(ng, streams);
+    if (e != hipSuccess) return hip_fail(e, "stream creation");
+    std::vector<hipEvent_t> events;
+    lead_status st = enqueue_batch(items, n, (hipStream_t)stream, streams, group, ng, events);
+    destroy_events(events);
+    return st;
+}
+
+lead_status lead_batch_graph_create(const lead_batch_item *items, int32_t n, void *stream, lead_batch_graph **out) {
+    if (!out || n < 0 || (n > 0 && !items)) return fail(LEAD_E_ARG, "bad argument");
+    *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        lead_status st = check_item(items[i]);
+        if (st != LEAD_OK) return fail(st, "item " + std::to_string(i) + ": " + g_err);
+    }
+    hipStream_t cap = nullptr;
+    hipError_t e;
+    std::vector<int> group;
+    const int ng = group_items(items, n, group);
+    std::vector<hipStream_t> streams;
+    if ((e = pool_streams(ng, streams)) != hipSuccess) return hip_fail(e, "stream creation");
+    // Capture on a private stream so the caller's stream never enters
+    // capture mode.  Wait for the caller's prior work first (the graph's
+    // launches are ordered on the launch stream).
+    if ((e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) return hip_fail(e, "synchronize");
+    if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    std::unique_ptr<lead_batch_graph> g(new (std::nothrow) lead_batch_graph());
+    if (!g) {
+        (void)hipStreamDestroy(cap);
+        return fail(LEAD_E_NOMEM, "out of host memory");
+    }
+    if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(e, "begin capture");
+    }
+    std::vector<hipEvent_t> events;
+    lead_status st = n > 0 ? enqueue_batch(items, n, cap, streams, group, ng, events) : LEAD_OK;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap, &graph);
+    destroy_events(events);
+    (void)hipStreamDestroy(cap);
+    if (st != LEAD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    g->graph = graph;
+    if ((e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "graph instantiate");
+    }
+    *out = g.release();
+    return LEAD_OK;
+}
+
+lead_status lead_batch_graph_launch(lead_batch_graph *g, void *stream) {
+    if (!g || !g->exec) return fail(LEAD_E_ARG, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return LEAD_OK;
+}
+
+void lead_batch_graph_destroy(lead_batch_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
+                                  const float *prior, lead_prior_mode mode, void *stream, lead_schedule *best) {
+    lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, nullptr, 0, nullptr);
+    if (st != LEAD_OK) return st;
+    if (shots == 0) return fail(LEAD_E_ARG, "autotune needs shots > 0");
+    const int64_t n = std::min<int64_t>(shots, 16384);
+    hipStream_t s = (hipStream_t)stream;
+    const int ew = (d->n + 63) / 64;
+    uint64_t *ehat = nullptr;
+    float *post = nullptr, *lam = nullptr;
+    lead_shot_stats *stats = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&ehat, sizeof(uint64_t) * n * ew);
+    if (e == hipSuccess) e = hipMalloc(&post, sizeof(float) * n * d->n);
+    if (e == hipSuccess) e = hipMalloc(&lam, sizeof(float) * n * d->n);
+    if (e == hipSuccess) e = hipMalloc(&stats, sizeof(lead_shot_stats) * n);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const lead_schedule saved = d->sched;
+    lead_schedule win = saved;
+    float best_ms = 1e30f;
+    if (e == hipSuccess) {
+        std::vector<lead_schedule> cand;
+        for (int fused = 0; fused < 2; ++fused)
+            for (int spw : {1, 2, 4, 8, 16, 21})
+                for (int chunk : {64, 256, 1024}) {
+                    if (fused && chunk != 256) continue;
+                    if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup) continue;
+                    if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, spw), spw, d->n) > 65536) continue;
+                    cand.push_back(lead_schedule{spw, fused, chunk, 0});
+                }
+        for (const lead_schedule &c : cand) {
+            if (lead_decoder_set_schedule(d, &c) != LEAD_OK) continue;
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, s);
+                if (e == hipSuccess)
+                    e = decode_chunks(d, n, synd, synd_words, prior, mode, ehat, ew, post,
+                                      d->params.stage == LEAD_STAGE_LOCAL ? lam : nullptr, stats, d->params.stage, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && rep > 0) ms_best = std::min(ms_best, ms);
+            }
+            if (e != hipSuccess) break;
+            if (ms_best < best_ms) {
+                best_ms = ms_best;
+                win = d->sched;
+            }
+        }
+    }
+    (void)hipFree(ehat);
+    (void)hipFree(post);
+    (void)hipFree(lam);
+    (void)hipFree(stats);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        d->sched = saved;
+        d->spw = saved.shots_per_workgroup;
+        return hip_fail(e, "autotune");
+    }
+    d->sched = win;
+    d->spw = win.shots_per_workgroup;
+    if (best) *best = win;
     return LEAD_OK;
 }
 
