@@ -234,6 +234,60 @@ lead_status lead_batch_graph_create(const lead_batch_item *items, int32_t n_item
 lead_status lead_batch_graph_launch(lead_batch_graph *graph, void *stream);
 void lead_batch_graph_destroy(lead_batch_graph *graph);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: a request loop with continuous batching.                          */
+/* ------------------------------------------------------------------------ */
+
+/* A server decodes requests (host syndrome batches with per-shot channel
+ * LLRs) for a fixed set of decoders.  A worker thread packs waiting requests
+ * of one decoder, in arrival order, into launch slots of up to
+ * `max_batch_shots` shots (splitting larger requests); each slot has its own
+ * decoder copy (device-resident code tables and workspace), device buffers,
+ * pinned staging and stream, and runs copy-in, decode and copy-out.  Requests
+ * that arrive while slots are busy are admitted into the next slot that
+ * frees, so their work overlaps the work already on the device.  Slots are
+ * created until their device memory would exceed `mem_budget_bytes` (at
+ * least one per decoder, at most `max_slots_per_decoder`). */
+typedef struct lead_server lead_server;
+
+typedef struct {
+    int64_t mem_budget_bytes;       /* device memory for slots (0 = 1 GiB)          */
+    int32_t max_batch_shots;        /* shots per launch slot (0 = 4096)             */
+    int32_t max_slots_per_decoder;  /* (0 = 4)                                      */
+    int32_t return_posteriors;      /* 1: keep L_post of every shot for the result */
+} lead_server_config;
+
+typedef struct {
+    int64_t submitted, completed, shots_completed, launches;
+    int32_t slots;                  /* launch slots created                         */
+    int32_t reserved;
+} lead_server_stats;
+
+/* Decoders are used as templates: the server clones them (parameters and
+ * schedule included); the caller keeps ownership of the originals. */
+lead_status lead_server_create(lead_decoder *const *decoders, int32_t n_decoders, const lead_server_config *config,
+                               lead_server **out);
+/* Copies the request's inputs (h_synd: shots x synd_words, h_prior: shots
+ * LLRs, one per shot) and queues it; *ticket identifies it.  Thread-safe. */
+lead_status lead_server_submit(lead_server *server, int32_t decoder_index, int64_t shots, const uint64_t *h_synd,
+                               int64_t synd_words, const float *h_prior, int64_t *ticket);
+/* *done = 1 once every shot of the request is decoded (0 otherwise). */
+lead_status lead_server_poll(lead_server *server, int64_t ticket, int32_t *done);
+/* Blocks until the request is decoded. */
+lead_status lead_server_wait(lead_server *server, int64_t ticket);
+/* Copies the results of a finished request (h_ehat: shots x ceil(n/64);
+ * h_post: shots x n, only with return_posteriors; h_stats: shots; any may be
+ * NULL), reports its submit and completion times (nanoseconds of the
+ * library's steady clock; may be NULL), and releases it. */
+lead_status lead_server_result(lead_server *server, int64_t ticket, uint64_t *h_ehat, float *h_post,
+                               lead_shot_stats *h_stats, int64_t *submit_ns, int64_t *done_ns);
+lead_status lead_server_get_stats(lead_server *server, lead_server_stats *out);
+/* Current value of the clock used for request timestamps. */
+int64_t lead_server_clock_ns(void);
+/* Finishes the work on the device, stops the worker, frees everything;
+ * unreleased requests are dropped. */
+void lead_server_destroy(lead_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,16 @@ class lead_batch_item(C.Structure):
                 ("d_post", C.c_void_p), ("d_prior_llr", C.c_void_p), ("d_stats", C.c_void_p)]
 
 
+class lead_server_config(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_int64), ("max_batch_shots", C.c_int32),
+                ("max_slots_per_decoder", C.c_int32), ("return_posteriors", C.c_int32)]
+
+
+class lead_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("shots_completed", C.c_int64),
+                ("launches", C.c_int64), ("slots", C.c_int32), ("reserved", C.c_int32)]
+
+
 STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views",
                 "local_fixed_views", "global_fixed_iter")
 
@@ -69,7 +79,9 @@ SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_
            "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
            "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
            "lead_decoder_get_schedule", "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
-           "lead_batch_graph_launch", "lead_batch_graph_destroy"]
+           "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_server_create", "lead_server_submit",
+           "lead_server_poll", "lead_server_wait", "lead_server_result", "lead_server_get_stats",
+           "lead_server_clock_ns", "lead_server_destroy"]
 
 _lib = None
 
@@ -109,10 +121,21 @@ def lib():
         L.lead_batch_graph_launch.argtypes = [P, P]
         L.lead_batch_graph_destroy.argtypes = [P]
         L.lead_batch_graph_destroy.restype = None
+        L.lead_server_create.argtypes = [C.POINTER(P), I32, C.POINTER(lead_server_config), C.POINTER(P)]
+        L.lead_server_submit.argtypes = [P, I32, I64, P, I64, P, C.POINTER(I64)]
+        L.lead_server_poll.argtypes = [P, I64, C.POINTER(I32)]
+        L.lead_server_wait.argtypes = [P, I64]
+        L.lead_server_result.argtypes = [P, I64, P, P, P, C.POINTER(I64), C.POINTER(I64)]
+        L.lead_server_get_stats.argtypes = [P, C.POINTER(lead_server_stats)]
+        L.lead_server_clock_ns.argtypes = []
+        L.lead_server_destroy.argtypes = [P]
+        L.lead_server_destroy.restype = None
         for name in SYMBOLS:
             fn = getattr(L, name)
-            if name not in ("lead_code_destroy", "lead_decoder_destroy", "lead_last_error",
-                            "lead_batch_graph_destroy"):
+            if name == "lead_server_clock_ns":
+                fn.restype = C.c_int64
+            elif name not in ("lead_code_destroy", "lead_decoder_destroy", "lead_last_error",
+                              "lead_batch_graph_destroy", "lead_server_destroy"):
                 fn.restype = C.c_int
         _lib = L
     return _lib
@@ -435,3 +458,67 @@ class Batch:
             except Exception:
                 pass
             self._graph = None
+
+
+class Server:
+    """Continuous-batching request loop over a set of decoders (host
+    requests in, host results out)."""
+
+    def __init__(self, decoders, mem_budget_bytes=1 << 30, max_batch_shots=4096, max_slots_per_decoder=4,
+                 return_posteriors=False):
+        self.decoders = list(decoders)
+        arr = (C.c_void_p * len(self.decoders))(*[d._h.value for d in self.decoders])
+        cfg = lead_server_config(mem_budget_bytes, max_batch_shots, max_slots_per_decoder, int(return_posteriors))
+        self.return_posteriors = return_posteriors
+        h = C.c_void_p()
+        _check(lib().lead_server_create(arr, len(self.decoders), C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def submit(self, index: int, synd: np.ndarray, prior: np.ndarray) -> int:
+        synd = np.ascontiguousarray(synd, dtype=np.uint64)
+        prior = np.ascontiguousarray(prior, dtype=np.float32)
+        if synd.ndim != 2 or prior.shape != (synd.shape[0],):
+            raise ValueError("synd must be [shots, words] and prior [shots]")
+        t = C.c_int64()
+        _check(lib().lead_server_submit(self._h, index, synd.shape[0], _np_ptr(synd), synd.shape[1],
+                                        _np_ptr(prior), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        _check(lib().lead_server_poll(self._h, ticket, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(lib().lead_server_wait(self._h, ticket))
+
+    def result(self, ticket: int, index: int, shots: int) -> dict:
+        dec = self.decoders[index]
+        ehat = np.zeros((shots, dec.ehat_words), dtype=np.uint64)
+        stats = np.zeros((shots, 8), dtype=np.int32)
+        post = np.zeros((shots, dec.n), dtype=np.float32) if self.return_posteriors else None
+        t0, t1 = C.c_int64(), C.c_int64()
+        _check(lib().lead_server_result(self._h, ticket, _np_ptr(ehat), None if post is None else _np_ptr(post),
+                                        _np_ptr(stats), C.byref(t0), C.byref(t1)))
+        return dict(ehat=ehat, post=post, stats=stats, submit_ns=t0.value, done_ns=t1.value)
+
+    def stats(self) -> dict:
+        st = lead_server_stats()
+        _check(lib().lead_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in lead_server_stats._fields_}
+
+    @staticmethod
+    def clock_ns() -> int:
+        return lib().lead_server_clock_ns()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.lead_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["code_build.cpp", "lead_api.cpp", "lead_kernels.hip"]
+SOURCES = ["code_build.cpp", "lead_api.cpp", "lead_server.cpp", "lead_kernels.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -11,6 +11,7 @@
 
 #include "../../include/lead.h"
 #include "code_build.hpp"
+#include "lead_internal.hpp"
 #include "lead_kernels.hpp"
 
 struct lead_code {
@@ -303,14 +304,17 @@ lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_
 
 void lead_code_destroy(lead_code *code) { delete code; }
 
-lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const lead_params *params,
-                                int64_t max_shots, lead_decoder **out) {
-    if (!code || !out || (t != LEAD_CHECK_Z && t != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad argument");
+}  // extern "C"
+
+namespace {
+
+lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_params *params, int64_t max_shots,
+                           lead_decoder **out) {
     *out = nullptr;
     if (max_shots < 0) return fail(LEAD_E_ARG, "max_shots < 0");
     lead_status st = check_params(params);
     if (st != LEAD_OK) return st;
-    const lead::Code &c = code->c;
+    const lead::Code &c = *code;
     const lead::TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
     if (!lead::kernel_supported(D, tt.r))
@@ -323,7 +327,7 @@ lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const 
         return fail(LEAD_E_UNSUPPORTED, "group order above " + std::to_string(lead::kMaxWorkgroup));
     std::unique_ptr<lead_decoder> d(new (std::nothrow) lead_decoder());
     if (!d) return fail(LEAD_E_NOMEM, "out of host memory");
-    d->keep = std::make_shared<lead::Code>(c);
+    d->keep = std::move(code);
     d->code = d->keep.get();
     d->type = t;
     d->params = *params;
@@ -352,19 +356,16 @@ lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const 
     for (int v = 0; v < d->N; ++v) {
         int k = 0;
         for (int j = 0; j < D2; ++j) {
-            const int s = v * D2 + j;
-            if (!tt.owned[s]) continue;
-            const int p = tt.partner[s];
+            const int sl = v * D2 + j;
+            if (!tt.owned[sl]) continue;
+            const int p = tt.partner[sl];
             own[(size_t)v * d->own_max + k++] =
                 (uint32_t)j | ((uint32_t)(p % D2) << 8) | ((uint32_t)(p / D2) << 16);
         }
     }
-    if ((e = hipMalloc(&d->d_view, sizeof(int32_t) * tt.view.size())) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = hipMalloc(&d->d_own, sizeof(uint32_t) * own.size())) != hipSuccess) {
-        (void)hipFree(d->d_view);
-        return hip_fail(e, "hipMalloc");
-    }
-    e = hipMemcpy(d->d_view, tt.view.data(), sizeof(int32_t) * tt.view.size(), hipMemcpyHostToDevice);
+    e = hipMalloc(&d->d_view, sizeof(int32_t) * tt.view.size());
+    if (e == hipSuccess) e = hipMalloc(&d->d_own, sizeof(uint32_t) * own.size());
+    if (e == hipSuccess) e = hipMemcpy(d->d_view, tt.view.data(), sizeof(int32_t) * tt.view.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d->d_own, own.data(), sizeof(uint32_t) * own.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d->d_Lv, sizeof(float) * (size_t)d->ws_shots * d->N * D2);
     if (e == hipSuccess) e = hipMalloc(&d->d_vflag, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
@@ -379,6 +380,42 @@ lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const 
     }
     *out = d.release();
     return LEAD_OK;
+}
+
+}  // namespace
+
+namespace lead {
+
+lead_status clone_decoder(const lead_decoder *src, int64_t max_shots, lead_decoder **out) {
+    if (!src || !out) return fail(LEAD_E_ARG, "bad argument");
+    lead_status st = create_decoder(src->keep, src->type, &src->params, max_shots, out);
+    if (st != LEAD_OK) return st;
+    (*out)->sched = src->sched;
+    (*out)->spw = src->spw;
+    return LEAD_OK;
+}
+
+void decoder_shape(const lead_decoder *d, int *n, int *m) {
+    *n = d->n;
+    *m = d->m;
+}
+
+lead_status set_error(lead_status s, const char *msg) { return fail(s, msg); }
+
+}  // namespace lead
+
+extern "C" {
+
+lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const lead_params *params,
+                                int64_t max_shots, lead_decoder **out) {
+    if (!code || !out || (t != LEAD_CHECK_Z && t != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad argument");
+    std::shared_ptr<lead::Code> copy;
+    try {
+        copy = std::make_shared<lead::Code>(code->c);
+    } catch (const std::bad_alloc &) {
+        return fail(LEAD_E_NOMEM, "out of host memory");
+    }
+    return create_decoder(std::move(copy), t, params, max_shots, out);
 }
 
 lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) {
