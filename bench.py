@@ -1,16 +1,22 @@
 """Benchmark: decoded shots/s of the LEAD decoder on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): the A_5 code
-(order 60, Delta = 6, [6,3] local codes, n = 1080, m = 540 Z checks), i.i.d.
-bit flips with p = 0.05, channel LLR ln(19) per shot, min-sum scale 0.75,
-alpha = 1, at most 50 local and 50 global iterations, 10^5 shots per step.
-One step = one full LEAD decode of a batch already resident in HBM: local BP
-on all 60 vertex views of every shot, alpha-regularised aggregation, global
-BP, and the outputs (packed e_hat, FP32 posterior LLRs, per-shot statistics)
-written back to HBM.  Every step decodes a different batch.
+Headline workload: the A_5 code (order 60, Delta = 6, [6,3] local codes,
+n = 1080, m = 540 Z checks), i.i.d. bit flips with p = 0.05, channel LLR
+ln(19) per shot, min-sum scale 0.75, alpha = 1, at most 50 local and 50
+global iterations, 10^5 shots per step.  One step = one full LEAD decode of
+a batch already resident in HBM (local BP on all 60 vertex views of every
+shot, alpha-regularised aggregation, global BP, and e_hat, FP32 posterior
+LLRs and per-shot statistics written back to HBM), replayed as a captured
+graph with the autotuned schedule.  Every step decodes a different batch.
 
-Prints one JSON line.  See the design doc for the roofline and baseline
-definitions.
+Reported beside it (same GPU, identical outputs): the plain per-round-launch
+form on the same batches; a mixed-code batch (D6 / A5 / PSL(2,7) codes with
+10^3 / 3*10^4 / 10^5 shots, p ~ U[0.02, 0.08] per shot) as one graph launch
+vs plain per-code launches; the serving loop fed a Poisson request stream
+(batch sizes log-uniform in 1..4096) with p50/p99 latency; the dominant
+kernel's roofline; and the FP64 oracle on the host cores.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,13 +34,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 P_FLIP = 0.05
-ROUNDS = 50
+ROUNDS = {"T": 32, "M": 50, "L": 64}
 SHOTS = 100_000
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: non-packed FP32/INT VALU lane-ops
 VALU_PEAK_GOPS = 256 * 64 * 2.4
 # Lane operations counted per edge update of min-sum (check update of one
-# edge plus its share of the variable update); see the design doc.
+# edge plus its share of the variable update).
 OPS_PER_EDGE_UPDATE = 10
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_17796_amd", "csrc", "lead_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_kernel_A5_p005_traffic.json")
@@ -50,9 +56,18 @@ def algorithmic_bytes_per_shot(n: int, m: int) -> float:
     return m / 8 + 4 + n / 8 + 4 * n + 20
 
 
+def edge_updates(stats: np.ndarray, eloc: int, order: int) -> float:
+    """Min-sum edge updates a decode performed: every local run updates the
+    E_loc edges of its view once per iteration, every global iteration the
+    order * E_loc edges of the global graph."""
+    return float(stats[:, 2].astype(np.float64).sum() * eloc + stats[:, 1].astype(np.float64).sum() * eloc * order)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline (FP64 oracle, test infrastructure)
+# ---------------------------------------------------------------------------
+
 def cpu_baseline(spec, shots_sample: int, seed: int, workers: int):
-    """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload, in independent worker processes."""
     t0 = time.time()
     with mp.get_context("spawn").Pool(workers) as pool:
         per = [shots_sample // workers + (1 if i < shots_sample % workers else 0) for i in range(workers)]
@@ -72,7 +87,7 @@ def _oracle_worker(job):
     e = bitflip_packed(shots, oc.n, P_FLIP, seed)
     s = oc.syndrome(e)
     oc.decode(s, np.full(shots, float(channel_llr(P_FLIP))),
-              p=O.params(max_iter_local=ROUNDS, max_iter_global=ROUNDS))
+              p=O.params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"]))
     return shots
 
 
@@ -86,6 +101,108 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": x.numel() * 4, "launches": 3}), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+
+def make_decoder(P, name, max_shots):
+    from lead_inputs import standard
+    code = P.Code.from_spec(standard(name))
+    dec = P.Decoder(code, max_shots=max_shots, max_iter_local=ROUNDS[name], max_iter_global=ROUNDS[name],
+                    ms_scale=0.75, alpha=1.0)
+    return code, dec
+
+
+def syndromes(torch, dec, n, shots, p, seed, distinct=None):
+    """Device syndromes of `shots` seeded bit-flip errors (p scalar or per
+    shot).  With `distinct`, that many error rows are drawn and repeated."""
+    from lead_inputs import bitflip_packed
+    k = shots if distinct is None else min(distinct, shots)
+    pk = p if np.isscalar(p) else np.asarray(p)[:k]
+    e = bitflip_packed(k, n, pk, seed)
+    s = dec.syndrome(torch.from_numpy(e.view(np.int64)).cuda())
+    if k < shots:
+        reps = -(-shots // k)
+        s = s.repeat(reps, 1)[:shots].contiguous()
+    return s
+
+
+def timed(torch, fn, reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(reps):
+        ev[i][0].record(stream)
+        fn(i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def served_stream(P, decs, requests, offered_shots_per_s, seed):
+    """Feed `requests` [(decoder index, synd, prior)] to a fresh server at
+    Poisson arrival times for the offered load; returns throughput and
+    latency percentiles."""
+    server = P.Server(list(decs), mem_budget_bytes=8 << 30, max_batch_shots=8192, max_slots_per_decoder=4)
+    rng = np.random.default_rng(seed)
+    mean_shots = np.mean([r[1].shape[0] for r in requests])
+    rate = offered_shots_per_s / mean_shots
+    gaps = rng.exponential(1.0 / rate, size=len(requests))
+    tickets = []
+    due = time.perf_counter()
+    for (k, synd, prior), gap in zip(requests, gaps):
+        due += gap
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        tickets.append((k, synd.shape[0], server.submit(k, synd, prior)))
+    lat, first, last, shots = [], None, None, 0
+    for k, n, t in tickets:
+        server.wait(t)
+        r = server.result(t, k, n)
+        lat.append((r["done_ns"] - r["submit_ns"]) / 1e6)
+        first = r["submit_ns"] if first is None else min(first, r["submit_ns"])
+        last = r["done_ns"] if last is None else max(last, r["done_ns"])
+        shots += n
+    st = server.stats()
+    server.close()
+    span = (last - first) / 1e9
+    lat = np.array(lat)
+    return {"offered_shots_per_s": offered_shots_per_s, "requests": len(requests), "shots": shots,
+            "shots_per_s": round(shots / span, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "launches": st["launches"], "slots": st["slots"]}
+
+
+def request_mix(torch, decs_named, n_requests, seed, codes):
+    """Requests with log-uniform batch sizes in 1..4096, codes uniform over
+    `codes`, per-request p ~ U[0.02, 0.08]; host copies of syndromes and
+    per-shot priors."""
+    from lead_inputs import channel_llr
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(0, np.log(4097), size=n_requests))).astype(int)
+    ks = rng.integers(0, len(codes), size=n_requests)
+    ps = rng.uniform(0.02, 0.08, size=n_requests)
+    pools = {}
+    for k in range(len(codes)):
+        code, dec = decs_named[codes[k]]
+        sel = ks == k
+        if not sel.any():
+            continue
+        pp = np.repeat(ps[sel], sizes[sel])
+        s = syndromes(torch, dec, code.n, int(sizes[sel].sum()), pp, seed=seed * 7 + k, distinct=20000)
+        pools[k] = (s.cpu().numpy().view(np.uint64), channel_llr(pp))
+    off = {k: 0 for k in pools}
+    reqs = []
+    for k, n in zip(ks, sizes):
+        s, pr = pools[int(k)]
+        o = off[int(k)]
+        reqs.append((int(k), s[o:o + n], pr[o:o + n]))
+        off[int(k)] = o + n
+    return reqs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,8 +211,11 @@ def main():
     ap.add_argument("--shots", type=int, default=SHOTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3200)
-    ap.add_argument("--plain-steps", type=int, default=3,
-                    help="steps of the plain per-round-launch form timed for comparison (0 = skip)")
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the eager single-kernel pass used for the roofline (for profilers)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -109,98 +229,127 @@ def main():
 
     import torch
     import paper_2605_17796_amd as P
-    from lead_inputs import standard, bitflip_packed, channel_llr
+    from lead_inputs import channel_llr
 
     assert torch.cuda.is_available(), "no GPU"
-    dev = torch.device("cuda:0")
-    spec = standard("M")
-    code = P.Code.from_spec(spec)
-    n, m = code.n, code.m()
+    torch.cuda.set_device(0)
     shots = args.shots
-    dec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS, max_iter_global=ROUNDS, ms_scale=0.75,
-                    alpha=1.0)
-
-    # A pool of distinct error batches, resident on the GPU: step i decodes
-    # batch i mod pool.
-    pool_batches = 4
-    synd_pool = []
-    for b in range(pool_batches):
-        e = bitflip_packed(shots, n, P_FLIP, seed=1000 + b)
-        synd_pool.append(dec.syndrome(torch.from_numpy(e.view(np.int64)).to(dev)))
-    lam = torch.full((shots,), float(channel_llr(P_FLIP)), dtype=torch.float32, device=dev)
-    out = dec.alloc_outputs(shots, dev)
-    torch.cuda.synchronize()
-
-    for i in range(args.warmup):
-        dec.decode(synd_pool[i % pool_batches], lam, out=out)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    stats_acc = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        dec.decode(synd_pool[i % pool_batches], lam, out=out)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = [a.elapsed_time(b) for a, b in ev]
-    st = out["stats"].cpu().numpy()
-    stats_acc.append(st)
-
-    ms_per_step = wall * 1000.0 / args.steps
-    value = shots / (wall / args.steps)
-    k_ms = float(np.mean(kernel_ms))
-
-    # edge updates actually performed in the last step (local: every view of
-    # every shot runs its own count; global: every edge of the shot's graph)
+    code, dec = make_decoder(P, "M", shots)
+    n, m = code.n, code.m()
     info = code.info
-    eloc = info.eloc[0]
-    edge_updates = float(st[:, 2].astype(np.float64).sum() * eloc +
-                         st[:, 1].astype(np.float64).sum() * eloc * info.order)
-    bytes_launch = algorithmic_bytes_per_shot(n, m) * shots
-    hbm_gbs = bytes_launch / (k_ms * 1e-3) / 1e9
-    valu_gops = OPS_PER_EDGE_UPDATE * edge_updates / (k_ms * 1e-3) / 1e9
 
+    pool_batches = 4
+    synd_pool = [syndromes(torch, dec, n, shots, P_FLIP, seed=1000 + b) for b in range(pool_batches)]
+    lam = torch.full((shots,), float(channel_llr(P_FLIP)), dtype=torch.float32, device="cuda")
+    out = dec.alloc_outputs(shots)
+    torch.cuda.synchronize()
+
+    # ---- roofline pass: the single-kernel (fused) schedule, HIP events around
+    #      each launch on the launch stream
+    dec.set_schedule(fused=1)
+    dec.decode(synd_pool[0], lam, out=out)
+    rl_reps = 1 if args.roofline_only else 5
+    _, rl_ms = timed(torch, lambda i: dec.decode(synd_pool[i % pool_batches], lam, out=out), rl_reps)
+    st = out["stats"].cpu().numpy()
+    k_ms = float(np.mean(rl_ms))
+    eu = edge_updates(st, info.eloc[0], info.order)
+    hbm_gbs = algorithmic_bytes_per_shot(n, m) * shots / (k_ms * 1e-3) / 1e9
+    valu_gops = OPS_PER_EDGE_UPDATE * eu / (k_ms * 1e-3) / 1e9
+    if args.roofline_only:
+        print(json.dumps({"roofline_pass_ms": round(k_ms, 3)}), flush=True)
+        return
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("kernel_sha") == kernel_hash() and rec.get("shots") == shots:
             traffic = rec.get("hbm_bytes_per_launch")
+    hbm_frac, valu_frac = hbm_gbs / HBM_PEAK_GBS, valu_gops / VALU_PEAK_GOPS
+    roof = {"bound": "alu", "achieved": round(valu_gops / 1000, 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
+            "unit": "TOP/s", "frac": round(valu_frac, 4), "traffic": traffic,
+            "kernel": "decode_kernel<6,9,64,0,false> (one launch decodes the batch)", "kernel_ms": round(k_ms, 3),
+            "hbm_achieved_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_frac, 5)}
 
-    hbm_frac = hbm_gbs / HBM_PEAK_GBS
-    valu_frac = valu_gops / VALU_PEAK_GOPS
-    if hbm_frac >= valu_frac:
-        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4), "traffic": traffic}
-    else:
-        roof = {"bound": "alu", "achieved": round(valu_gops / 1000, 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
-                "unit": "TOP/s", "frac": round(valu_frac, 4), "traffic": traffic}
+    # ---- headline: autotuned schedule, each batch captured as a graph
+    dec.set_schedule()
+    best = dec.autotune(synd_pool[0], lam)
+    graphs = [P.Batch([(dec, synd_pool[b], lam, out, P.LEAD_PRIOR_PER_SHOT)]).capture()
+              for b in range(pool_batches)]
+    for i in range(args.warmup):
+        graphs[i % pool_batches].replay()
+    wall, _ = timed(torch, lambda i: graphs[i % pool_batches].replay(), args.steps)
+    st = out["stats"].cpu().numpy()
+    ms_per_step = wall * 1000.0 / args.steps
+    value = shots / (wall / args.steps)
+    del graphs
 
+    # ---- plain per-round-launch form on the same batches
     plain = None
     if args.plain_steps > 0:
         dec.decode(synd_pool[0], lam, out=out, plain=True)
-        torch.cuda.synchronize()
-        tp = time.perf_counter()
-        for i in range(args.plain_steps):
-            dec.decode(synd_pool[i % pool_batches], lam, out=out, plain=True)
-        torch.cuda.synchronize()
-        pw = (time.perf_counter() - tp) / args.plain_steps
+        pw, _ = timed(torch, lambda i: dec.decode(synd_pool[i % pool_batches], lam, out=out, plain=True),
+                      args.plain_steps)
+        pw /= args.plain_steps
         plain = {"shots_per_s": round(shots / pw, 1), "ms_per_step": round(pw * 1000, 3),
                  "form": "lead_decode_plain: Phases 1-2 launch, one launch per global round with state in HBM "
                          "and a host-visible convergence count, finalize launch",
-                 "fused_over_plain": round(value * pw / shots, 3)}
+                 "batched_over_plain": round(value * pw / shots, 3)}
+
+    # ---- mixed-code batch (D6 / A5 / PSL(2,7)): one graph launch vs plain
+    mixed = None
+    decs_named = {"M": (code, dec)}
+    if not args.no_mixed:
+        from lead_inputs import uniform_p
+        sizes = {"T": 1000, "M": 30000, "L": 100000}
+        entries, plain_items = [], []
+        for i, name in enumerate(("T", "M", "L")):
+            c2, d2 = make_decoder(P, name, sizes[name]) if name != "M" else (code, dec)
+            decs_named[name] = (c2, d2)
+            ps = uniform_p(sizes[name], 0.02, 0.08, seed=2000 + i)
+            s = syndromes(torch, d2, c2.n, sizes[name], ps, seed=2000 + i, distinct=20000)
+            pr = torch.from_numpy(channel_llr(ps)).cuda()
+            o = d2.alloc_outputs(sizes[name])
+            if name != "M":
+                d2.autotune(s, pr)
+            entries.append((d2, s, pr, o, P.LEAD_PRIOR_PER_SHOT))
+            plain_items.append((d2, s, pr, o))
+        batch = P.Batch(entries).capture()
+        batch.replay()
+        bw, _ = timed(torch, lambda i: batch.replay(), 2)
+        bw /= 2
+        pw2, _ = timed(torch, lambda i: [d2.decode(s, pr, out=o, plain=True) for d2, s, pr, o in plain_items], 1)
+        total = sum(sizes.values())
+        mixed = {"shots": sizes, "batched_graph_shots_per_s": round(total / bw, 1),
+                 "plain_per_code_shots_per_s": round(total / pw2, 1), "batched_over_plain": round(pw2 / bw, 3)}
+        del batch
+
+    # ---- serving loop: Poisson stream of host requests
+    served = None
+    if not args.no_served:
+        served = {}
+        reqs_m = request_mix(torch, decs_named, 400, seed=31, codes=["M"])
+        served["A5_only"] = [served_stream(P, [dec], reqs_m, load, seed=41) for load in (1e6, 4e6)]
+        # the same requests served without batching: one request at a time,
+        # copy-in, plain decode, copy-out
+        t0 = time.perf_counter()
+        pshots = 0
+        for k, s, pr in reqs_m[:120]:
+            o = dec.decode(torch.from_numpy(s.view(np.int64)).cuda(), torch.from_numpy(pr).cuda(), plain=True)
+            o["ehat"].cpu()
+            pshots += s.shape[0]
+        served["A5_plain_one_request_at_a_time_shots_per_s"] = round(pshots / (time.perf_counter() - t0), 1)
+        if not args.no_mixed:
+            reqs_x = request_mix(torch, decs_named, 300, seed=32, codes=["T", "M", "L"])
+            decs_x = [decs_named[c][1] for c in ("T", "M", "L")]
+            served["mixed_3_codes"] = [served_stream(P, decs_x, reqs_x, 2e5, seed=42)]
 
     cpu = None
     if not args.no_cpu_baseline:
+        from lead_inputs import standard
         workers = max(1, min(16, os.cpu_count() or 1))
-        sample = args.cpu_sample
-        rate, cwall = cpu_baseline(spec, sample, seed=7, workers=workers)
+        rate, cwall = cpu_baseline(standard("M"), args.cpu_sample, seed=7, workers=workers)
         cpu = {"value": round(rate, 1), "unit": "decoded shots/s", "cores": workers, "kind": "oracle",
-               "sample": f"{sample} shots of the same workload (A5 code, p=0.05, 50+50 rounds), FP64 oracle, "
-                         f"{workers} worker processes, {cwall:.1f} s wall"}
+               "sample": f"{args.cpu_sample} shots of the headline workload (A5 code, p=0.05, 50+50 rounds), "
+                         f"FP64 oracle, {workers} worker processes, {cwall:.1f} s wall"}
 
     line = {
         "metric": "decoded shots/sec at n~1080, p=0.05",
@@ -217,15 +366,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "LEAD-BP full decode, A5 code n=1080 (Delta=6, [6,3] local codes), "
                                "bit-flip p=0.05, <=50 local + <=50 global min-sum rounds, beta=0.75, alpha=1",
-                   "shots_per_step": shots, "form": "fused single launch (lead_decode)"},
-        "kernel_ms": round(k_ms, 3),
+                   "shots_per_step": shots,
+                   "form": "batched: captured graph of lead_decode with the autotuned schedule",
+                   "schedule": best},
         "roofline": roof,
-        "hbm_frac": round(hbm_frac, 4),
-        "valu_frac": round(valu_frac, 4),
         "decode_stats": {"converged": round(float((st[:, 0] == 1).mean()), 4),
                          "mean_global_iters": round(float(st[:, 1].mean()), 2),
-                         "mean_local_iters": round(float(st[:, 2].mean() / 60.0), 2)},
+                         "mean_local_iters": round(float(st[:, 2].mean() / info.order), 2)},
         "plain_form": plain,
+        "mixed_batch": mixed,
+        "served": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
