@@ -1,0 +1,47 @@
+// Argument blocks passed by value to the decoding kernels.  The run-time
+// compiler sees this header too; it has no <cstdint>, and its own fixed-width
+// types live in __hip_internal.
+#pragma once
+#ifdef __HIPCC_RTC__
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
+#else
+#include <cstdint>
+#endif
+
+namespace lead {
+
+constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
+
+// Everything a decode launch needs, passed by value in the kernel argument
+// segment (so the check masks live in scalar registers).
+struct DecodeArgs {
+    const uint64_t *synd;
+    const float *prior;
+    uint64_t *ehat;
+    float *post;
+    float *lam_out;
+    void *stats;               // lead_shot_stats[shots]
+    const int32_t *view;       // [N][D2] qubit ids
+    const uint32_t *own;       // [N][own_max] packed j | j' << 8 | v' << 16
+    int64_t shots;
+    int64_t synd_words, ehat_words;
+    int32_t prior_mode, spw, N, n, r, own_max;
+    float alpha, beta, clampv;
+    int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
+    uint64_t mask[kMaxChecks];
+};
+
+// Workspace of the split path (Phase 1 in its own work-queue kernel).
+struct LocalArgs {
+    float *Lv;                 // [shots][N][D2] clamped local posteriors
+    uint32_t *vflag;           // [shots][N] iterations | converged << 16 | fixed point << 17
+    int64_t *counter;          // work-queue head
+    int64_t items;             // shots * N
+    int32_t chunk;             // items a wave takes at a time
+    int32_t waves;             // waves launched
+};
+
+}  // namespace lead

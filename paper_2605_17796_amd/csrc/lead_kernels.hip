@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
             s.local_iters_max = shf[L.sl * 8 + SF_ITMAX];
             s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
             s.local_fixed_views = shf[L.sl * 8 + SF_NFIX];
-            a.stats[L.shot] = s;
+            reinterpret_cast<lead_shot_stats *>(a.stats)[L.shot] = s;
         }
         return;
     }
@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
             s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
             s.local_fixed_views = shf[L.sl * 8 + SF_NFIX];
             s.global_fixed_iter = gfix;
-            a.stats[L.shot] = s;
+            reinterpret_cast<lead_shot_stats *>(a.stats)[L.shot] = s;
         }
     }
 }
@@ -706,9 +706,10 @@ __global__ void __launch_bounds__(WG) round_kernel(RoundArgs ra) {
                 a.ehat[L.shot * a.ehat_words + w] = lo | (hi << 32);
             }
         if (L.v == 0 && a.stats) {
-            a.stats[L.shot].converged = gconv;
-            a.stats[L.shot].global_iters = itg;
-            a.stats[L.shot].global_fixed_iter = ran_out ? 0 : stat[3];
+            lead_shot_stats *so = reinterpret_cast<lead_shot_stats *>(a.stats) + L.shot;
+            so->converged = gconv;
+            so->global_iters = itg;
+            so->global_fixed_iter = ran_out ? 0 : stat[3];
         }
     }
 }

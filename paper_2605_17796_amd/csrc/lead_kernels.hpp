@@ -4,41 +4,12 @@
 #include <cstdint>
 
 #include "../../include/lead.h"
+#include "lead_args.hpp"
 
 namespace lead {
 
-constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
 constexpr int kMaxWorkgroup = 256;   // threads per workgroup
 constexpr uint32_t kNoOwn = 0xFFFFFFFFu;
-
-// Everything a decode launch needs, passed by value in the kernel argument
-// segment (so the check masks live in scalar registers).
-struct DecodeArgs {
-    const uint64_t *synd;
-    const float *prior;
-    uint64_t *ehat;
-    float *post;
-    float *lam_out;
-    lead_shot_stats *stats;
-    const int32_t *view;       // [N][D2] qubit ids
-    const uint32_t *own;       // [N][own_max] packed j | j' << 8 | v' << 16
-    int64_t shots;
-    int64_t synd_words, ehat_words;
-    int32_t prior_mode, spw, N, n, r, own_max;
-    float alpha, beta, clampv;
-    int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
-    uint64_t mask[kMaxChecks];
-};
-
-// Workspace of the split path (Phase 1 in its own work-queue kernel).
-struct LocalArgs {
-    float *Lv;                 // [shots][N][D2] clamped local posteriors
-    uint32_t *vflag;           // [shots][N] iterations | converged << 16 | fixed point << 17
-    int64_t *counter;          // work-queue head
-    int64_t items;             // shots * N
-    int32_t chunk;             // items a wave takes at a time
-    int32_t waves;             // waves launched
-};
 
 struct SyndArgs {
     const uint64_t *err;
