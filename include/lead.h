@@ -98,6 +98,15 @@ lead_status lead_code_query(const lead_code *code, lead_code_info *out);
 lead_status lead_code_get_H(const lead_code *code, lead_check_type t, int32_t *indptr, int32_t *indices);
 /* Host view table of type t: order x delta^2 qubit ids (V0 for Z, V1 for X). */
 lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_t *view);
+/* Compiles, for gfx950 and without touching a GPU, the decoding kernels
+ * specialised to the local check structure of type t (its check masks and
+ * the local position map of the two occurrences of a qubit, Sec. II-B), and
+ * caches the code object for the rest of the process; lead_decoder_create
+ * does the same on first use and then loads it.  LEAD_E_UNSUPPORTED (with the
+ * reason in lead_last_error) when the code has no position map or the
+ * run-time compiler is unavailable; decoders then use the precompiled
+ * kernels, with identical results. */
+lead_status lead_code_specialize(const lead_code *code, lead_check_type t);
 void lead_code_destroy(lead_code *code);
 
 /* ------------------------------------------------------------------------ */
@@ -187,6 +196,12 @@ typedef struct {
                                      runs in a work-queue kernel first           */
     int32_t local_chunk;          /* queue items a wave takes at a time            */
     int32_t local_waves;          /* waves of the work-queue kernel                 */
+    int32_t specialized;          /* 1: the work-queue form (fused = 0) runs the
+                                     kernels compiled for this code (see
+                                     lead_code_specialize; its own workgroup
+                                     shape, shots_per_workgroup unused); 0: the
+                                     precompiled kernels.  Reads back as 1 only
+                                     when those kernels are available.          */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);

@@ -53,7 +53,7 @@ class lead_params(C.Structure):
 
 class lead_schedule(C.Structure):
     _fields_ = [("shots_per_workgroup", C.c_int32), ("fused", C.c_int32), ("local_chunk", C.c_int32),
-                ("local_waves", C.c_int32)]
+                ("local_waves", C.c_int32), ("specialized", C.c_int32)]
 
 
 class lead_batch_item(C.Structure):
@@ -76,7 +76,7 @@ STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max
                 "local_fixed_views", "global_fixed_iter")
 
 SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
-           "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
+           "lead_code_specialize", "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
            "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
            "lead_decoder_get_schedule", "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
            "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_server_create", "lead_server_submit",
@@ -103,6 +103,7 @@ def lib():
         L.lead_code_query.argtypes = [P, C.POINTER(lead_code_info)]
         L.lead_code_get_H.argtypes = [P, I32, P, P]
         L.lead_code_get_views.argtypes = [P, I32, P]
+        L.lead_code_specialize.argtypes = [P, I32]
         L.lead_code_destroy.argtypes = [P]
         L.lead_code_destroy.restype = None
         L.lead_decoder_create.argtypes = [P, I32, C.POINTER(lead_params), I64, C.POINTER(P)]
@@ -185,6 +186,10 @@ def lead_code_get_views(code, t, order, d2):
     view = np.zeros((order, d2), dtype=np.int32)
     _check(lib().lead_code_get_views(code, t, _np_ptr(view)))
     return view
+
+
+def lead_code_specialize(code, t):
+    _check(lib().lead_code_specialize(code, t))
 
 
 def lead_code_destroy(code):
@@ -327,6 +332,10 @@ class Code:
     def views(self, t=LEAD_CHECK_Z) -> np.ndarray:
         return lead_code_get_views(self._h, t, self.info.order, self.info.delta ** 2)
 
+    def specialize(self, t=LEAD_CHECK_Z):
+        """Compile (no GPU needed) the kernels specialised to check type t."""
+        lead_code_specialize(self._h, t)
+
 
 class Decoder:
     """LEAD decoder for one check type of a code, on the current device."""
@@ -355,8 +364,9 @@ class Decoder:
         self.params = lead_params_make(**params)
         lead_decoder_set_params(self._h, self.params)
 
-    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0):
-        lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves))
+    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=1):
+        lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves,
+                                                         specialized))
 
     def get_schedule(self) -> dict:
         sc = lead_decoder_get_schedule(self._h)

@@ -94,16 +94,38 @@ int packed_rank(std::vector<uint64_t> m, int rows, int words) {
     return rank;
 }
 
-// Orient the view multigraph (one edge per qubit between its two views)
-// along Euler tours of each component, after pairing odd-degree views with
-// auxiliary edges; the tail of each real edge owns the qubit.
+// sigma[j] = j' when the other occurrence of the qubit at local position j
+// sits at position j' in every view; empty otherwise.
+void position_map(int order, int d2, TypeTables &tt) {
+    tt.sigma.assign(d2, -1);
+    for (int s = 0; s < order * d2; ++s) {
+        const int j = s % d2, jp = tt.partner[s] % d2;
+        if (tt.sigma[j] < 0) tt.sigma[j] = jp;
+        if (tt.sigma[j] != jp) { tt.sigma.clear(); return; }
+    }
+}
+
+// Ownership of every qubit (see TypeTables).  The qubits not decided by the
+// position rule are edges of a view multigraph, oriented along Euler tours
+// of each component after pairing odd-degree views with auxiliary edges; the
+// tail of each real edge owns the qubit.
 void balanced_ownership(int order, int d2, TypeTables &tt) {
     const int nslots = order * d2;
+    tt.owned.assign(nslots, 0);
+    std::vector<int> cnt(order, 0);
     // edge e = qubit, endpoints = its two slots
-    std::vector<int> first(tt.partner.size(), 0);
     std::vector<std::pair<int, int>> edges;            // (slot a, slot b), a < b
-    for (int s = 0; s < nslots; ++s)
-        if (s < tt.partner[s]) edges.push_back({s, tt.partner[s]});
+    for (int s = 0; s < nslots; ++s) {
+        if (s > tt.partner[s]) continue;
+        const int j = s % d2;
+        if (!tt.sigma.empty() && tt.sigma[j] != j) {
+            const int own = j < tt.sigma[j] ? s : tt.partner[s];
+            tt.owned[own] = 1;
+            cnt[own / d2]++;
+        } else {
+            edges.push_back({s, tt.partner[s]});
+        }
+    }
     const int real = (int)edges.size();
     std::vector<std::vector<int>> inc(order);
     auto add = [&](int e, int u, int w) { inc[u].push_back(e); if (w != u) inc[w].push_back(e); };
@@ -141,8 +163,6 @@ void balanced_ownership(int order, int d2, TypeTables &tt) {
             stack.push_back({w, e});
         }
     }
-    tt.owned.assign(nslots, 0);
-    std::vector<int> cnt(order, 0);
     for (int e = 0; e < real; ++e) {
         int a = edges[e].first, b = edges[e].second;
         int own = (tail[e] == a / d2) ? a : b;
@@ -294,6 +314,7 @@ int build_code(int order, const uint16_t *mul, int delta, const int32_t *A, cons
             tt.partner[slot_a[q]] = slot_b[q];
             tt.partner[slot_b[q]] = slot_a[q];
         }
+        position_map(N, D2, tt);
         balanced_ownership(N, D2, tt);
         // global CSR
         const int m = N * tt.r;

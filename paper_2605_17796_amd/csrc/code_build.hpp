@@ -20,10 +20,15 @@ struct TypeTables {
     int eloc = 0;
     // Each qubit sits in exactly two views; partner[v*D2+j] = v'*D2+j' is the
     // other occurrence.  owned[v*D2+j] = 1 for the occurrence that owns the
-    // qubit (computes its shared quantities).  Ownership is an orientation of
-    // the view multigraph along Euler tours, so every view owns at most
-    // ceil(D2/2) qubits.
+    // qubit (computes its shared quantities).  On a Cayley complex the local
+    // position of the other occurrence depends on j alone: sigma[j] = j' for
+    // every view (sigma is empty when that does not hold).  Then position j
+    // owns its qubit in every view when j < sigma[j]; the qubits at fixed
+    // points of sigma (and every qubit when sigma is empty) are oriented
+    // along Euler tours of the view multigraph.  Either way every view owns
+    // at most ceil(D2/2) qubits.
     std::vector<int32_t> partner;
+    std::vector<int32_t> sigma;
     std::vector<uint8_t> owned;
     int own_max = 0;
 };

@@ -12,7 +12,12 @@
 #include "../../include/lead.h"
 #include "code_build.hpp"
 #include "lead_internal.hpp"
+#include "lead_jit.hpp"
 #include "lead_kernels.hpp"
+
+static_assert(sizeof(lead::ShotStats) == sizeof(lead_shot_stats), "ShotStats layout");
+static_assert(offsetof(lead::ShotStats, global_fixed_iter) == offsetof(lead_shot_stats, global_fixed_iter),
+              "ShotStats layout");
 
 struct lead_code {
     lead::Code c;
@@ -34,6 +39,10 @@ struct lead_decoder {
     uint64_t mask[lead::kMaxChecks] = {};
     int32_t *d_view = nullptr;
     uint32_t *d_own = nullptr;
+    // kernels compiled for this code's check structure, with their tables
+    std::shared_ptr<const lead::jit::Kernels> spec;
+    uint32_t *d_pv = nullptr;
+    uint64_t *d_fown = nullptr;
     // schedule and split-path workspace (for ws_shots shots)
     lead_schedule sched{};
     int64_t ws_shots = 0;
@@ -75,6 +84,28 @@ constexpr int64_t kChunkShots = 32768;
 
 int default_spw(int N) { return std::max(1, 64 / N); }
 
+bool use_spec(const lead_decoder *d) { return d->spec && d->sched.specialized && !d->sched.fused; }
+
+// Split-path launches with the kernels compiled for the decoder's code.
+hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArgs w, hipStream_t s) {
+    const lead::jit::Kernels &k = *d->spec;
+    hipError_t e = lead::launch_reset_counter(w.counter, s);
+    if (e != hipSuccess) return e;
+    void *largs[] = {&a, &w};
+    e = hipModuleLaunchKernel(k.local[a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1, 64, 1,
+                              1, 0, s, largs, nullptr);
+    if (e != hipSuccess) return e;
+    a.spw = k.spw;
+    lead::SpecArgs x{d->d_pv, d->d_fown};
+    const int D2 = d->D * d->D, ew32 = (d->n + 31) / 32;
+    const size_t lds = (k.bperm ? 0 : sizeof(float) * (size_t)D2 * k.wg) + sizeof(int) * (size_t)k.spw * 8 +
+                       sizeof(uint32_t) * (size_t)k.spw * ew32;
+    const int64_t grid = (a.shots + k.spw - 1) / k.spw;
+    void *gargs[] = {&a, &w, &x};
+    return hipModuleLaunchKernel(k.global, (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
+                                 nullptr);
+}
+
 lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode mode) {
     lead::LocalArgs w{};
     w.Lv = d->d_Lv;
@@ -82,7 +113,8 @@ lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode
     w.counter = d->d_counter;
     w.items = shots * d->N;
     w.chunk = d->sched.local_chunk;
-    const int64_t per_cu = d->waves_per_cu[mode == LEAD_PRIOR_PER_SHOT ? 0 : 1];
+    const int pm = mode == LEAD_PRIOR_PER_SHOT ? 0 : 1;
+    const int64_t per_cu = use_spec(d) ? d->spec->local_waves_per_cu[pm] : d->waves_per_cu[pm];
     int64_t waves = d->sched.local_waves > 0 ? d->sched.local_waves : per_cu * d->cus;
     const int64_t need = (w.items + w.chunk - 1) / w.chunk;
     w.waves = (int32_t)std::max<int64_t>(1, std::min(waves, need));
@@ -160,7 +192,7 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         a.shots = cnt;
         a.stage = stage;
         const lead::LocalArgs w = local_args(d, cnt, mode);
-        hipError_t e = lead::launch_decode(d->D, d->r, a, w, split, s);
+        hipError_t e = use_spec(d) ? launch_spec(d, a, w, s) : lead::launch_decode(d->D, d->r, a, w, split, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -302,6 +334,16 @@ lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_
     return LEAD_OK;
 }
 
+lead_status lead_code_specialize(const lead_code *code, lead_check_type t) {
+    if (!code || (t != LEAD_CHECK_Z && t != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad argument");
+    const std::string src = lead::jit::source(code->c, t);
+    if (src.empty()) return fail(LEAD_E_UNSUPPORTED, "the code has no local position map");
+    std::vector<char> obj;
+    std::string err;
+    if (!lead::jit::compile(src, obj, err)) return fail(LEAD_E_UNSUPPORTED, err);
+    return LEAD_OK;
+}
+
 void lead_code_destroy(lead_code *code) { delete code; }
 
 }  // extern "C"
@@ -370,12 +412,31 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
     if (e == hipSuccess) e = hipMalloc(&d->d_Lv, sizeof(float) * (size_t)d->ws_shots * d->N * D2);
     if (e == hipSuccess) e = hipMalloc(&d->d_vflag, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
     if (e == hipSuccess) e = hipMalloc(&d->d_counter, sizeof(int64_t));
+    // kernels for this code's check structure (the precompiled ones serve
+    // when they cannot be built)
+    if (e == hipSuccess) {
+        std::string jerr;
+        d->spec = lead::jit::load(c, t, d->device, jerr);
+        if (d->spec) {
+            std::vector<uint32_t> pv;
+            std::vector<uint64_t> fown;
+            lead::jit::partner_tables(c, t, pv, fown);
+            e = hipMalloc(&d->d_pv, sizeof(uint32_t) * pv.size());
+            if (e == hipSuccess) e = hipMalloc(&d->d_fown, sizeof(uint64_t) * fown.size());
+            if (e == hipSuccess) e = hipMemcpy(d->d_pv, pv.data(), sizeof(uint32_t) * pv.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(d->d_fown, fown.data(), sizeof(uint64_t) * fown.size(), hipMemcpyHostToDevice);
+        }
+        d->sched.specialized = d->spec ? 1 : 0;
+    }
     if (e != hipSuccess) {
         (void)hipFree(d->d_view);
         (void)hipFree(d->d_own);
         (void)hipFree(d->d_Lv);
         (void)hipFree(d->d_vflag);
         (void)hipFree(d->d_counter);
+        (void)hipFree(d->d_pv);
+        (void)hipFree(d->d_fown);
         return hip_fail(e, "device allocation");
     }
     *out = d.release();
@@ -440,6 +501,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.fused = sc->fused ? 1 : 0;
     d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
     d->sched.local_waves = sc->local_waves;
+    d->sched.specialized = (sc->specialized && d->spec) ? 1 : 0;
     return LEAD_OK;
 }
 
@@ -456,6 +518,8 @@ void lead_decoder_destroy(lead_decoder *d) {
     (void)hipFree(d->d_Lv);
     (void)hipFree(d->d_vflag);
     (void)hipFree(d->d_counter);
+    (void)hipFree(d->d_pv);
+    (void)hipFree(d->d_fown);
     free_plain(d);
     delete d;
 }
@@ -646,8 +710,11 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
                     if (fused && chunk != 256) continue;
                     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup) continue;
                     if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, spw), spw, d->n) > 65536) continue;
-                    cand.push_back(lead_schedule{spw, fused, chunk, 0});
+                    cand.push_back(lead_schedule{spw, fused, chunk, 0, 0});
                 }
+        // the specialised split kernels fix their own workgroup shape
+        if (d->spec)
+            for (int chunk : {64, 256, 1024}) cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, 1});
         for (const lead_schedule &c : cand) {
             if (lead_decoder_set_schedule(d, &c) != LEAD_OK) continue;
             float ms_best = 1e30f;

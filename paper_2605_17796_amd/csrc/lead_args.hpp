@@ -15,6 +15,13 @@ namespace lead {
 
 constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
 
+// Per-shot statistics as the kernels write them (the layout of the public
+// lead_shot_stats).
+struct ShotStats {
+    int32_t converged, global_iters, local_iters_sum, local_iters_max, local_converged_views, local_fixed_views,
+        global_fixed_iter, reserved;
+};
+
 // Everything a decode launch needs, passed by value in the kernel argument
 // segment (so the check masks live in scalar registers).
 struct DecodeArgs {
@@ -23,7 +30,7 @@ struct DecodeArgs {
     uint64_t *ehat;
     float *post;
     float *lam_out;
-    void *stats;               // lead_shot_stats[shots]
+    void *stats;               // ShotStats[shots]
     const int32_t *view;       // [N][D2] qubit ids
     const uint32_t *own;       // [N][own_max] packed j | j' << 8 | v' << 16
     int64_t shots;
@@ -42,6 +49,16 @@ struct LocalArgs {
     int64_t items;             // shots * N
     int32_t chunk;             // items a wave takes at a time
     int32_t waves;             // waves launched
+};
+
+// Extra tables of the Phase 2-3 kernel compiled for one code: for view v and
+// local position j, the view holding the other occurrence of the qubit
+// (pv[v * ceil(D2/2) + j/2], 16 bits per position, even j in the low half),
+// and for views whose qubits at fixed points of the position map are owned
+// by the view, the owned positions as a bit mask (fown[v]).
+struct SpecArgs {
+    const uint32_t *pv;
+    const uint64_t *fown;
 };
 
 }  // namespace lead

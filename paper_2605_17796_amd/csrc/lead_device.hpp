@@ -1,0 +1,52 @@
+// Device arithmetic shared by the precompiled decoding kernels and the
+// kernels the library compiles at run time for one code.  Both must produce
+// the same bits, so everything here is either a correctly rounded IEEE
+// operation or a single hardware instruction (v_exp_f32, v_log_f32,
+// v_rcp_f32, v_med3_f32), never a library routine whose rounding could
+// differ between compiler versions.  Self-contained for the run-time
+// compiler.
+#pragma once
+#include "lead_args.hpp"
+
+namespace lead_dev {
+
+constexpr float kBig = 1e30f;
+constexpr uint32_t kSign = 0x80000000u;
+
+__device__ __forceinline__ float clampf(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
+
+// Sign tests use the IEEE sign bit: no variable sum or mu is ever -0 (every
+// sum starts from a prior canonicalised to +0 and x + (-x) rounds to +0), so
+// signbit(x) == (x < 0) throughout.
+__device__ __forceinline__ uint32_t signbit_of(float x) { return __float_as_uint(x) >> 31; }
+
+// Message of min-sum check state (m1, m2, am, q) to its k-th variable:
+// (-1)^{q_k} * (k == am ? m2 : m1), with m1, m2 already scaled by beta.  The
+// sign bit is moved to bit 31 and merged into the (non-negative) magnitude.
+__device__ __forceinline__ float msg_of(float m1, float m2, uint32_t am, uint32_t q, uint32_t k) {
+    const float mag = (k == am) ? m2 : m1;
+    return __uint_as_float(__float_as_uint(mag) | ((q << (31u - k)) & kSign));
+}
+
+// e^x as 2^(x log2 e) on the hardware exponential.
+__device__ __forceinline__ float exp_hw(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
+// Phase 2 of Algorithm 1 for one qubit from the clamped posteriors La, Lb of
+// its two views (Sec. III, the regularised aggregation):
+//   p = sigma(-L) = 1 / (1 + e^L),  q = 1 - p = sigma(L) = 1 / (1 + e^-L),
+//   p_hat = alpha * (p_a + p_b) / 2,  1 - p_hat = (1 - alpha) + alpha * (q_a + q_b) / 2,
+//   lambda' = ln(1 - p_hat) - ln(p_hat), clamped.
+// 1 - p_hat is formed from q rather than by subtraction, so it keeps full
+// relative precision when p_hat is close to 1.  Symmetric in (La, Lb) bit for
+// bit (only sums of the two views' terms are formed), so either occurrence of
+// the qubit computes the same value.
+__device__ __forceinline__ float aggregate_llr(float La, float Lb, float alpha, float clampv) {
+    const float pa = __builtin_amdgcn_rcpf(1.f + exp_hw(La)), pb = __builtin_amdgcn_rcpf(1.f + exp_hw(Lb));
+    const float qa = __builtin_amdgcn_rcpf(1.f + exp_hw(-La)), qb = __builtin_amdgcn_rcpf(1.f + exp_hw(-Lb));
+    const float ph = alpha * (0.5f * (pa + pb));
+    const float qh = __builtin_fmaf(alpha, 0.5f * (qa + qb), 1.f - alpha);
+    const float l2 = __builtin_amdgcn_logf(qh) - __builtin_amdgcn_logf(ph);   // log2 ratio
+    return clampf(l2 * 0.693147180559945309f, clampv) + 0.f;
+}
+
+}  // namespace lead_dev

@@ -1,0 +1,200 @@
+// Run-time compilation of the specialised kernels (see lead_jit.hpp).
+#include "lead_jit.hpp"
+
+#include <dlfcn.h>
+#include <hip/hiprtc.h>
+
+#include <cstdlib>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <utility>
+
+namespace lead {
+namespace jit {
+
+// Texts of lead_args.hpp, lead_device.hpp and lead_spec.hpp, embedded at
+// build time (the run-time compiler reads headers from memory).
+extern const int kNumHeaders;
+extern const char *const kHeaderNames[];
+extern const char *const kHeaderTexts[];
+
+namespace {
+
+// hipRTC, opened on first use: the process may already hold a copy (the one
+// PyTorch ships), which dlopen then returns.
+struct Rtc {
+    bool ok = false;
+    std::string err;
+    hiprtcResult (*create)(hiprtcProgram *, const char *, const char *, int, const char *const *,
+                           const char *const *) = nullptr;
+    hiprtcResult (*compile)(hiprtcProgram, int, const char *const *) = nullptr;
+    hiprtcResult (*log_size)(hiprtcProgram, size_t *) = nullptr;
+    hiprtcResult (*log)(hiprtcProgram, char *) = nullptr;
+    hiprtcResult (*code_size)(hiprtcProgram, size_t *) = nullptr;
+    hiprtcResult (*code)(hiprtcProgram, char *) = nullptr;
+    hiprtcResult (*destroy)(hiprtcProgram *) = nullptr;
+};
+
+const Rtc &rtc() {
+    static Rtc r;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        void *h = nullptr;
+        for (const char *name : {"libhiprtc.so.7", "libhiprtc.so", "/opt/rocm/lib/libhiprtc.so.7"})
+            if ((h = dlopen(name, RTLD_NOW | RTLD_LOCAL))) break;
+        if (!h) {
+            r.err = "hipRTC not found";
+            return;
+        }
+        auto sym = [&](auto &fp, const char *s) {
+            fp = reinterpret_cast<std::remove_reference_t<decltype(fp)>>(dlsym(h, s));
+            return fp != nullptr;
+        };
+        r.ok = sym(r.create, "hiprtcCreateProgram") && sym(r.compile, "hiprtcCompileProgram") &&
+               sym(r.log_size, "hiprtcGetProgramLogSize") && sym(r.log, "hiprtcGetProgramLog") &&
+               sym(r.code_size, "hiprtcGetCodeSize") && sym(r.code, "hiprtcGetCode") &&
+               sym(r.destroy, "hiprtcDestroyProgram");
+        if (!r.ok) r.err = "hipRTC lacks an entry point";
+    });
+    return r;
+}
+
+std::mutex g_mu;
+std::map<std::string, std::vector<char>> g_objects;
+std::map<std::pair<int, std::string>, std::shared_ptr<const Kernels>> g_modules;
+
+int workgroup_for(int order) { return ((order + 63) / 64) * 64; }
+
+}  // namespace
+
+std::string source(const Code &c, int t) {
+    const TypeTables &tt = c.t[t];
+    const int D = c.delta, D2 = D * D;
+    if (tt.sigma.empty() || (int)tt.sigma.size() != D2) return std::string();
+    int nfix = 0;
+    for (int j = 0; j < D2; ++j) nfix += tt.sigma[j] == j;
+    const int wg = workgroup_for(c.order);
+    std::ostringstream o;
+    o << "#include \"lead_spec.hpp\"\n"
+      << "struct LeadCode {\n"
+      << "    static constexpr int D = " << D << ", R = " << tt.r << ", NFIX = " << nfix << ";\n"
+      << "    static constexpr uint64_t mask[" << tt.r << "] = {";
+    for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";
+    o << "};\n    static constexpr int sigma[" << D2 << "] = {";
+    for (int j = 0; j < D2; ++j) o << (j ? ", " : "") << tt.sigma[j];
+    o << "};\n};\n";
+    for (int pm = 0; pm < 2; ++pm)
+        o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_" << pm
+          << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ">(a, w); }\n";
+    o << "extern \"C\" __global__ void __launch_bounds__(" << wg
+      << ") lead_spec_global(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) "
+      << "{ lead_spec::global_body<LeadCode, " << wg << ", " << (wg == 64 ? "true" : "false") << ">(a, w, x); }\n";
+    return o.str();
+}
+
+bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_objects.find(src);
+        if (it != g_objects.end()) {
+            obj = it->second;
+            return true;
+        }
+    }
+    const Rtc &r = rtc();
+    if (!r.ok) {
+        err = r.err;
+        return false;
+    }
+    hiprtcProgram prog = nullptr;
+    if (r.create(&prog, src.c_str(), "lead_spec_code.hip", kNumHeaders, kHeaderTexts, kHeaderNames) !=
+        HIPRTC_SUCCESS) {
+        err = "hiprtcCreateProgram failed";
+        return false;
+    }
+    const char *opts[] = {"--gpu-architecture=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                          "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult cr = r.compile(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    bool ok = cr == HIPRTC_SUCCESS;
+    if (!ok) {
+        size_t n = 0;
+        r.log_size(prog, &n);
+        std::string log(n, '\0');
+        if (n) r.log(prog, &log[0]);
+        err = "hipRTC compile failed: " + log.substr(0, 2000);
+    } else {
+        size_t n = 0;
+        ok = r.code_size(prog, &n) == HIPRTC_SUCCESS && n > 0;
+        obj.assign(n, 0);
+        ok = ok && r.code(prog, obj.data()) == HIPRTC_SUCCESS;
+        if (!ok) err = "hipRTC returned no code";
+    }
+    r.destroy(&prog);
+    if (ok) {
+        // LEAD_JIT_DUMP=<dir>: keep a copy of every code object (for inspection)
+        if (const char *dir = std::getenv("LEAD_JIT_DUMP")) {
+            std::ostringstream name;
+            name << dir << "/lead_spec_" << std::hex << std::hash<std::string>{}(src) << ".co";
+            std::ofstream(name.str(), std::ios::binary).write(obj.data(), (std::streamsize)obj.size());
+        }
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_objects.emplace(src, obj);
+    }
+    return ok;
+}
+
+std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::string &err) {
+    const std::string src = source(c, t);
+    if (src.empty()) {
+        err = "no local position map";
+        return nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_modules.find({device, src});
+        if (it != g_modules.end()) return it->second;
+    }
+    std::vector<char> obj;
+    if (!compile(src, obj, err)) return nullptr;
+    auto k = std::make_shared<Kernels>();
+    hipError_t e = hipModuleLoadData(&k->module, obj.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->local[0], k->module, "lead_spec_local_0");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->local[1], k->module, "lead_spec_local_1");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->global, k->module, "lead_spec_global");
+    if (e != hipSuccess) {
+        err = std::string("module load: ") + hipGetErrorString(e);
+        if (k->module) (void)hipModuleUnload(k->module);
+        return nullptr;
+    }
+    k->wg = workgroup_for(c.order);
+    k->spw = k->wg / c.order;
+    k->bperm = k->wg == 64;
+    for (int pm = 0; pm < 2; ++pm) {
+        int nb = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->local[pm], 64, 0) == hipSuccess && nb > 0)
+            k->local_waves_per_cu[pm] = nb;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto ins = g_modules.emplace(std::make_pair(device, src), k);
+    return ins.first->second;   // another thread may have loaded it first
+}
+
+void partner_tables(const Code &c, int t, std::vector<uint32_t> &pv, std::vector<uint64_t> &fown) {
+    const TypeTables &tt = c.t[t];
+    const int D2 = c.delta * c.delta, NP = (D2 + 1) / 2, N = c.order;
+    pv.assign((size_t)N * NP, 0u);
+    fown.assign((size_t)N, 0ull);
+    for (int v = 0; v < N; ++v)
+        for (int j = 0; j < D2; ++j) {
+            const int s = v * D2 + j;
+            const uint32_t vp = (uint32_t)(tt.partner[s] / D2);
+            pv[(size_t)v * NP + j / 2] |= vp << (16 * (j & 1));
+            if (!tt.sigma.empty() && tt.sigma[j] == j && tt.owned[s]) fown[v] |= 1ull << j;
+        }
+}
+
+}  // namespace jit
+}  // namespace lead

@@ -1,0 +1,45 @@
+// Kernels compiled at run time for the local check structure of one code.
+//
+// The check masks and the local position map of a code become compile-time
+// constants of lead_spec.hpp's kernels (hipRTC, gfx950).  Code objects are
+// cached per process by source text, modules per device; neither is ever
+// unloaded.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "code_build.hpp"
+
+namespace lead {
+namespace jit {
+
+struct Kernels {
+    hipModule_t module = nullptr;
+    hipFunction_t local[2] = {};   // Phase 1 queue kernel: per-shot prior, per-qubit prior
+    hipFunction_t global = nullptr;  // Phases 2-3
+    int wg = 0;                    // workgroup size of `global`
+    int spw = 0;                   // shots per workgroup of `global`
+    bool bperm = false;            // partner values exchanged within the wave
+    int local_waves_per_cu[2] = {4, 4};
+};
+
+// Source text of the kernels for check type t of code c; empty when the code
+// has no local position map (the precompiled kernels serve it).
+std::string source(const Code &c, int t);
+
+// Code object of `src` for gfx950 (compiled once per process).  Needs no GPU.
+bool compile(const std::string &src, std::vector<char> &obj, std::string &err);
+
+// Kernels of check type t of code c on the current device (device index
+// `device`), compiled and loaded on first use.
+std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::string &err);
+
+// Partner tables of lead::SpecArgs for check type t: pv (order * ceil(D2/2)
+// words) and fown (order words).
+void partner_tables(const Code &c, int t, std::vector<uint32_t> &pv, std::vector<uint64_t> &fown);
+
+}  // namespace jit
+}  // namespace lead

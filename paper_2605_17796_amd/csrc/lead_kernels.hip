@@ -12,8 +12,8 @@
 //
 // Phase 2 (alpha-regularised aggregation) and Phase 3 (global BP with the
 // aggregated prior) couple the two views of each qubit through LDS.  Every
-// qubit is owned by one of its two occurrences (an Euler-tour orientation
-// computed on the host, at most ceil(Delta^2/2) per view); the owner computes
+// qubit is owned by one of its two occurrences (decided on the host, at most
+// ceil(Delta^2/2) per view); the owner computes
 // the shared quantities and writes them to both occurrences, so no two lanes
 // ever touch the same LDS word between barriers.
 //
@@ -27,17 +27,7 @@
 namespace lead {
 namespace {
 
-constexpr float kBig = 1e30f;
-
-__device__ __forceinline__ float clampf(float x, float c) { return __builtin_amdgcn_fmed3f(x, -c, c); }
-
-// Message of check state (m1, m2, am, q) to its k-th variable:
-// (-1)^{q_k} * (k == am ? m2 : m1), with m1, m2 already scaled by beta.  The
-// sign bit is moved to bit 31 and merged into the (non-negative) magnitude.
-__device__ __forceinline__ float msg_of(float m1, float m2, uint32_t am, uint32_t q, uint32_t k) {
-    const float mag = (k == am) ? m2 : m1;
-    return __uint_as_float(__float_as_uint(mag) | ((q << (31u - k)) & 0x80000000u));
-}
+using namespace lead_dev;
 
 // Compressed min-sum state of the checks of one vertex: beta * smallest and
 // beta * second-smallest |mu|, edge position of the smallest, and the sign
@@ -51,11 +41,6 @@ struct CheckState {
         for (int c = 0; c < RMAX; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
     }
 };
-
-// Sign tests use the IEEE sign bit: no variable sum or mu is ever -0 (every
-// sum starts from a prior canonicalised to +0 and x + (-x) rounds to +0), so
-// signbit(x) == (x < 0) throughout.
-__device__ __forceinline__ uint32_t signbit_of(float x) { return __float_as_uint(x) >> 31; }
 
 // Check update of every check of the lane's vertex.  Reads S_j (the variable
 // sums of the previous iteration), forms mu_{j->c} = clamp(S_j - m_{c->j}),
@@ -371,10 +356,8 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
     }
     CheckState<RMAX> st;
 
-    // ---- Phase 2: regularised aggregation of the owned qubits --------------
-    // p = sigma(-L) and q = sigma(L) of both views (after the confidence
-    // boost), p_hat = alpha * mean(p), 1 - p_hat = (1 - alpha) + alpha * mean(q),
-    // lambda' = ln(1 - p_hat) - ln(p_hat).
+    // ---- Phase 2: regularised aggregation of the owned qubits, after the
+    // confidence boost (aggregate_llr) ----------------------------------------
     uint32_t ent[OWN];
     float lamp[OWN];
 #pragma unroll
@@ -392,11 +375,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
                 if (conv_v && La < 0.f) La = fminf(La, 0.f);
                 if (convf[ob % WG] && Lb < 0.f) Lb = fminf(Lb, 0.f);
             }
-            const float pa = 1.f / (1.f + expf(La)), pb = 1.f / (1.f + expf(Lb));
-            const float qa = 1.f / (1.f + expf(-La)), qb = 1.f / (1.f + expf(-Lb));
-            const float ph = a.alpha * (0.5f * (pa + pb));
-            const float qh = (1.f - a.alpha) + a.alpha * (0.5f * (qa + qb));
-            lamp[k] = clampf(logf(qh) - logf(ph), a.clampv) + 0.f;
+            lamp[k] = aggregate_llr(La, Lb, a.alpha, a.clampv);
         }
     }
     if (a.lam_out) {
@@ -407,12 +386,12 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
     if (a.stage == LEAD_STAGE_LOCAL) {
         __syncthreads();
         if (L.live && L.v == 0 && a.stats) {
-            lead_shot_stats s = {};
+            ShotStats s = {};
             s.local_iters_sum = shf[L.sl * 8 + SF_ITSUM];
             s.local_iters_max = shf[L.sl * 8 + SF_ITMAX];
             s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
             s.local_fixed_views = shf[L.sl * 8 + SF_NFIX];
-            reinterpret_cast<lead_shot_stats *>(a.stats)[L.shot] = s;
+            reinterpret_cast<ShotStats *>(a.stats)[L.shot] = s;
         }
         return;
     }
@@ -513,7 +492,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
                 a.ehat[L.shot * a.ehat_words + w] = lo | (hi << 32);
             }
         if (L.v == 0 && a.stats) {
-            lead_shot_stats s = {};
+            ShotStats s = {};
             s.converged = gconv;
             s.global_iters = itg;
             s.local_iters_sum = shf[L.sl * 8 + SF_ITSUM];
@@ -521,7 +500,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
             s.local_converged_views = shf[L.sl * 8 + SF_NCONV];
             s.local_fixed_views = shf[L.sl * 8 + SF_NFIX];
             s.global_fixed_iter = gfix;
-            reinterpret_cast<lead_shot_stats *>(a.stats)[L.shot] = s;
+            reinterpret_cast<ShotStats *>(a.stats)[L.shot] = s;
         }
     }
 }
@@ -706,7 +685,7 @@ __global__ void __launch_bounds__(WG) round_kernel(RoundArgs ra) {
                 a.ehat[L.shot * a.ehat_words + w] = lo | (hi << 32);
             }
         if (L.v == 0 && a.stats) {
-            lead_shot_stats *so = reinterpret_cast<lead_shot_stats *>(a.stats) + L.shot;
+            ShotStats *so = reinterpret_cast<ShotStats *>(a.stats) + L.shot;
             so->converged = gconv;
             so->global_iters = itg;
             so->global_fixed_iter = ran_out ? 0 : stat[3];
@@ -830,6 +809,11 @@ hipError_t launch_round(int D, int, const RoundArgs &ra, hipStream_t s) {
         case 8: return launch_round_d<8, 16>(wg, ra, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_reset_counter(int64_t *counter, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s) {

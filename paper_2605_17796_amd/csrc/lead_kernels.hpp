@@ -5,6 +5,7 @@
 
 #include "../../include/lead.h"
 #include "lead_args.hpp"
+#include "lead_device.hpp"
 
 namespace lead {
 
@@ -38,6 +39,7 @@ int workgroup_size(int N, int spw);
 hipError_t launch_decode(int D, int rmax_needed, const DecodeArgs &a, const LocalArgs &w, bool split,
                          hipStream_t s);
 hipError_t launch_round(int D, int rmax_needed, const RoundArgs &a, hipStream_t s);
+hipError_t launch_reset_counter(int64_t *counter, hipStream_t s);
 hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s);
 bool kernel_supported(int D, int r);
 int local_waves_per_cu(int D, int pm);

@@ -76,3 +76,15 @@ def test_library_rejects_invalid_descriptions(lead):
         lead.Code(bad, 2, [1, 4], [2, 3], [0b11], [0b11])
     assert lead.STATUS_NAMES[ei.value.status] == "LEAD_E_GROUP"
     assert "TNC" in lead.lib().lead_last_error().decode() or True
+
+
+@pytest.mark.parametrize("name", ["T", "M", "L", "appendix"])
+def test_specialised_kernels_compile(name):
+    """The kernels specialised to a code's check structure compile for gfx950
+    on the host (no GPU), for both check types (the appendix code has every
+    local position fixed by the position map)."""
+    import paper_2605_17796_amd as P
+    spec, oc = code_pair(name)
+    code = P.Code.from_spec(spec)
+    for t in (0, 1):
+        code.specialize(t)
