@@ -42,25 +42,39 @@ VALU_PEAK_GOPS = 256 * 64 * 2.4
 # Lane operations counted per edge update of min-sum (check update of one
 # edge plus its share of the variable update).
 OPS_PER_EDGE_UPDATE = 10
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_17796_amd", "csrc", "lead_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_kernel_A5_p005_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2605_17796_amd", "csrc")
+# sources of the kernels compiled for the code (device code and its generator)
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("lead_spec.hpp", "lead_device.hpp", "lead_args.hpp", "lead_jit.cpp")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lead_spec_global_A5_p005_traffic.json")
+# schedule of the headline when the autotuner is skipped (--schedule overrides)
+DEFAULT_SCHEDULE = {"specialized": 1, "local_chunk": 64}
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes_per_shot(n: int, m: int) -> float:
-    # syndrome in (m bits) + prior (4 B) + e_hat out (n bits) + L_post out
-    # (4n B) + statistics out (5 x 4 B)
-    return m / 8 + 4 + n / 8 + 4 * n + 20
+    # the decode's own I/O: syndrome in (m bits) + prior (4 B) + e_hat out
+    # (n bits) + L_post out (4n B) + statistics out (32 B)
+    return m / 8 + 4 + n / 8 + 4 * n + 32
 
 
-def edge_updates(stats: np.ndarray, eloc: int, order: int) -> float:
-    """Min-sum edge updates a decode performed: every local run updates the
-    E_loc edges of its view once per iteration, every global iteration the
-    order * E_loc edges of the global graph."""
-    return float(stats[:, 2].astype(np.float64).sum() * eloc + stats[:, 1].astype(np.float64).sum() * eloc * order)
+def global_kernel_bytes_per_shot(n: int, m: int, order: int, d2: int) -> float:
+    # Phases 2-3 kernel: local posteriors in (order * d2 * 4 B) and their
+    # flags (order * 4 B), syndrome in, e_hat + L_post + statistics out
+    return order * d2 * 4 + order * 4 + m / 8 + n / 8 + 4 * n + 32
+
+
+def edge_updates(stats: np.ndarray, eloc: int, order: int):
+    """Min-sum edge updates of a decode, (Phase 1, Phase 3): every local run
+    updates the E_loc edges of its view once per iteration, every global
+    iteration the order * E_loc edges of the global graph."""
+    return (float(stats[:, 2].astype(np.float64).sum() * eloc),
+            float(stats[:, 1].astype(np.float64).sum() * eloc * order))
 
 
 # ---------------------------------------------------------------------------
@@ -215,7 +229,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="only the eager single-kernel pass used for the roofline (for profilers)")
+                    help="only the eager pass used for the roofline, with --schedule (for profilers)")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="JSON schedule of the headline instead of the autotuner's choice")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -244,34 +260,64 @@ def main():
     out = dec.alloc_outputs(shots)
     torch.cuda.synchronize()
 
-    # ---- roofline pass: the single-kernel (fused) schedule, HIP events around
-    #      each launch on the launch stream
-    dec.set_schedule(fused=1)
+    # ---- schedule of the headline: the autotuner's choice (or --schedule)
+    if args.schedule is not None or args.roofline_only:
+        best = dict(DEFAULT_SCHEDULE if args.schedule is None else json.loads(args.schedule))
+        dec.set_schedule(**best)
+        best = dec.get_schedule()
+    else:
+        best = dec.autotune(synd_pool[0], lam)
+
+    # ---- roofline pass: eager decodes with that schedule; HIP events on the
+    #      decode stream around every Phase 1 and Phases 2-3 launch
     dec.decode(synd_pool[0], lam, out=out)
-    rl_reps = 1 if args.roofline_only else 5
-    _, rl_ms = timed(torch, lambda i: dec.decode(synd_pool[i % pool_batches], lam, out=out), rl_reps)
-    st = out["stats"].cpu().numpy()
-    k_ms = float(np.mean(rl_ms))
-    eu = edge_updates(st, info.eloc[0], info.order)
-    hbm_gbs = algorithmic_bytes_per_shot(n, m) * shots / (k_ms * 1e-3) / 1e9
-    valu_gops = OPS_PER_EDGE_UPDATE * eu / (k_ms * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    rl_reps = 2 if args.roofline_only else 4
+    dec.time_phases(True)
+    eu_local = eu_global = 0.0
+    for i in range(rl_reps):
+        dec.decode(synd_pool[i % pool_batches], lam, out=out)
+        st = out["stats"].cpu().numpy()
+        a, b = edge_updates(st, info.eloc[0], info.order)
+        eu_local += a
+        eu_global += b
+    pt = dec.phase_times()
+    dec.time_phases(False)
+    if pt["global_launches"] == 0:
+        raise SystemExit(f"the schedule {best} does not run the work-queue form, which the roofline pass times")
+    d2 = info.delta ** 2
+    kern = {}
+    for phase, eu, ms, nl in (("global", eu_global, pt["global_ms"], pt["global_launches"]),
+                              ("local", eu_local, pt["local_ms"], pt["local_launches"])):
+        gops = OPS_PER_EDGE_UPDATE * eu / (ms * 1e-3) / 1e9
+        kern[phase] = {"achieved": gops / 1000, "frac": gops / VALU_PEAK_GOPS, "ms_per_launch": ms / nl,
+                       "launches": nl, "ops_per_launch": OPS_PER_EDGE_UPDATE * eu / nl}
+    shots_per_launch = rl_reps * shots / pt["global_launches"]
+    g_bytes = global_kernel_bytes_per_shot(n, m, info.order, d2) * shots_per_launch
+    hbm_gbs = g_bytes / (kern["global"]["ms_per_launch"] * 1e-3) / 1e9
     if args.roofline_only:
-        print(json.dumps({"roofline_pass_ms": round(k_ms, 3)}), flush=True)
+        print(json.dumps({"roofline_pass": kern, "schedule": best}), flush=True)
         return
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
-        if rec.get("kernel_sha") == kernel_hash() and rec.get("shots") == shots:
+        if rec.get("kernel_sha") == kernel_hash() and rec.get("shots_per_launch") == shots_per_launch:
             traffic = rec.get("hbm_bytes_per_launch")
-    hbm_frac, valu_frac = hbm_gbs / HBM_PEAK_GBS, valu_gops / VALU_PEAK_GOPS
-    roof = {"bound": "alu", "achieved": round(valu_gops / 1000, 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
-            "unit": "TOP/s", "frac": round(valu_frac, 4), "traffic": traffic,
-            "kernel": "decode_kernel<6,9,64,0,false> (one launch decodes the batch)", "kernel_ms": round(k_ms, 3),
-            "hbm_achieved_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_frac, 5)}
+    form = {1: "compressed check state", 2: "one register per message"}.get(best.get("specialized"), "")
+    roof = {"bound": "alu", "achieved": round(kern["global"]["achieved"], 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
+            "unit": "TOP/s", "frac": round(kern["global"]["frac"], 4), "traffic": traffic,
+            "kernel": f"lead_spec_global_{best.get('specialized')} (Phases 2-3 compiled for the A5 code, {form}; "
+                      f"{shots_per_launch:.0f} shots per launch)",
+            "kernel_ms": round(kern["global"]["ms_per_launch"], 3),
+            "algorithmic_ops_per_launch": round(kern["global"]["ops_per_launch"]),
+            "hbm_algorithmic_bytes_per_launch": round(g_bytes),
+            "hbm_achieved_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 5),
+            "phase1_kernel": {"kernel": f"lead_spec_local_{best.get('specialized')}0 (Phase 1 work queue)",
+                              "kernel_ms": round(kern["local"]["ms_per_launch"], 3),
+                              "achieved": round(kern["local"]["achieved"], 3),
+                              "frac": round(kern["local"]["frac"], 4)}}
 
-    # ---- headline: autotuned schedule, each batch captured as a graph
-    dec.set_schedule()
-    best = dec.autotune(synd_pool[0], lam)
+    # ---- headline: each batch captured as a graph, replayed
     graphs = [P.Batch([(dec, synd_pool[b], lam, out, P.LEAD_PRIOR_PER_SHOT)]).capture()
               for b in range(pool_batches)]
     for i in range(args.warmup):
@@ -367,7 +413,8 @@ def main():
         "config": {"workload": "LEAD-BP full decode, A5 code n=1080 (Delta=6, [6,3] local codes), "
                                "bit-flip p=0.05, <=50 local + <=50 global min-sum rounds, beta=0.75, alpha=1",
                    "shots_per_step": shots,
-                   "form": "batched: captured graph of lead_decode with the autotuned schedule",
+                   "form": "batched: captured graph of lead_decode (kernels compiled for the code), "
+                           + ("schedule from --schedule" if args.schedule else "autotuned schedule"),
                    "schedule": best},
         "roofline": roof,
         "decode_stats": {"converged": round(float((st[:, 0] == 1).mean()), 4),

@@ -196,15 +196,33 @@ typedef struct {
                                      runs in a work-queue kernel first           */
     int32_t local_chunk;          /* queue items a wave takes at a time            */
     int32_t local_waves;          /* waves of the work-queue kernel                 */
-    int32_t specialized;          /* 1: the work-queue form (fused = 0) runs the
+    int32_t specialized;          /* the work-queue form (fused = 0) runs the
                                      kernels compiled for this code (see
-                                     lead_code_specialize; its own workgroup
-                                     shape, shots_per_workgroup unused); 0: the
-                                     precompiled kernels.  Reads back as 1 only
-                                     when those kernels are available.          */
+                                     lead_code_specialize; they pick their own
+                                     workgroup shape): 1 with the compressed
+                                     min-sum check state, 2 with one register
+                                     per message (views of at most 128 edges);
+                                     0: the precompiled kernels.  Reads back as
+                                     the form in use (a form that was not
+                                     compiled is replaced by the other). The
+                                     default is 2 where available.              */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);
+
+/* Device time per phase of the work-queue form (fused = 0).  While timing
+ * is on, lead_decode brackets each Phase 1 launch and each Phases 2-3 launch
+ * with HIP events on its stream (except while that stream is being captured
+ * into a graph).  lead_decoder_phase_times waits for the last recorded event
+ * and returns the milliseconds and launch counts summed since timing was
+ * last switched on; switching it on clears the sums. */
+typedef struct {
+    double local_ms;              /* Phase 1 (work-queue local BP kernel)        */
+    double global_ms;             /* Phases 2-3 (aggregation and global BP)      */
+    int64_t local_launches, global_launches;
+} lead_phase_times;
+lead_status lead_decoder_time_phases(lead_decoder *dec, int32_t enable);
+lead_status lead_decoder_phase_times(lead_decoder *dec, lead_phase_times *out);
 
 /* Times candidate schedules (fused / work-queue Phase 1, shots per
  * workgroup, queue chunk) on the caller's batch (at most 16384 of its shots)

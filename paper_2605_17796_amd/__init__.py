@@ -56,6 +56,11 @@ class lead_schedule(C.Structure):
                 ("local_waves", C.c_int32), ("specialized", C.c_int32)]
 
 
+class lead_phase_times(C.Structure):
+    _fields_ = [("local_ms", C.c_double), ("global_ms", C.c_double), ("local_launches", C.c_int64),
+                ("global_launches", C.c_int64)]
+
+
 class lead_batch_item(C.Structure):
     _fields_ = [("decoder", C.c_void_p), ("shots", C.c_int64), ("d_synd", C.c_void_p), ("synd_words", C.c_int64),
                 ("d_prior", C.c_void_p), ("mode", C.c_int32), ("d_ehat", C.c_void_p), ("ehat_words", C.c_int64),
@@ -78,7 +83,8 @@ STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max
 SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
            "lead_code_specialize", "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
            "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
-           "lead_decoder_get_schedule", "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
+           "lead_decoder_get_schedule", "lead_decoder_time_phases", "lead_decoder_phase_times",
+           "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
            "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_server_create", "lead_server_submit",
            "lead_server_poll", "lead_server_wait", "lead_server_result", "lead_server_get_stats",
            "lead_server_clock_ns", "lead_server_destroy"]
@@ -110,6 +116,8 @@ def lib():
         L.lead_decoder_set_params.argtypes = [P, C.POINTER(lead_params)]
         L.lead_decoder_set_schedule.argtypes = [P, C.POINTER(lead_schedule)]
         L.lead_decoder_get_schedule.argtypes = [P, C.POINTER(lead_schedule)]
+        L.lead_decoder_time_phases.argtypes = [P, I32]
+        L.lead_decoder_phase_times.argtypes = [P, C.POINTER(lead_phase_times)]
         L.lead_decoder_destroy.argtypes = [P]
         L.lead_decoder_destroy.restype = None
         dec_args = [P, I64, P, I64, P, I32, P, I64, P, P, P, P]
@@ -364,13 +372,25 @@ class Decoder:
         self.params = lead_params_make(**params)
         lead_decoder_set_params(self._h, self.params)
 
-    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=1):
+    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=2):
         lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves,
                                                          specialized))
 
     def get_schedule(self) -> dict:
         sc = lead_decoder_get_schedule(self._h)
         return {f: getattr(sc, f) for f, _ in lead_schedule._fields_}
+
+    def time_phases(self, enable=True):
+        """Switch per-phase device timing of the work-queue form on (clearing
+        the sums) or off."""
+        _check(lib().lead_decoder_time_phases(self._h, 1 if enable else 0))
+
+    def phase_times(self) -> dict:
+        """Summed device milliseconds and launch counts of Phase 1 and of
+        Phases 2-3 since timing was switched on."""
+        t = lead_phase_times()
+        _check(lib().lead_decoder_phase_times(self._h, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in lead_phase_times._fields_}
 
     def alloc_outputs(self, shots, device="cuda", post=True, lam=False, stats=True):
         import torch

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -51,6 +52,10 @@ struct lead_decoder {
     float *d_Lv = nullptr;
     uint32_t *d_vflag = nullptr;
     int64_t *d_counter = nullptr;
+    // phase timing: event triples (before Phase 1, between, after Phases 2-3)
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, 3>> tev;
+    lead_phase_times tsum{};
     // per-round state of lead_decode_plain (allocated on first use)
     float *d_S = nullptr, *d_cst = nullptr, *d_lamp = nullptr;
     int32_t *d_status = nullptr, *d_active = nullptr, *h_active = nullptr;
@@ -86,14 +91,27 @@ int default_spw(int N) { return std::max(1, 64 / N); }
 
 bool use_spec(const lead_decoder *d) { return d->spec && d->sched.specialized && !d->sched.fused; }
 
+// The specialised form a schedule asks for, or the one compiled when it
+// asks for the other (0: precompiled kernels).
+int spec_form(const lead_decoder *d, int want) {
+    if (!d->spec || want <= 0) return 0;
+    if (want == lead::jit::kExplicit && d->spec->has[1]) return lead::jit::kExplicit;
+    if (want == lead::jit::kCompressed && d->spec->has[0]) return lead::jit::kCompressed;
+    return d->spec->best_form();
+}
+
 // Split-path launches with the kernels compiled for the decoder's code.
-hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArgs w, hipStream_t s) {
+hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArgs w, hipStream_t s,
+                       std::array<hipEvent_t, 3> *ev) {
     const lead::jit::Kernels &k = *d->spec;
     hipError_t e = lead::launch_reset_counter(w.counter, s);
+    if (e == hipSuccess && ev) e = hipEventRecord((*ev)[0], s);
     if (e != hipSuccess) return e;
+    const int f = d->sched.specialized - 1;
     void *largs[] = {&a, &w};
-    e = hipModuleLaunchKernel(k.local[a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1, 64, 1,
-                              1, 0, s, largs, nullptr);
+    e = hipModuleLaunchKernel(k.local[f][a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1, 64,
+                              1, 1, 0, s, largs, nullptr);
+    if (e == hipSuccess && ev) e = hipEventRecord((*ev)[1], s);
     if (e != hipSuccess) return e;
     a.spw = k.spw;
     lead::SpecArgs x{d->d_pv, d->d_fown};
@@ -102,8 +120,10 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
                        sizeof(uint32_t) * (size_t)k.spw * ew32;
     const int64_t grid = (a.shots + k.spw - 1) / k.spw;
     void *gargs[] = {&a, &w, &x};
-    return hipModuleLaunchKernel(k.global, (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
-                                 nullptr);
+    e = hipModuleLaunchKernel(k.global[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
+                              nullptr);
+    if (e == hipSuccess && ev) e = hipEventRecord((*ev)[2], s);
+    return e;
 }
 
 lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode mode) {
@@ -114,7 +134,8 @@ lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode
     w.items = shots * d->N;
     w.chunk = d->sched.local_chunk;
     const int pm = mode == LEAD_PRIOR_PER_SHOT ? 0 : 1;
-    const int64_t per_cu = use_spec(d) ? d->spec->local_waves_per_cu[pm] : d->waves_per_cu[pm];
+    const int64_t per_cu =
+        use_spec(d) ? d->spec->local_waves_per_cu[d->sched.specialized - 1][pm] : d->waves_per_cu[pm];
     int64_t waves = d->sched.local_waves > 0 ? d->sched.local_waves : per_cu * d->cus;
     const int64_t need = (w.items + w.chunk - 1) / w.chunk;
     w.waves = (int32_t)std::max<int64_t>(1, std::min(waves, need));
@@ -170,13 +191,52 @@ lead_status check_decode_args(const lead_decoder *d, int64_t shots, const uint64
     return LEAD_OK;
 }
 
+// Events of one timed split launch, or nullptr when not timing (or while s
+// is being captured).
+std::array<hipEvent_t, 3> *timing_events(lead_decoder *d, hipStream_t s) {
+    if (!d->timing) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    std::array<hipEvent_t, 3> ev{};
+    for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) {
+            for (auto &y : ev)
+                if (y) (void)hipEventDestroy(y);
+            return nullptr;
+        }
+    d->tev.push_back(ev);
+    return &d->tev.back();
+}
+
+// Adds the recorded event triples to the sums and releases them.
+hipError_t drain_timing(lead_decoder *d) {
+    hipError_t e = hipSuccess;
+    for (auto &ev : d->tev) {
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        float a = 0.f, b = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
+        if (e == hipSuccess) {
+            d->tsum.local_ms += a;
+            d->tsum.global_ms += b;
+            d->tsum.local_launches++;
+            d->tsum.global_launches++;
+        }
+        for (auto &x : ev) (void)hipEventDestroy(x);
+    }
+    d->tev.clear();
+    return e;
+}
+
 // Launches the decode of `shots` shots (in workspace-sized chunks for the
 // split path) on stream s.
 hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
                          const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post,
                          float *lam, lead_shot_stats *stats, int stage, hipStream_t s) {
     const bool split = !d->sched.fused;
-    const int64_t step = split ? d->ws_shots : shots;
+    // equal chunks of at most ws_shots (no small tail launch)
+    const int64_t nchunks = split ? (shots + d->ws_shots - 1) / d->ws_shots : 1;
+    const int64_t step = (shots + nchunks - 1) / nchunks;
     for (int64_t off = 0; off < shots; off += step) {
         const int64_t cnt = std::min(step, shots - off);
         lead::DecodeArgs a = base_args(d);
@@ -192,7 +252,9 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         a.shots = cnt;
         a.stage = stage;
         const lead::LocalArgs w = local_args(d, cnt, mode);
-        hipError_t e = use_spec(d) ? launch_spec(d, a, w, s) : lead::launch_decode(d->D, d->r, a, w, split, s);
+        std::array<hipEvent_t, 3> *ev = split ? timing_events(d, s) : nullptr;
+        hipError_t e = use_spec(d) ? launch_spec(d, a, w, s, ev)
+                                   : lead::launch_decode(d->D, d->r, a, w, split, s, ev ? ev->data() : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -427,7 +489,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             if (e == hipSuccess)
                 e = hipMemcpy(d->d_fown, fown.data(), sizeof(uint64_t) * fown.size(), hipMemcpyHostToDevice);
         }
-        d->sched.specialized = d->spec ? 1 : 0;
+        d->sched.specialized = spec_form(d.get(), lead::jit::kExplicit);
     }
     if (e != hipSuccess) {
         (void)hipFree(d->d_view);
@@ -501,13 +563,30 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.fused = sc->fused ? 1 : 0;
     d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
     d->sched.local_waves = sc->local_waves;
-    d->sched.specialized = (sc->specialized && d->spec) ? 1 : 0;
+    d->sched.specialized = spec_form(d, sc->specialized);
     return LEAD_OK;
 }
 
 lead_status lead_decoder_get_schedule(const lead_decoder *d, lead_schedule *sc) {
     if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
     *sc = d->sched;
+    return LEAD_OK;
+}
+
+lead_status lead_decoder_time_phases(lead_decoder *d, int32_t enable) {
+    if (!d) return fail(LEAD_E_ARG, "decoder is NULL");
+    hipError_t e = drain_timing(d);
+    d->tsum = lead_phase_times{};
+    d->timing = enable != 0;
+    if (e != hipSuccess) return hip_fail(e, "phase timing");
+    return LEAD_OK;
+}
+
+lead_status lead_decoder_phase_times(lead_decoder *d, lead_phase_times *out) {
+    if (!d || !out) return fail(LEAD_E_ARG, "bad argument");
+    hipError_t e = drain_timing(d);
+    if (e != hipSuccess) return hip_fail(e, "phase timing");
+    *out = d->tsum;
     return LEAD_OK;
 }
 
@@ -520,6 +599,7 @@ void lead_decoder_destroy(lead_decoder *d) {
     (void)hipFree(d->d_counter);
     (void)hipFree(d->d_pv);
     (void)hipFree(d->d_fown);
+    (void)drain_timing(d);
     free_plain(d);
     delete d;
 }
@@ -713,8 +793,10 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
                     cand.push_back(lead_schedule{spw, fused, chunk, 0, 0});
                 }
         // the specialised split kernels fix their own workgroup shape
-        if (d->spec)
-            for (int chunk : {64, 256, 1024}) cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, 1});
+        for (int form : {lead::jit::kCompressed, lead::jit::kExplicit})
+            if (d->spec && d->spec->has[form - 1])
+                for (int chunk : {64, 256, 1024})
+                    cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, form});
         for (const lead_schedule &c : cand) {
             if (lead_decoder_set_schedule(d, &c) != LEAD_OK) continue;
             float ms_best = 1e30f;

@@ -85,13 +85,30 @@ std::string source(const Code &c, int t) {
     for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";
     o << "};\n    static constexpr int sigma[" << D2 << "] = {";
     for (int j = 0; j < D2; ++j) o << (j ? ", " : "") << tt.sigma[j];
-    o << "};\n};\n";
-    for (int pm = 0; pm < 2; ++pm)
-        o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_" << pm
-          << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ">(a, w); }\n";
-    o << "extern \"C\" __global__ void __launch_bounds__(" << wg
-      << ") lead_spec_global(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) "
-      << "{ lead_spec::global_body<LeadCode, " << wg << ", " << (wg == 64 ? "true" : "false") << ">(a, w, x); }\n";
+    o << "};\n";
+    // edge tables
+    std::ostringstream deg, base;
+    int e = 0;
+    for (int i = 0; i < tt.r; ++i) {
+        const int k = __builtin_popcountll(tt.mask[i]);
+        deg << (i ? ", " : "") << k;
+        base << (i ? ", " : "") << e;
+        e += k;
+    }
+    o << "    static constexpr int E = " << e << ";\n"
+      << "    static constexpr int deg[" << tt.r << "] = {" << deg.str() << "};\n"
+      << "    static constexpr int base[" << tt.r << "] = {" << base.str() << "};\n};\n";
+    for (int form = kCompressed; form <= kExplicit; ++form) {
+        if (form == kExplicit && tt.eloc > kExplicitMaxEdges) continue;
+        const char *xf = form == kExplicit ? "true" : "false";
+        for (int pm = 0; pm < 2; ++pm)
+            o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_" << form << pm
+              << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << xf
+              << ">(a, w); }\n";
+        o << "extern \"C\" __global__ void __launch_bounds__(" << wg << ") lead_spec_global_" << form
+          << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
+          << ", " << (wg == 64 ? "true" : "false") << ", " << xf << ">(a, w, x); }\n";
+    }
     return o.str();
 }
 
@@ -139,6 +156,7 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
             std::ostringstream name;
             name << dir << "/lead_spec_" << std::hex << std::hash<std::string>{}(src) << ".co";
             std::ofstream(name.str(), std::ios::binary).write(obj.data(), (std::streamsize)obj.size());
+            std::ofstream(name.str() + ".hip") << src;
         }
         std::lock_guard<std::mutex> lk(g_mu);
         g_objects.emplace(src, obj);
@@ -161,9 +179,20 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::strin
     if (!compile(src, obj, err)) return nullptr;
     auto k = std::make_shared<Kernels>();
     hipError_t e = hipModuleLoadData(&k->module, obj.data());
-    if (e == hipSuccess) e = hipModuleGetFunction(&k->local[0], k->module, "lead_spec_local_0");
-    if (e == hipSuccess) e = hipModuleGetFunction(&k->local[1], k->module, "lead_spec_local_1");
-    if (e == hipSuccess) e = hipModuleGetFunction(&k->global, k->module, "lead_spec_global");
+    for (int form = kCompressed; form <= kExplicit && e == hipSuccess; ++form) {
+        if (form == kExplicit && c.t[t].eloc > kExplicitMaxEdges) break;
+        const std::string f = std::to_string(form);
+        for (int pm = 0; pm < 2 && e == hipSuccess; ++pm)
+            e = hipModuleGetFunction(&k->local[form - 1][pm], k->module, ("lead_spec_local_" + f + std::to_string(pm)).c_str());
+        if (e == hipSuccess) e = hipModuleGetFunction(&k->global[form - 1], k->module, ("lead_spec_global_" + f).c_str());
+        if (e == hipSuccess) k->has[form - 1] = true;
+        for (int pm = 0; pm < 2 && e == hipSuccess; ++pm) {
+            int nb = 0;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->local[form - 1][pm], 64, 0) == hipSuccess &&
+                nb > 0)
+                k->local_waves_per_cu[form - 1][pm] = nb;
+        }
+    }
     if (e != hipSuccess) {
         err = std::string("module load: ") + hipGetErrorString(e);
         if (k->module) (void)hipModuleUnload(k->module);
@@ -172,11 +201,6 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::strin
     k->wg = workgroup_for(c.order);
     k->spw = k->wg / c.order;
     k->bperm = k->wg == 64;
-    for (int pm = 0; pm < 2; ++pm) {
-        int nb = 0;
-        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->local[pm], 64, 0) == hipSuccess && nb > 0)
-            k->local_waves_per_cu[pm] = nb;
-    }
     std::lock_guard<std::mutex> lk(g_mu);
     auto ins = g_modules.emplace(std::make_pair(device, src), k);
     return ins.first->second;   // another thread may have loaded it first

@@ -16,14 +16,24 @@
 namespace lead {
 namespace jit {
 
+// Check-state forms of the specialised kernels (lead_schedule.specialized).
+enum Form { kCompressed = 1, kExplicit = 2 };
+
+// Views with at most this many local edges also get the explicit-message
+// form (one VGPR per message).
+constexpr int kExplicitMaxEdges = 128;
+
 struct Kernels {
     hipModule_t module = nullptr;
-    hipFunction_t local[2] = {};   // Phase 1 queue kernel: per-shot prior, per-qubit prior
-    hipFunction_t global = nullptr;  // Phases 2-3
+    // [form - 1][prior mode]: Phase 1 queue kernel for per-shot / per-qubit priors
+    hipFunction_t local[2][2] = {};
+    hipFunction_t global[2] = {};  // [form - 1]: Phases 2-3
+    bool has[2] = {false, false};  // [form - 1]: compiled
     int wg = 0;                    // workgroup size of `global`
     int spw = 0;                   // shots per workgroup of `global`
     bool bperm = false;            // partner values exchanged within the wave
-    int local_waves_per_cu[2] = {4, 4};
+    int local_waves_per_cu[2][2] = {{4, 4}, {4, 4}};
+    int best_form() const { return has[1] ? kExplicit : kCompressed; }
 };
 
 // Source text of the kernels for check type t of code c; empty when the code

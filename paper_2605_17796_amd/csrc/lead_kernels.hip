@@ -47,8 +47,9 @@ struct CheckState {
 // and replaces each check state by the min-sum state of the new messages
 //   m_{c->j} = beta (-1)^{s_c} prod_{j' != j} sgn(mu_{j'}) min_{j' != j} |mu_{j'}|.
 // Returns whether the hard decisions [S_j < 0] satisfy every check, and sets
-// `same` when every new check state equals the previous one bit for bit (the
-// message state is then a fixed point of the iteration).
+// `same` when every new message equals the previous one bit for bit (the
+// messages are then a fixed point of the iteration: the next variable sums
+// equal the current ones, and so on).
 template <int WG, int RMAX>
 __device__ __forceinline__ bool check_pass(const DecodeArgs &a, const float *bl, uint64_t sv,
                                            CheckState<RMAX> &st, bool &same) {
@@ -80,8 +81,11 @@ __device__ __forceinline__ bool check_pass(const DecodeArgs &a, const float *bl,
             const uint32_t all = (uint32_t)((1ull << k) - 1ull);
             const uint32_t nq = flip ? (sg ^ all) : sg;
             const float b1 = a.beta * n1, b2 = a.beta * n2;
-            same = same && nq == st.q[c] && nam == st.am[c] && __float_as_uint(b1) == __float_as_uint(st.m1[c]) &&
-                   __float_as_uint(b2) == __float_as_uint(st.m2[c]);
+            // every outgoing message unchanged (the position of the smallest
+            // matters only when the two magnitudes differ)
+            same = same && nq == st.q[c] && __float_as_uint(b1) == __float_as_uint(st.m1[c]) &&
+                   __float_as_uint(b2) == __float_as_uint(st.m2[c]) &&
+                   (nam == st.am[c] || __float_as_uint(b1) == __float_as_uint(b2));
             st.q[c] = nq;
             st.m1[c] = b1;
             st.m2[c] = b2;
@@ -714,7 +718,7 @@ hipError_t launch_round_d(int wg, const RoundArgs &ra, hipStream_t s) {
 }
 
 template <int D, int RMAX, int WG>
-hipError_t launch_decode_t(const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s) {
+hipError_t launch_decode_t(const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s, hipEvent_t *ev) {
     const size_t lds = decode_lds_bytes(D, WG, a.spw, a.n);
     const int64_t grid = (a.shots + a.spw - 1) / a.spw;
     const bool pm0 = a.prior_mode == LEAD_PRIOR_PER_SHOT;
@@ -722,11 +726,14 @@ hipError_t launch_decode_t(const DecodeArgs &a, const LocalArgs &w, bool split, 
         hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, w.counter);
         const int waves = w.waves;
         const size_t llds = sizeof(float) * D * D * 64;
+        if (ev) (void)hipEventRecord(ev[0], s);
         if (pm0)
             hipLaunchKernelGGL((local_kernel<D, RMAX, 0>), dim3(waves), dim3(64), llds, s, a, w);
         else
             hipLaunchKernelGGL((local_kernel<D, RMAX, 1>), dim3(waves), dim3(64), llds, s, a, w);
+        if (ev) (void)hipEventRecord(ev[1], s);
         hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 0, true>), dim3((unsigned)grid), dim3(WG), lds, s, a, w);
+        if (ev) (void)hipEventRecord(ev[2], s);
     } else if (pm0) {
         hipLaunchKernelGGL((decode_kernel<D, RMAX, WG, 0, false>), dim3((unsigned)grid), dim3(WG), lds, s, a, w);
     } else {
@@ -736,12 +743,13 @@ hipError_t launch_decode_t(const DecodeArgs &a, const LocalArgs &w, bool split, 
 }
 
 template <int D, int RMAX>
-hipError_t launch_decode_d(int wg, const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s) {
+hipError_t launch_decode_d(int wg, const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s,
+                           hipEvent_t *ev) {
     switch (wg) {
-        case 64: return launch_decode_t<D, RMAX, 64>(a, w, split, s);
-        case 128: return launch_decode_t<D, RMAX, 128>(a, w, split, s);
-        case 192: return launch_decode_t<D, RMAX, 192>(a, w, split, s);
-        case 256: return launch_decode_t<D, RMAX, 256>(a, w, split, s);
+        case 64: return launch_decode_t<D, RMAX, 64>(a, w, split, s, ev);
+        case 128: return launch_decode_t<D, RMAX, 128>(a, w, split, s, ev);
+        case 192: return launch_decode_t<D, RMAX, 192>(a, w, split, s, ev);
+        case 256: return launch_decode_t<D, RMAX, 256>(a, w, split, s, ev);
         default: return hipErrorInvalidValue;
     }
 }
@@ -787,14 +795,15 @@ bool kernel_supported(int D, int r) {
     }
 }
 
-hipError_t launch_decode(int D, int, const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s) {
+hipError_t launch_decode(int D, int, const DecodeArgs &a, const LocalArgs &w, bool split, hipStream_t s,
+                         hipEvent_t *ev) {
     if (a.shots <= 0) return hipSuccess;
     const int wg = workgroup_size(a.N, a.spw);
     switch (D) {
-        case 3: return launch_decode_d<3, 4>(wg, a, w, split, s);
-        case 4: return launch_decode_d<4, 9>(wg, a, w, split, s);
-        case 6: return launch_decode_d<6, 9>(wg, a, w, split, s);
-        case 8: return launch_decode_d<8, 16>(wg, a, w, split, s);
+        case 3: return launch_decode_d<3, 4>(wg, a, w, split, s, ev);
+        case 4: return launch_decode_d<4, 9>(wg, a, w, split, s, ev);
+        case 6: return launch_decode_d<6, 9>(wg, a, w, split, s, ev);
+        case 8: return launch_decode_d<8, 16>(wg, a, w, split, s, ev);
         default: return hipErrorInvalidValue;
     }
 }

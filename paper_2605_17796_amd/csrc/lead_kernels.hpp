@@ -36,8 +36,10 @@ struct RoundArgs {
 size_t decode_lds_bytes(int D, int wg, int spw, int n);
 int workgroup_size(int N, int spw);
 
+// ev (split path only, may be null): events recorded before the Phase 1
+// kernel, between the two kernels, and after the Phases 2-3 kernel.
 hipError_t launch_decode(int D, int rmax_needed, const DecodeArgs &a, const LocalArgs &w, bool split,
-                         hipStream_t s);
+                         hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_round(int D, int rmax_needed, const RoundArgs &a, hipStream_t s);
 hipError_t launch_reset_counter(int64_t *counter, hipStream_t s);
 hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s);

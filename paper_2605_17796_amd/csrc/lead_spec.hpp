@@ -8,7 +8,15 @@
 //   C::sigma[D*D]   the local position of the other occurrence of the qubit
 //                   at position j (the same map for every view of a Cayley
 //                   complex),
-//   C::NFIX         the number of fixed points of sigma.
+//   C::NFIX         the number of fixed points of sigma,
+//   C::E, C::deg[R], C::base[R]
+//                   the local edges (numbered check by check, positions
+//                   ascending within a check): their count, and per check
+//                   the degree and the number of its first edge.
+// Every loop below runs over compile-time bounds and indexes arrays with
+// loop-constant subscripts only (through tables, not constexpr functions
+// with loops of their own), so that each index folds to an immediate once
+// the loops are unrolled and no array is left in scratch memory.
 // Every edge loop then unrolls completely: edge positions, register indices
 // and sign-bit positions are immediates, and the variable sums S_j of a view
 // stay in VGPRs in both phases of BP (the precompiled kernels keep them in
@@ -29,65 +37,195 @@ using lead::DecodeArgs;
 using lead::LocalArgs;
 using lead::SpecArgs;
 
-template <int R>
-struct State {
+// Min-sum check update of check c from mu_{j->c} = clamp(S_j - m_{c->j}):
+// the smallest and second smallest |mu| (n1, n2), the position of the
+// smallest (nam), the sign bit of every mu at bit 31 (us, for the first deg
+// edges) and the parity of those signs (ps).  Returns the parity of the sign
+// bits of S over the check (the hard-decision test).
+template <class C, class Msg>
+__device__ __forceinline__ uint32_t check_scan(int c, const float (&S)[C::D * C::D], float clampv, const Msg &msg,
+                                               float &n1, float &n2, uint32_t &nam, uint32_t (&us)[C::D * C::D],
+                                               uint32_t &ps) {
+    constexpr int D2 = C::D * C::D;
+    uint32_t par = 0u;
+    n1 = kBig;
+    n2 = kBig;
+    nam = 0u;
+    ps = 0u;
+    uint32_t k = 0u;
+#pragma unroll
+    for (int j = 0; j < D2; ++j) {
+        if ((C::mask[c] >> j) & 1ull) {
+            par ^= __float_as_uint(S[j]);
+            const float mu = clampf(S[j] - msg(k), clampv);
+            us[k] = __float_as_uint(mu) & kSign;
+            ps ^= us[k];
+            const float ab = fabsf(mu);
+            n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
+            const bool lt = ab < n1;
+            nam = lt ? k : nam;
+            n1 = lt ? ab : n1;
+            ++k;
+        }
+    }
+    return par;
+}
+
+// Compressed check state (the precompiled kernels' form): per check
+// beta * n1, beta * n2, the position of the smallest and the sign bit of
+// every outgoing message; messages are rebuilt from it when needed.
+template <class C>
+struct Compressed {
+    static constexpr int R = C::R;
     float m1[R], m2[R];
     uint32_t am[R], q[R];
     __device__ __forceinline__ void clear() {
 #pragma unroll
         for (int c = 0; c < R; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
     }
+    // Check update of every check of the view from the sums S of the
+    // previous iteration.  Returns whether [S_j < 0] satisfies every check;
+    // `same` tells whether every check state is unchanged bit for bit.
+    __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
+                                          bool &same) {
+        bool sat = true;
+        // bits that differ between the old and the new state, accumulated
+        // as an integer so that each comparison is done as soon as its
+        // operands exist (a chain of boolean ands lets the compiler keep
+        // every old value live until the end)
+        uint32_t diff = 0u;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            float n1, n2;
+            uint32_t nam, ps, us[C::D * C::D];
+            const uint32_t par = check_scan<C>(
+                c, S, clampv, [&](uint32_t k) { return msg_of(m1[c], m2[c], am[c], q[c], k); }, n1, n2, nam, us, ps);
+            const uint32_t sc = (uint32_t)(sv >> c) & 1u;
+            sat = sat && ((par >> 31) == sc);
+            // bit k of the new sign word: sign of mu_k xor the parity of all
+            // signs xor the syndrome bit
+            const uint32_t flip = (ps >> 31) ^ sc;
+            uint32_t nq = 0u;
+#pragma unroll
+            for (int k = 0; k < C::D * C::D; ++k)
+                if (k < C::deg[c]) nq |= ((us[k] >> 31) ^ flip) << k;
+            const float b1 = beta * n1, b2 = beta * n2;
+            // every outgoing message unchanged (the position of the smallest
+            // matters only when the two magnitudes differ)
+            uint32_t b1u = __float_as_uint(b1), b2u = __float_as_uint(b2);
+            const uint32_t dterm = (nq ^ q[c]) | (b1u ^ __float_as_uint(m1[c])) | (b2u ^ __float_as_uint(m2[c])) |
+                                   (b1u == b2u ? 0u : nam ^ am[c]);
+            diff |= dterm;
+            // the new state is written from operands that depend on the
+            // comparison (see Explicit::check)
+            asm("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam) : "v"(dterm));
+            q[c] = nq;
+            m1[c] = __uint_as_float(b1u);
+            m2[c] = __uint_as_float(b2u);
+            am[c] = nam;
+            asm volatile("" : "+v"(diff));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        same = diff == 0u;
+        return sat;
+    }
+    // S_j += m_{c->j} for every edge, checks in order.
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            uint32_t k = 0u;
+#pragma unroll
+            for (int j = 0; j < C::D * C::D; ++j)
+                if ((C::mask[c] >> j) & 1ull) S[j] += msg_of(m1[c], m2[c], am[c], q[c], k++);
+        }
+    }
 };
 
-// Check update of every check of the view from the sums S of the previous
-// iteration: mu_{j->c} = clamp(S_j - m_{c->j}) and the new min-sum state
-// (beta * smallest |mu|, beta * second smallest, position of the smallest,
-// outgoing signs).  Returns whether [S_j < 0] satisfies every check; `same`
-// tells whether every state is unchanged bit for bit.
+// Explicit messages: every m_{c->j} of the view in a register (edges
+// numbered check by check, positions ascending within a check).  The
+// messages are the compressed form's, bit for bit: magnitude beta * n2 on the
+// edge of the smallest |mu| and beta * n1 elsewhere, sign = sign(mu_k) xor
+// parity of all signs xor syndrome bit.  The edge of the smallest needs no
+// tracking: it is an edge with |mu_k| == n1, and where several edges tie at
+// n1, n2 == n1 and every choice gives the same message.
 template <class C>
-__device__ __forceinline__ bool check_pass(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
-                                           State<C::R> &st, bool &same) {
-    constexpr int D2 = C::D * C::D;
-    bool sat = true;
-    same = true;
+struct Explicit {
+    static constexpr int R = C::R, E = C::E;
+    float m[E];
+    __device__ __forceinline__ void clear() {
 #pragma unroll
-    for (int c = 0; c < C::R; ++c) {
-        float n1 = kBig, n2 = kBig;
-        uint32_t nam = 0u, sg = 0u, par = 0u, k = 0u;
-#pragma unroll
-        for (int j = 0; j < D2; ++j) {
-            if ((C::mask[c] >> j) & 1ull) {
-                par ^= __float_as_uint(S[j]);
-                const float mu = clampf(S[j] - msg_of(st.m1[c], st.m2[c], st.am[c], st.q[c], k), clampv);
-                const float ab = fabsf(mu);
-                sg |= signbit_of(mu) << k;
-                n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
-                const bool lt = ab < n1;
-                nam = lt ? k : nam;
-                n1 = lt ? ab : n1;
-                ++k;
-            }
-        }
-        const uint32_t sc = (uint32_t)(sv >> c) & 1u;
-        sat = sat && ((par >> 31) == sc);
-        const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
-        const uint32_t all = (uint32_t)((1ull << k) - 1ull);
-        const uint32_t nq = flip ? (sg ^ all) : sg;
-        const float b1 = beta * n1, b2 = beta * n2;
-        same = same && nq == st.q[c] && nam == st.am[c] && __float_as_uint(b1) == __float_as_uint(st.m1[c]) &&
-               __float_as_uint(b2) == __float_as_uint(st.m2[c]);
-        st.q[c] = nq;
-        st.m1[c] = b1;
-        st.m2[c] = b2;
-        st.am[c] = nam;
-        // one check at a time: the scheduler would otherwise hoist the mu of
-        // every edge of the view ahead of the serial min chains, keeping them
-        // all live (VALU results feed the next instruction without stalls,
-        // so that buys nothing)
-        __builtin_amdgcn_sched_barrier(0);
+        for (int e = 0; e < E; ++e) m[e] = 0.f;
     }
-    return sat;
-}
+    __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
+                                          bool &same) {
+        constexpr int D2 = C::D * C::D;
+        bool sat = true;
+        uint32_t diff = 0u;   // see Compressed::check
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int b = C::base[c];
+#pragma unroll
+            for (int k = 0; k < D2; ++k)
+                if (k < C::deg[c]) asm volatile("" : "+v"(m[b + k]));
+            float n1 = kBig, n2 = kBig, mu[D2];
+            uint32_t par = 0u, ps = 0u, k = 0u;
+#pragma unroll
+            for (int j = 0; j < D2; ++j) {
+                if ((C::mask[c] >> j) & 1ull) {
+                    par ^= __float_as_uint(S[j]);
+                    mu[k] = clampf(S[j] - m[b + k], clampv);
+                    ps ^= __float_as_uint(mu[k]);
+                    n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[k]));
+                    n1 = fminf(n1, fabsf(mu[k]));
+                    ++k;
+                }
+            }
+            const uint32_t sc = (uint32_t)(sv >> c) & 1u;
+            sat = sat && ((par >> 31) == sc);
+            const uint32_t px = (ps ^ (sc << 31)) & kSign;
+            uint32_t b1 = __float_as_uint(beta * n1), b2 = __float_as_uint(beta * n2);
+            asm("" : "+v"(b1), "+v"(b2));   // keep the two products (not a product per edge)
+#pragma unroll
+            for (int e = 0; e < D2; ++e)
+                if (e < C::deg[c]) {
+                    uint32_t mag = fabsf(mu[e]) == n1 ? b2 : b1;
+                    const uint32_t sgn = (__float_as_uint(mu[e]) & kSign) ^ px;
+                    // compare first, then form the new message from operands
+                    // that depend on the comparison: the old message is then
+                    // dead when the new one is written and both can share a
+                    // register (no copy at the loop back-edge)
+                    const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + e]);
+                    diff |= dterm;
+                    asm("" : "+v"(mag) : "v"(dterm));
+                    m[b + e] = __uint_as_float(mag | sgn);
+                }
+            asm volatile("" : "+v"(diff));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        same = diff == 0u;
+        return sat;
+    }
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            uint32_t k = 0u;
+#pragma unroll
+            for (int j = 0; j < C::D * C::D; ++j)
+                if ((C::mask[c] >> j) & 1ull) S[j] += m[C::base[c] + k++];
+        }
+    }
+};
+
+template <class C, bool X>
+struct Pick {
+    using type = Compressed<C>;
+};
+template <class C>
+struct Pick<C, true> {
+    using type = Explicit<C>;
+};
+template <class C, bool X>
+using CheckState = typename Pick<C, X>::type;
 
 // Whether [S_j < 0] satisfies every check of the view.
 template <class C>
@@ -105,23 +243,6 @@ __device__ __forceinline__ bool parity(const float (&S)[C::D * C::D], uint64_t s
     return sat;
 }
 
-// S_j += m_{c->j} for every edge, checks in order.
-template <class C>
-__device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], const State<C::R> &st) {
-    constexpr int D2 = C::D * C::D;
-#pragma unroll
-    for (int c = 0; c < C::R; ++c) {
-        uint32_t k = 0u;
-#pragma unroll
-        for (int j = 0; j < D2; ++j) {
-            if ((C::mask[c] >> j) & 1ull) {
-                S[j] += msg_of(st.m1[c], st.m2[c], st.am[c], st.q[c], k);
-                ++k;
-            }
-        }
-    }
-}
-
 // r syndrome bits of vertex v: bits v*r .. v*r + r - 1 of the shot's row.
 __device__ __forceinline__ uint64_t local_syndrome(const DecodeArgs &a, int64_t shot, int v) {
     const uint64_t *row = a.synd + shot * a.synd_words;
@@ -137,7 +258,14 @@ __device__ __forceinline__ uint64_t local_syndrome(const DecodeArgs &a, int64_t 
 // ends.  Stopping rules and outputs are those of the precompiled local
 // kernel: Lv[item][j] = clamp(S_j), vflag[item] = iterations | converged << 16
 // | fixed point << 17.
-template <class C, int PM>
+//
+// Every step of the loop is executed by all lanes, with or without an item
+// (the variable update S^{t-1} = lambda + sum of messages, then the check
+// update of iteration t; a fresh item has all-zero messages, so its first
+// variable update gives S^0 = lambda exactly).  Only the output stores are
+// divergent.  Updating S or the check states under a divergent branch would
+// make the compiler keep the old and the new copies of them live at once.
+template <class C, int PM, bool X>
 __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs &w) {
     constexpr int D2 = C::D * C::D;
     constexpr int NL = PM == 0 ? 1 : D2;
@@ -152,9 +280,7 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     float S[D2];
 #pragma unroll
     for (int j = 0; j < NL; ++j) lam[j] = 0.f;
-#pragma unroll
-    for (int j = 0; j < D2; ++j) S[j] = 0.f;
-    State<C::R> st;
+    CheckState<C, X> st;
     st.clear();
     for (;;) {
         uint64_t need = __ballot(!valid);
@@ -187,8 +313,6 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
                     for (int j = 0; j < NL; ++j) lam[j] = a.prior[base + a.view[v * D2 + j]] + 0.f;
                 }
                 st.clear();
-#pragma unroll
-                for (int j = 0; j < D2; ++j) S[j] = lam[PM == 0 ? 0 : j];
                 t = 1;
             }
             const int64_t taken = __popcll(need) < avail ? __popcll(need) : avail;
@@ -196,48 +320,62 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
             need = __ballot(!valid);
         }
         if (__ballot(valid) == 0ull) break;
-        if (valid) {
-            bool same;
-            const bool sat = check_pass<C>(S, sv, a.beta, a.clampv, st, same);
-            int conv = 0, it = 0, fixed = 0;
-            bool fin = false;
-            if (t > a.Tl) {
-                conv = sat ? 1 : 0;
-                it = a.Tl;
-                fin = true;
-            } else if (t > 1 && sat && a.early_exit) {
-                conv = 1;
-                it = t - 1;
-                fin = true;
-            } else if (t > 1 && same && a.fixed_stop) {
-                conv = sat ? 1 : 0;
-                it = a.Tl;
-                fixed = 1;
-                fin = true;
-            }
-            if (fin) {
-                float *out = w.Lv + item * D2;
 #pragma unroll
-                for (int j = 0; j < D2; ++j) out[j] = clampf(S[j], a.clampv);
-                w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
-                valid = false;
-            } else {
-#pragma unroll
-                for (int j = 0; j < D2; ++j) S[j] = lam[PM == 0 ? 0 : j];
-                accumulate<C>(S, st);
-                ++t;
-            }
+        for (int j = 0; j < D2; ++j) S[j] = lam[PM == 0 ? 0 : j];
+        st.accumulate(S);
+        bool same;
+        const bool sat = st.check(S, sv, a.beta, a.clampv, same);
+        int conv = 0, it = 0, fixed = 0;
+        bool fin = false;
+        if (t > a.Tl) {
+            conv = sat ? 1 : 0;
+            it = a.Tl;
+            fin = true;
+        } else if (t > 1 && sat && a.early_exit) {
+            conv = 1;
+            it = t - 1;
+            fin = true;
+        } else if (t > 1 && same && a.fixed_stop) {
+            conv = sat ? 1 : 0;
+            it = a.Tl;
+            fixed = 1;
+            fin = true;
         }
+        if (valid && fin) {
+            float *out = w.Lv + item * D2;
+#pragma unroll
+            for (int j = 0; j < D2; ++j) out[j] = clampf(S[j], a.clampv);
+            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
+            valid = false;
+        }
+        ++t;
     }
 }
 
 // Per-shot LDS flags (the precompiled kernel's layout).
 enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5, SF_CHG = 6, SF_NFIX = 7 };
 
-// Value of X at the other occurrence of local position J: lane `addr` (a
-// byte address) holds it at position sigma[J].  BPERM: the partner lane is
-// in the same wave and is read with ds_bpermute; otherwise X has been stored
-// to LDS as buf[j][lane].
+// Partner addresses: for local position j, the byte address of the lane
+// that holds the other occurrence of the qubit (lane * 4).  Within one wave
+// (BPERM) they fit in 8 bits, four per register; across waves in 16 bits.
+template <bool BPERM>
+struct PartnerAddr {
+    static constexpr int PER = BPERM ? 4 : 2, BITS = 32 / PER;
+    static constexpr uint32_t MASK = BPERM ? 0xffu : 0xffffu;
+    template <int D2>
+    static constexpr int words() { return (D2 + PER - 1) / PER; }
+};
+
+template <bool BPERM, int J, int NW>
+__device__ __forceinline__ uint32_t partner_addr(const uint32_t (&pa)[NW]) {
+    using A = PartnerAddr<BPERM>;
+    return (pa[J / A::PER] >> ((J % A::PER) * A::BITS)) & A::MASK;
+}
+
+// Value of X at the other occurrence of local position J: lane `addr` holds
+// it at position sigma[J].  BPERM: the partner lane is in the same wave and
+// is read with ds_bpermute; otherwise X has been stored to LDS as
+// buf[j][lane].
 template <class C, int WG, bool BPERM, int J>
 __device__ __forceinline__ float partner(const float (&X)[C::D * C::D], const float *buf, uint32_t addr) {
     if (BPERM)
@@ -245,12 +383,12 @@ __device__ __forceinline__ float partner(const float (&X)[C::D * C::D], const fl
     return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(buf) + C::sigma[J] * WG * 4 + addr);
 }
 
-template <class C, int WG, bool BPERM, int J = 0>
+template <class C, int WG, bool BPERM, int NW, int J = 0>
 __device__ __forceinline__ void partner_all(const float (&X)[C::D * C::D], float (&Y)[C::D * C::D],
-                                            const float *buf, const uint32_t (&pa)[(C::D * C::D + 1) / 2]) {
+                                            const float *buf, const uint32_t (&pa)[NW]) {
     if constexpr (J < C::D * C::D) {
-        Y[J] = partner<C, WG, BPERM, J>(X, buf, (pa[J >> 1] >> ((J & 1) * 16)) & 0xffffu);
-        partner_all<C, WG, BPERM, J + 1>(X, Y, buf, pa);
+        Y[J] = partner<C, WG, BPERM, J>(X, buf, partner_addr<BPERM, J>(pa));
+        partner_all<C, WG, BPERM, NW, J + 1>(X, Y, buf, pa);
     }
 }
 
@@ -270,10 +408,11 @@ __device__ __forceinline__ void store_all(const float (&X)[C::D * C::D], float *
 // view forms its partial sum P_j (lambda' on owned positions, then its
 // checks' messages in check order) and S_j = P_j + P_j' of the other
 // occurrence.
-template <class C, int WG, bool BPERM>
+template <class C, int WG, bool BPERM, bool X>
 __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x) {
     constexpr int D2 = C::D * C::D;
-    constexpr int NP = (D2 + 1) / 2;
+    constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
+    constexpr int NW = PartnerAddr<BPERM>::template words<D2>();  // words of the packed addresses
     extern __shared__ float lds[];
     float *buf = lds;
     int *shf = reinterpret_cast<int *>(lds + (BPERM ? 0 : D2 * WG));
@@ -288,7 +427,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     for (int i = tid; i < a.spw * ew32; i += WG) ebits[i] = 0u;
 
     float S[D2];
-    uint32_t pa[NP];
+    uint32_t pa[NW];
     uint64_t sv = 0, fown = 0;
     int it_v = 0, conv_v = 0, fixed_v = 0;
     if (live) {
@@ -302,17 +441,21 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         conv_v = (int)((f >> 16) & 1u);
         fixed_v = (int)((f >> 17) & 1u);
         const uint32_t base = (uint32_t)(sl * a.N);
+        using A = PartnerAddr<BPERM>;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const uint32_t p = x.pv[v * NP + k];
-            pa[k] = ((base + (p & 0xffffu)) * 4u) | (((base + (p >> 16)) * 4u) << 16);
+        for (int k = 0; k < NW; ++k) pa[k] = 0u;
+#pragma unroll
+        for (int j = 0; j < D2; ++j) {
+            const uint32_t vp = (x.pv[v * NP + j / 2] >> (16 * (j & 1))) & 0xffffu;
+            pa[j / A::PER] |= ((base + vp) * 4u) << ((j % A::PER) * A::BITS);
         }
         if (C::NFIX) fown = x.fown[v];
     } else {
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] = 0.f;
+        using A = PartnerAddr<BPERM>;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) pa[k] = (uint32_t)tid * 4u * 0x10001u;
+        for (int k = 0; k < NW; ++k) pa[k] = BPERM ? (uint32_t)tid * 4u * 0x01010101u : (uint32_t)tid * 4u * 0x10001u;
     }
     __syncthreads();
     if (live) {
@@ -330,7 +473,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     {
         float Lp[D2];
         store_all<C, WG, BPERM>(S, buf);
-        partner_all<C, WG, BPERM>(S, Lp, buf, pa);
+        partner_all<C, WG, BPERM, NW>(S, Lp, buf, pa);
 #pragma unroll
         for (int j = 0; j < D2; ++j) lam[j] = aggregate_llr(clampf(S[j], a.clampv), clampf(Lp[j], a.clampv), a.alpha, a.clampv);
     }
@@ -365,14 +508,15 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     };
 #pragma unroll
     for (int j = 0; j < D2; ++j) S[j] = lam[j];
-    State<C::R> st;
+    CheckState<C, X> st;
     st.clear();
     if (!BPERM) __syncthreads();
     bool done = !live;
     int itg = 0, gconv = 0, gfix = 0;
     for (int t = 1; t <= a.Tg; ++t) {
-        bool sat = true, same = true;
-        if (!done) sat = check_pass<C>(S, sv, a.beta, a.clampv, st, same);
+        // computed by every lane (see local_body); done lanes discard it
+        bool same;
+        const bool sat = st.check(S, sv, a.beta, a.clampv, same);
         if (!done && !sat) shf[sl * 8 + (t & 1)] = 1;
         if (!done && !same) shf[sl * 8 + SF_CHG] = t;
         __syncthreads();
@@ -396,10 +540,10 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         // partial sums of this view, then S_j = P_j + P of the other occurrence
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] = owned(j) ? lam[j] : 0.f;
-        accumulate<C>(S, st);
+        st.accumulate(S);
         float Q[D2];
         store_all<C, WG, BPERM>(S, buf);
-        partner_all<C, WG, BPERM>(S, Q, buf, pa);
+        partner_all<C, WG, BPERM, NW>(S, Q, buf, pa);
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] += Q[j];
     }

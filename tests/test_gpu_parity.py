@@ -159,7 +159,8 @@ def test_zero_syndrome_and_ragged_batches():
 @pytest.mark.parametrize("sched", [dict(shots_per_workgroup=2), dict(shots_per_workgroup=3),
                                    dict(shots_per_workgroup=4), dict(fused=1), dict(fused=1, shots_per_workgroup=4),
                                    dict(local_chunk=64), dict(local_chunk=4096, local_waves=7),
-                                   dict(specialized=0), dict(specialized=0, local_chunk=64)])
+                                   dict(specialized=0), dict(specialized=0, local_chunk=64),
+                                   dict(specialized=1)])
 def test_schedule_does_not_change_results(sched):
     """Launch geometry (shots per workgroup, Phase 1 fused into the per-shot
     kernel or run from a work queue, queue chunk, wave count) leaves every

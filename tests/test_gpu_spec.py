@@ -31,16 +31,19 @@ def _priors(mode, ps, n, seed):
     return channel_llr(rng.uniform(0.02, 0.08, (ps.shape[0], n))).astype(np.float32)
 
 
-def _both(dec, synd, prior, mode):
-    dec.set_schedule(specialized=1)
-    assert dec.get_schedule()["specialized"] == 1
-    a = run_gpu(dec, synd, prior, mode, lam=True)
-    dec.set_schedule(specialized=0)
-    assert dec.get_schedule()["specialized"] == 0
-    b = run_gpu(dec, synd, prior, mode, lam=True)
+def _forms(dec, synd, prior, mode, eloc):
+    """Outputs under every kernel form: specialised with one register per
+    message (views of at most 128 edges), specialised with the compressed
+    check state, precompiled split, precompiled fused."""
+    runs = {}
+    for form in (2, 1, 0):
+        dec.set_schedule(specialized=form)
+        want = form if form != 2 or eloc <= 128 else 1
+        assert dec.get_schedule()["specialized"] == want
+        runs[form] = run_gpu(dec, synd, prior, mode, lam=True)
     dec.set_schedule(fused=1)
-    c = run_gpu(dec, synd, prior, mode, lam=True)
-    return a, b, c
+    runs["fused"] = run_gpu(dec, synd, prior, mode, lam=True)
+    return runs
 
 
 CASES = [("T", 0, 0, {}), ("T", 1, 2, {}), ("M", 0, 0, {}), ("M", 1, 0, {}), ("M", 0, 1, {}), ("M", 0, 2, {}),
@@ -59,12 +62,13 @@ def test_specialised_equals_precompiled(name, t, mode, params):
     shots = {"T": 777, "M": 301, "L": 41, "appendix": 257}[name]
     synd, ps = _inputs(dec, oc, shots, seed=900 + shots + 7 * t + mode, t=t)
     prior = _priors(mode, ps, oc.n, seed=31 + mode)
-    a, b, c = _both(dec, synd, prior, mode)
+    runs = _forms(dec, synd, prior, mode, code.info.eloc[t])
     keys = ("lam", "stats") if params.get("stage") == 1 else ("ehat", "post", "lam", "stats")
-    for k in keys:
-        assert np.array_equal(a[k], b[k]), (k, "specialised vs precompiled split")
-        assert np.array_equal(a[k], c[k]), (k, "specialised vs precompiled fused")
-    log(f"[spec] {name} t={t} mode={mode} {params}: {shots} shots bit-identical "
+    a = runs[2]
+    for form in (1, 0, "fused"):
+        for k in keys:
+            assert np.array_equal(a[k], runs[form][k]), (k, form)
+    log(f"[spec] {name} t={t} mode={mode} {params}: {shots} shots bit-identical over every kernel form "
         f"(converged {a['stats'][:, 0].mean():.3f})")
 
 
@@ -81,7 +85,34 @@ def test_specialised_ragged_and_chunked():
         part = run_gpu(dec, synd[:n_sub], prior[:n_sub], 0, lam=True)
         for k in ("ehat", "post", "lam", "stats"):
             assert np.array_equal(part[k], full[k][:n_sub]), (n_sub, k)
-    dec.set_schedule(specialized=0)
-    ref = run_gpu(dec, synd, prior, 0, lam=True)
-    for k in ("ehat", "post", "lam", "stats"):
-        assert np.array_equal(full[k], ref[k]), k
+    for form in (1, 0):
+        dec.set_schedule(specialized=form)
+        ref = run_gpu(dec, synd, prior, 0, lam=True)
+        for k in ("ehat", "post", "lam", "stats"):
+            assert np.array_equal(full[k], ref[k]), (form, k)
+
+
+def test_phase_timing():
+    """Per-phase device time of the work-queue form: one pair of timed
+    launches per workspace chunk, none while a graph is being captured."""
+    import paper_2605_17796_amd as P
+    torch = torch_dev()
+    spec, oc = code_pair("T")
+    code, dec = gpu_decoder(spec, max_shots=40000)
+    synd, ps = _inputs(dec, oc, 40000, seed=8, t=0)
+    s = torch.from_numpy(synd.view(np.int64)).cuda()
+    prior = torch.from_numpy(channel_llr(ps).astype(np.float32)).cuda()
+    dec.time_phases(True)
+    out = dec.decode(s, prior)
+    pt = dec.phase_times()
+    assert pt["local_launches"] == 2 and pt["global_launches"] == 2      # 32768 + 7232 shots
+    assert pt["local_ms"] > 0 and pt["global_ms"] > 0
+    g = P.Batch([(dec, s, prior, out, P.LEAD_PRIOR_PER_SHOT)]).capture()
+    g.replay()
+    torch.cuda.synchronize()
+    assert dec.phase_times()["global_launches"] == 2
+    dec.time_phases(False)
+    dec.decode(s, prior, out=out)
+    torch.cuda.synchronize()
+    assert dec.phase_times()["global_launches"] == 0
+    log(f"[timing] T 40000 shots: {pt}")
