@@ -298,16 +298,16 @@ def main():
     if args.roofline_only:
         print(json.dumps({"roofline_pass": kern, "schedule": best}), flush=True)
         return
+    gname = f"lead_spec_global_{best.get('specialized')}"
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("kernel_sha") == kernel_hash() and rec.get("shots_per_launch") == shots_per_launch:
-            traffic = rec.get("hbm_bytes_per_launch")
+            traffic = rec.get("kernels", {}).get(gname, {}).get("hbm_bytes_per_launch")
     form = {1: "compressed check state", 2: "one register per message"}.get(best.get("specialized"), "")
     roof = {"bound": "alu", "achieved": round(kern["global"]["achieved"], 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
             "unit": "TOP/s", "frac": round(kern["global"]["frac"], 4), "traffic": traffic,
-            "kernel": f"lead_spec_global_{best.get('specialized')} (Phases 2-3 compiled for the A5 code, {form}; "
-                      f"{shots_per_launch:.0f} shots per launch)",
+            "kernel": f"{gname} (Phases 2-3 compiled for the A5 code, {form}; {shots_per_launch:.0f} shots per launch)",
             "kernel_ms": round(kern["global"]["ms_per_launch"], 3),
             "algorithmic_ops_per_launch": round(kern["global"]["ops_per_launch"]),
             "hbm_algorithmic_bytes_per_launch": round(g_bytes),
