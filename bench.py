@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-baseline-decoder", action="store_true",
+                    help="skip the global-BP-only (single-stage) comparison leg")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the eager pass used for the roofline, with --schedule (for profilers)")
     ap.add_argument("--schedule", type=str, default=None,
@@ -340,6 +342,28 @@ def main():
                          "and a host-visible convergence count, finalize launch",
                  "batched_over_plain": round(value * pw / shots, 3)}
 
+    # ---- the single-stage baseline: global BP alone with the channel priors
+    #      on the same batches (stage GLOBAL)
+    base_leg = None
+    if not args.no_baseline_decoder:
+        gdec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
+                         ms_scale=0.75, alpha=1.0, stage=2)
+        gout = gdec.alloc_outputs(shots)
+        gdec.decode(synd_pool[0], lam, out=gout)
+        gw, _ = timed(torch, lambda i: gdec.decode(synd_pool[i % pool_batches], lam, out=gout), 2)
+        gst = gout["stats"].cpu().numpy()     # batch 1 of the pool
+        dec.decode(synd_pool[1], lam, out=out)
+        lst = out["stats"].cpu().numpy()
+        r_over_m = info.r[0] / m
+        base_leg = {
+            "global_bp_only_shots_per_s": round(2 * shots / gw, 1),
+            "global_bp_only": {"converged": round(float(gst[:, 0].mean()), 4),
+                               "mean_iterations": round(float(gst[:, 1].mean()), 2)},
+            "lead": {"converged": round(float(lst[:, 0].mean()), 4),
+                     "mean_iterations_I": round(float((lst[:, 1] + lst[:, 2] / info.order * r_over_m).mean()), 2),
+                     "mean_global_iterations": round(float(lst[:, 1].mean()), 2)},
+            "note": "same 10^5 syndromes; I = I_g + mean local iterations x r/m (the paper's iteration measure)"}
+
     # ---- mixed-code batch (D6 / A5 / PSL(2,7)): one graph launch vs plain
     mixed = None
     decs_named = {"M": (code, dec)}
@@ -421,6 +445,7 @@ def main():
                          "mean_global_iters": round(float(st[:, 1].mean()), 2),
                          "mean_local_iters": round(float(st[:, 2].mean() / info.order), 2)},
         "plain_form": plain,
+        "single_stage_baseline": base_leg,
         "mixed_batch": mixed,
         "served": served,
         "cpu_baseline": cpu,

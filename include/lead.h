@@ -57,7 +57,10 @@ typedef enum {
 
 typedef enum { LEAD_CHECK_Z = 0, LEAD_CHECK_X = 1 } lead_check_type;
 typedef enum { LEAD_PRIOR_PER_SHOT = 0, LEAD_PRIOR_SHARED = 1, LEAD_PRIOR_FULL = 2 } lead_prior_mode;
-typedef enum { LEAD_STAGE_FULL = 0, LEAD_STAGE_LOCAL = 1 } lead_stage;
+/* FULL: Algorithm 1 (Phases 1-3).  LOCAL: Phases 1-2 only (lambda' out).
+ * GLOBAL: global BP alone with the channel priors as its prior, no local
+ * phase: the standard single-stage decoder LEAD is compared against. */
+typedef enum { LEAD_STAGE_FULL = 0, LEAD_STAGE_LOCAL = 1, LEAD_STAGE_GLOBAL = 2 } lead_stage;
 
 typedef struct lead_code lead_code;
 typedef struct lead_decoder lead_decoder;
@@ -120,7 +123,7 @@ typedef struct {
     int32_t max_iter_global;  /* global BP iteration cap, 1..1000                 */
     float llr_clamp;          /* |mu|, |L|, |lambda'| clamped to this, > 0        */
     int32_t early_exit;       /* 1: stop a BP run at the first H e = s            */
-    int32_t stage;            /* lead_stage: FULL, or LOCAL (Phases 1-2 only)      */
+    int32_t stage;            /* lead_stage: FULL, LOCAL or GLOBAL                */
     int32_t boost;            /* 1: Phase-1 confidence boost (Alg. 1)             */
     int32_t fixed_point_stop; /* 1: end a BP run whose messages reproduce
                                  themselves bit for bit (every later iteration
@@ -153,18 +156,23 @@ lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const 
 lead_status lead_decoder_set_params(lead_decoder *dec, const lead_params *params);
 void lead_decoder_destroy(lead_decoder *dec);
 
-/* LEAD decode of `shots` syndromes in one fused launch: every shot runs
- * Phase 1 (local BP on each vertex view), Phase 2 (aggregation) and, in the
- * FULL stage, Phase 3 (global BP) inside one workgroup, with all messages
- * kept on chip.
+/* LEAD decode of `shots` syndromes: Phase 1 (local BP on each vertex view),
+ * Phase 2 (aggregation) and, in the FULL stage, Phase 3 (global BP).  The
+ * schedule (lead_decoder_set_schedule) picks the kernels: by default a
+ * work-queue kernel for Phase 1 and a per-shot kernel for Phases 2-3, both
+ * compiled for the decoder's code; or one fused per-shot kernel.  Every
+ * schedule gives bit-identical outputs.  In the GLOBAL stage only the global
+ * BP runs (on the fused per-shot kernel), with prior lambda' = the channel
+ * LLR of each qubit.
  *   d_synd      shots x synd_words packed syndromes, synd_words >= ceil(m/64)
  *   d_prior     channel LLRs ln((1-p)/p): PER_SHOT: shots floats; SHARED: n
  *               floats; FULL: shots x n floats
  *   d_ehat      shots x ehat_words packed estimates (FULL stage; may be NULL
  *               in the LOCAL stage), ehat_words >= ceil(n/64)
  *   d_post      shots x n posterior LLRs of global BP, or NULL
- *   d_prior_llr shots x n regularised priors lambda' (Phase 2 output), or NULL;
- *               required in the LOCAL stage
+ *   d_prior_llr shots x n regularised priors lambda' (Phase 2 output; the
+ *               channel LLRs in the GLOBAL stage), or NULL; required in the
+ *               LOCAL stage
  *   d_stats     shots lead_shot_stats, or NULL
  * A shot that does not converge is not an error: its estimate and
  * posteriors are still written and stats.converged is 0. */

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "liblead.so")
 LEAD_OK = 0
 LEAD_CHECK_Z, LEAD_CHECK_X = 0, 1
 LEAD_PRIOR_PER_SHOT, LEAD_PRIOR_SHARED, LEAD_PRIOR_FULL = 0, 1, 2
-LEAD_STAGE_FULL, LEAD_STAGE_LOCAL = 0, 1
+LEAD_STAGE_FULL, LEAD_STAGE_LOCAL, LEAD_STAGE_GLOBAL = 0, 1, 2
 STATUS_NAMES = {0: "LEAD_OK", -1: "LEAD_E_ARG", -2: "LEAD_E_GROUP", -3: "LEAD_E_SYMMETRY", -4: "LEAD_E_TNC",
                 -5: "LEAD_E_LOCALCODE", -6: "LEAD_E_NOMEM", -7: "LEAD_E_DEVICE", -8: "LEAD_E_CAPACITY",
                 -9: "LEAD_E_UNSUPPORTED"}

@@ -81,7 +81,8 @@ lead_status check_params(const lead_params *p) {
     if (p->max_iter_local < 1 || p->max_iter_local > 1000 || p->max_iter_global < 1 || p->max_iter_global > 1000)
         return fail(LEAD_E_ARG, "iteration caps must be in 1..1000");
     if (!(p->llr_clamp > 0.f) || !std::isfinite(p->llr_clamp)) return fail(LEAD_E_ARG, "llr_clamp must be > 0");
-    if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL) return fail(LEAD_E_ARG, "bad stage");
+    if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL && p->stage != LEAD_STAGE_GLOBAL)
+        return fail(LEAD_E_ARG, "bad stage");
     return LEAD_OK;
 }
 
@@ -233,7 +234,9 @@ hipError_t drain_timing(lead_decoder *d) {
 hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
                          const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post,
                          float *lam, lead_shot_stats *stats, int stage, hipStream_t s) {
-    const bool split = !d->sched.fused;
+    // global BP alone runs on the fused per-shot kernel (there is no Phase 1)
+    const bool gonly = d->params.stage == LEAD_STAGE_GLOBAL;
+    const bool split = !d->sched.fused && !gonly;
     // equal chunks of at most ws_shots (no small tail launch)
     const int64_t nchunks = split ? (shots + d->ws_shots - 1) / d->ws_shots : 1;
     const int64_t step = (shots + nchunks - 1) / nchunks;
@@ -250,10 +253,11 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         a.lam_out = lam ? lam + off * d->n : nullptr;
         a.stats = stats ? stats + off : nullptr;
         a.shots = cnt;
-        a.stage = stage;
+        a.stage = stage == LEAD_STAGE_LOCAL ? LEAD_STAGE_LOCAL : LEAD_STAGE_FULL;
+        a.global_only = gonly ? 1 : 0;
         const lead::LocalArgs w = local_args(d, cnt, mode);
         std::array<hipEvent_t, 3> *ev = split ? timing_events(d, s) : nullptr;
-        hipError_t e = use_spec(d) ? launch_spec(d, a, w, s, ev)
+        hipError_t e = split && use_spec(d) ? launch_spec(d, a, w, s, ev)
                                    : lead::launch_decode(d->D, d->r, a, w, split, s, ev ? ev->data() : nullptr);
         if (e != hipSuccess) return e;
     }

@@ -38,6 +38,7 @@ struct DecodeArgs {
     int32_t prior_mode, spw, N, n, r, own_max;
     float alpha, beta, clampv;
     int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
+    int32_t global_only;       // no Phase 1; lambda' = the channel prior
     uint64_t mask[kMaxChecks];
 };
 

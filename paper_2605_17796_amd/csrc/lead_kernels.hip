@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
             conv_v = (int)((f >> 16) & 1u);
             fixed_v = (int)((f >> 17) & 1u);
         }
-    } else {
+    } else if (!a.global_only) {
         float lamv[PM == 0 ? 1 : D2];
 #pragma unroll
         for (int j = 0; j < (PM == 0 ? 1 : D2); ++j) lamv[j] = 0.f;
@@ -349,6 +349,9 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
         if (L.live)
             for (int t = 1;; ++t)
                 if (local_step<D, RMAX, WG, PM>(a, bl, sv, lamv, st, t, conv_v, it_v, fixed_v)) break;
+    } else {
+#pragma unroll
+        for (int j = 0; j < D2; ++j) bl[j * WG] = 0.f;   // no local posteriors
     }
     convf[tid] = conv_v;
     __syncthreads();
@@ -380,6 +383,11 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
                 if (convf[ob % WG] && Lb < 0.f) Lb = fminf(Lb, 0.f);
             }
             lamp[k] = aggregate_llr(La, Lb, a.alpha, a.clampv);
+            if (!SPLIT && a.global_only) {
+                // global BP alone: the channel prior of the qubit
+                const int64_t base = a.prior_mode == LEAD_PRIOR_FULL ? L.shot * a.n : 0;
+                lamp[k] = (PM == 0 ? a.prior[L.shot] : a.prior[base + a.view[L.v * D2 + (ent[k] & 0xff)]]) + 0.f;
+            }
         }
     }
     if (a.lam_out) {

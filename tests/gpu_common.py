@@ -131,3 +131,26 @@ def bitflip_inputs(oc, shots, p, seed, t=0):
     s = oc.syndrome(e, t)
     lam = np.full(shots, float(channel_llr(p)), dtype=np.float32)
     return e, s, lam
+
+
+def oracle_global_conditioned(oc, synd, prior, t=0, k=K_PERTURB, **kw):
+    """Oracle global BP alone (channel priors, no local phase) with the
+    per-shot `ill` flag from K perturbed runs, in the layout compare()
+    expects (stats columns converged, iterations)."""
+    ref = oc.global_bp(synd, prior, t=t, p=oracle_params(**kw))
+    n = oc.n
+    e_ref = unpack_bits(ref["ehat"], n)
+    near0 = np.abs(ref["post"]) < LLR_TOL
+    ill = np.zeros(synd.shape[0], dtype=bool)
+    spread = np.zeros(synd.shape[0])
+    for i in range(k):
+        pk = oc.global_bp(synd, prior, t=t, p=oracle_params(perturb=PERTURB, perturb_seed=i + 1, **kw))
+        d = np.abs(pk["post"] - ref["post"]).max(axis=1)
+        spread = np.maximum(spread, d)
+        ill |= d > ILL_TOL
+        ill |= np.any((unpack_bits(pk["ehat"], n) != e_ref) & ~near0, axis=1)
+        ill |= np.any(pk["stats"] != ref["stats"], axis=1)
+    ref["ill"] = ill
+    ref["spread"] = spread
+    ref["margin"] = np.full(synd.shape[0], np.inf)
+    return ref

@@ -381,3 +381,54 @@ def test_iteration_count_is_first_success(name):
             _, _, cb, _ = o.bp(H, s, lam, it - 1, o.params(early_exit=0))
             assert not cb
     assert any(t > 3 for t in seen), seen
+
+
+# ---------------------------------------------------------------------------
+# global BP alone (the single-stage baseline: channel priors, no local phase)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_global_bp_first_iteration_is_scaled_single_check_min_cost(name):
+    """One global min-sum iteration on H_t: L_i = lam_i + beta * sum over the
+    checks c of i of the exact min-cost message of check c alone (brute force
+    over the check's support), for random syndromes and per-qubit priors."""
+    from oracle import oracle as o
+    _, oc = code_pair(name)
+    rng = np.random.default_rng(5)
+    for t in (0, 1):
+        H = oc.H(t)
+        m, n = H.shape
+        s = rng.integers(0, 2, size=(2, m)).astype(np.uint8)
+        lam = rng.uniform(-1.0, 4.0, size=(2, n))
+        synd = pack_bits(s)
+        out = oc.global_bp(synd, lam, t=t, p=o.params(ms_scale=0.75, early_exit=0, max_iter_global=1))
+        for shot in range(2):
+            want = lam[shot].copy()
+            for c in range(m):
+                sup = list(np.nonzero(H[c])[0])
+                w = len(sup)
+                pats = ((np.arange(1 << w)[:, None] >> np.arange(w)) & 1)
+                good = (pats.sum(axis=1) % 2) == s[shot, c]
+                for k, j in enumerate(sup):
+                    others = [q for q in range(w) if q != k]
+                    cost = pats[:, others] @ lam[shot, [sup[q] for q in others]]
+                    want[j] += 0.75 * (cost[good & (pats[:, k] == 1)].min() - cost[good & (pats[:, k] == 0)].min())
+            assert np.allclose(out["post"][shot], np.clip(want, -30, 30), atol=1e-12)
+            assert np.array_equal(unpack_bits(out["ehat"][shot:shot + 1], n)[0], (out["post"][shot] < 0).astype(np.uint8))
+            assert out["stats"][shot, 1] == 1
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_global_bp_zero_syndrome_closed_form(name):
+    """s = 0 with a uniform prior lam > 0: global BP converges after one
+    iteration with L_i = lam (1 + beta d_i), d_i the column weight of H_t."""
+    from oracle import oracle as o
+    _, oc = code_pair(name)
+    lam = float(channel_llr(0.05))
+    for t in (0, 1):
+        deg = oc.H(t).sum(axis=0)
+        s = np.zeros((2, (oc.m(t) + 63) // 64), dtype=np.uint64)
+        out = oc.global_bp(s, np.full(2, lam), t=t, p=o.params(ms_scale=0.75, max_iter_global=9))
+        assert np.array_equal(out["stats"], [[1, 1], [1, 1]])
+        assert np.allclose(out["post"], lam * (1 + 0.75 * deg), rtol=1e-12)
+        assert not out["ehat"].any()
