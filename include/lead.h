@@ -61,6 +61,9 @@ typedef enum { LEAD_PRIOR_PER_SHOT = 0, LEAD_PRIOR_SHARED = 1, LEAD_PRIOR_FULL =
  * GLOBAL: global BP alone with the channel priors as its prior, no local
  * phase: the standard single-stage decoder LEAD is compared against. */
 typedef enum { LEAD_STAGE_FULL = 0, LEAD_STAGE_LOCAL = 1, LEAD_STAGE_GLOBAL = 2 } lead_stage;
+/* BP flavour of both stages: flooding min-sum with scale ms_scale, or
+ * flooding sum-product (no scale). */
+typedef enum { LEAD_BP_MINSUM = 0, LEAD_BP_SUMPRODUCT = 1 } lead_bp;
 
 typedef struct lead_code lead_code;
 typedef struct lead_decoder lead_decoder;
@@ -104,8 +107,9 @@ lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_
 /* Compiles, for gfx950 and without touching a GPU, the decoding kernels
  * specialised to the local check structure of type t (its check masks and
  * the local position map of the two occurrences of a qubit, Sec. II-B), and
- * caches the code object for the rest of the process; lead_decoder_create
- * does the same on first use and then loads it.  LEAD_E_UNSUPPORTED (with the
+ * caches the code objects for the rest of the process (the min-sum forms,
+ * and the sum-product form where views have at most 128 local edges);
+ * lead_decoder_create does the same on first use and then loads them.  LEAD_E_UNSUPPORTED (with the
  * reason in lead_last_error) when the code has no position map or the
  * run-time compiler is unavailable; decoders then use the precompiled
  * kernels, with identical results. */
@@ -130,6 +134,12 @@ typedef struct {
                                  would repeat it); results and reported
                                  iteration counts are identical to running to
                                  the cap                                       */
+    int32_t bp;               /* lead_bp.  Sum-product runs on the kernels
+                                 compiled for the code with one register per
+                                 message (views of at most 128 local edges),
+                                 in lead_decode, batches and the server;
+                                 lead_decode_plain and stage GLOBAL are
+                                 min-sum only (LEAD_E_UNSUPPORTED)            */
 } lead_params;
 
 /* Per-shot statistics (32 bytes). */
@@ -204,7 +214,8 @@ typedef struct {
                                      runs in a work-queue kernel first           */
     int32_t local_chunk;          /* queue items a wave takes at a time            */
     int32_t local_waves;          /* waves of the work-queue kernel                 */
-    int32_t specialized;          /* the work-queue form (fused = 0) runs the
+    int32_t specialized;          /* (3 with sum-product, whatever is asked)
+                                     the work-queue form (fused = 0) runs the
                                      kernels compiled for this code (see
                                      lead_code_specialize; they pick their own
                                      workgroup shape): 1 with the compressed
@@ -213,7 +224,7 @@ typedef struct {
                                      0: the precompiled kernels.  Reads back as
                                      the form in use (a form that was not
                                      compiled is replaced by the other). The
-                                     default is 2 where available.              */
+                                     default is 1.                              */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);

@@ -23,6 +23,7 @@ LEAD_OK = 0
 LEAD_CHECK_Z, LEAD_CHECK_X = 0, 1
 LEAD_PRIOR_PER_SHOT, LEAD_PRIOR_SHARED, LEAD_PRIOR_FULL = 0, 1, 2
 LEAD_STAGE_FULL, LEAD_STAGE_LOCAL, LEAD_STAGE_GLOBAL = 0, 1, 2
+LEAD_BP_MINSUM, LEAD_BP_SUMPRODUCT = 0, 1
 STATUS_NAMES = {0: "LEAD_OK", -1: "LEAD_E_ARG", -2: "LEAD_E_GROUP", -3: "LEAD_E_SYMMETRY", -4: "LEAD_E_TNC",
                 -5: "LEAD_E_LOCALCODE", -6: "LEAD_E_NOMEM", -7: "LEAD_E_DEVICE", -8: "LEAD_E_CAPACITY",
                 -9: "LEAD_E_UNSUPPORTED"}
@@ -48,7 +49,7 @@ class lead_code_info(C.Structure):
 class lead_params(C.Structure):
     _fields_ = [("alpha", C.c_float), ("ms_scale", C.c_float), ("max_iter_local", C.c_int32),
                 ("max_iter_global", C.c_int32), ("llr_clamp", C.c_float), ("early_exit", C.c_int32),
-                ("stage", C.c_int32), ("boost", C.c_int32), ("fixed_point_stop", C.c_int32)]
+                ("stage", C.c_int32), ("boost", C.c_int32), ("fixed_point_stop", C.c_int32), ("bp", C.c_int32)]
 
 
 class lead_schedule(C.Structure):
@@ -205,9 +206,9 @@ def lead_code_destroy(code):
 
 
 def lead_params_make(alpha=1.0, ms_scale=0.75, max_iter_local=32, max_iter_global=32, llr_clamp=30.0,
-                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1, fixed_point_stop=1) -> lead_params:
+                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1, fixed_point_stop=1, bp=LEAD_BP_MINSUM) -> lead_params:
     return lead_params(alpha, ms_scale, max_iter_local, max_iter_global, llr_clamp, early_exit, stage, boost,
-                       fixed_point_stop)
+                       fixed_point_stop, bp)
 
 
 def lead_decoder_create(code, t, params: lead_params, max_shots: int):
@@ -372,7 +373,7 @@ class Decoder:
         self.params = lead_params_make(**params)
         lead_decoder_set_params(self._h, self.params)
 
-    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=2):
+    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=1):
         lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves,
                                                          specialized))
 

@@ -83,6 +83,9 @@ lead_status check_params(const lead_params *p) {
     if (!(p->llr_clamp > 0.f) || !std::isfinite(p->llr_clamp)) return fail(LEAD_E_ARG, "llr_clamp must be > 0");
     if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL && p->stage != LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_ARG, "bad stage");
+    if (p->bp != LEAD_BP_MINSUM && p->bp != LEAD_BP_SUMPRODUCT) return fail(LEAD_E_ARG, "bad bp");
+    if (p->bp == LEAD_BP_SUMPRODUCT && p->stage == LEAD_STAGE_GLOBAL)
+        return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL runs min-sum only");
     return LEAD_OK;
 }
 
@@ -92,9 +95,12 @@ int default_spw(int N) { return std::max(1, 64 / N); }
 
 bool use_spec(const lead_decoder *d) { return d->spec && d->sched.specialized && !d->sched.fused; }
 
+bool sum_product(const lead_decoder *d) { return d->params.bp == LEAD_BP_SUMPRODUCT; }
+
 // The specialised form a schedule asks for, or the one compiled when it
-// asks for the other (0: precompiled kernels).
+// asks for the other (0: precompiled kernels).  Sum-product has one form.
 int spec_form(const lead_decoder *d, int want) {
+    if (sum_product(d)) return d->spec && d->spec->has[2] ? lead::jit::kSumProduct : 0;
     if (!d->spec || want <= 0) return 0;
     if (want == lead::jit::kExplicit && d->spec->has[1]) return lead::jit::kExplicit;
     if (want == lead::jit::kCompressed && d->spec->has[0]) return lead::jit::kCompressed;
@@ -407,6 +413,9 @@ lead_status lead_code_specialize(const lead_code *code, lead_check_type t) {
     std::vector<char> obj;
     std::string err;
     if (!lead::jit::compile(src, obj, err)) return fail(LEAD_E_UNSUPPORTED, err);
+    // the sum-product form, where a view is small enough for it
+    const std::string sp = lead::jit::source(code->c, t, true);
+    if (!sp.empty() && !lead::jit::compile(sp, obj, err)) return fail(LEAD_E_UNSUPPORTED, err);
     return LEAD_OK;
 }
 
@@ -482,7 +491,8 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
     // when they cannot be built)
     if (e == hipSuccess) {
         std::string jerr;
-        d->spec = lead::jit::load(c, t, d->device, jerr);
+        d->spec = lead::jit::load(c, t, d->device, sum_product(d.get()), jerr);
+        if (!d->spec && sum_product(d.get())) e = hipErrorNotSupported;
         if (d->spec) {
             std::vector<uint32_t> pv;
             std::vector<uint64_t> fown;
@@ -493,7 +503,15 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             if (e == hipSuccess)
                 e = hipMemcpy(d->d_fown, fown.data(), sizeof(uint64_t) * fown.size(), hipMemcpyHostToDevice);
         }
-        d->sched.specialized = spec_form(d.get(), lead::jit::kExplicit);
+        d->sched.specialized = spec_form(d.get(), lead::jit::kCompressed);
+        if (e == hipErrorNotSupported) {
+            (void)hipFree(d->d_view);
+            (void)hipFree(d->d_own);
+            (void)hipFree(d->d_Lv);
+            (void)hipFree(d->d_vflag);
+            (void)hipFree(d->d_counter);
+            return fail(LEAD_E_UNSUPPORTED, "sum-product: " + jerr);
+        }
     }
     if (e != hipSuccess) {
         (void)hipFree(d->d_view);
@@ -549,6 +567,18 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
     if (!d) return fail(LEAD_E_ARG, "decoder is NULL");
     lead_status st = check_params(params);
     if (st != LEAD_OK) return st;
+    if (params->bp != d->params.bp) {
+        // the other BP flavour needs the other set of compiled kernels
+        std::string jerr;
+        auto k = lead::jit::load(*d->code, d->type, d->device, params->bp == LEAD_BP_SUMPRODUCT, jerr);
+        if (!k && params->bp == LEAD_BP_SUMPRODUCT) return fail(LEAD_E_UNSUPPORTED, "sum-product: " + jerr);
+        if (k && !d->d_pv) return fail(LEAD_E_UNSUPPORTED, "no partner tables");
+        d->spec = k;
+        d->params = *params;
+        d->sched.specialized = spec_form(d, lead::jit::kCompressed);
+        if (sum_product(d)) d->sched.fused = 0;
+        return LEAD_OK;
+    }
     d->params = *params;
     return LEAD_OK;
 }
@@ -568,6 +598,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
     d->sched.local_waves = sc->local_waves;
     d->sched.specialized = spec_form(d, sc->specialized);
+    if (sum_product(d)) d->sched.fused = 0;   // sum-product runs the work-queue form only
     return LEAD_OK;
 }
 
@@ -626,6 +657,7 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
                               float *post, float *lam, lead_shot_stats *stats, void *stream) {
     lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
     if (st != LEAD_OK || shots == 0) return st;
+    if (sum_product(d)) return fail(LEAD_E_UNSUPPORTED, "the plain form runs min-sum only");
     if (d->params.stage == LEAD_STAGE_LOCAL)
         return lead_decode(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream);
     hipStream_t s = (hipStream_t)stream;
@@ -788,7 +820,7 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
     float best_ms = 1e30f;
     if (e == hipSuccess) {
         std::vector<lead_schedule> cand;
-        for (int fused = 0; fused < 2; ++fused)
+        for (int fused = 0; fused < 2 && !sum_product(d); ++fused)
             for (int spw : {1, 2, 4, 8, 16, 21})
                 for (int chunk : {64, 256, 1024}) {
                     if (fused && chunk != 256) continue;
@@ -797,7 +829,7 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
                     cand.push_back(lead_schedule{spw, fused, chunk, 0, 0});
                 }
         // the specialised split kernels fix their own workgroup shape
-        for (int form : {lead::jit::kCompressed, lead::jit::kExplicit})
+        for (int form : {lead::jit::kCompressed, lead::jit::kExplicit, lead::jit::kSumProduct})
             if (d->spec && d->spec->has[form - 1])
                 for (int chunk : {64, 256, 1024})
                     cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, form});

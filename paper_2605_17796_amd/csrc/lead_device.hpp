@@ -49,4 +49,38 @@ __device__ __forceinline__ float aggregate_llr(float La, float Lb, float alpha, 
     return clampf(l2 * 0.693147180559945309f, clampv) + 0.f;
 }
 
+// Sum-product in the log domain (Gallager's phi):
+//   phi(x) = ln((e^x + 1) / (e^x - 1)) = -ln tanh(x / 2) = log1p(2 / expm1(x)),  x >= 0,
+// its own inverse, with phi(0) = +inf and phi(+inf) = 0; the check message
+// 2 atanh(prod_j' tanh(mu_j' / 2)) has magnitude phi(sum_j' phi(|mu_j'|)).
+// expm1 and log1p take a short series where the plain form would cancel, so
+// phi keeps full relative precision at both ends (phi(30) ~ 1.9e-13 and
+// phi(1e-6) ~ 14.5).
+__device__ __forceinline__ float expm1_nonneg(float x) {
+    // x (1 + x/2 (1 + x/3 (... (1 + x/8)))) below 1/2: truncation below 1e-8 relative
+    float t = __builtin_fmaf(x, 0.125f, 1.f);
+    t = __builtin_fmaf(x * (1.f / 7.f), t, 1.f);
+    t = __builtin_fmaf(x * (1.f / 6.f), t, 1.f);
+    t = __builtin_fmaf(x * 0.2f, t, 1.f);
+    t = __builtin_fmaf(x * 0.25f, t, 1.f);
+    t = __builtin_fmaf(x * (1.f / 3.f), t, 1.f);
+    t = __builtin_fmaf(x * 0.5f, t, 1.f);
+    const float series = x * t;
+    return x < 0.5f ? series : exp_hw(x) - 1.f;
+}
+
+__device__ __forceinline__ float log1p_nonneg(float y) {
+    // y - y^2/2 + y^3/3 - y^4/4 + y^5/5 below 1/32: truncation below 1e-9 relative
+    float t = __builtin_fmaf(y, 0.2f, -0.25f);
+    t = __builtin_fmaf(y, t, 1.f / 3.f);
+    t = __builtin_fmaf(y, t, -0.5f);
+    t = __builtin_fmaf(y, t, 1.f);
+    const float series = y * t;
+    return y < 0.03125f ? series : __builtin_amdgcn_logf(1.f + y) * 0.693147180559945309f;
+}
+
+__device__ __forceinline__ float phi(float x) {
+    return log1p_nonneg(2.f * __builtin_amdgcn_rcpf(expm1_nonneg(x)));
+}
+
 }  // namespace lead_dev

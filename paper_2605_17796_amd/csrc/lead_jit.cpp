@@ -70,10 +70,11 @@ int workgroup_for(int order) { return ((order + 63) / 64) * 64; }
 
 }  // namespace
 
-std::string source(const Code &c, int t) {
+std::string source(const Code &c, int t, bool sp) {
     const TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
     if (tt.sigma.empty() || (int)tt.sigma.size() != D2) return std::string();
+    if (sp && tt.eloc > kExplicitMaxEdges) return std::string();
     int nfix = 0;
     for (int j = 0; j < D2; ++j) nfix += tt.sigma[j] == j;
     const int wg = workgroup_for(c.order);
@@ -98,16 +99,16 @@ std::string source(const Code &c, int t) {
     o << "    static constexpr int E = " << e << ";\n"
       << "    static constexpr int deg[" << tt.r << "] = {" << deg.str() << "};\n"
       << "    static constexpr int base[" << tt.r << "] = {" << base.str() << "};\n};\n";
-    for (int form = kCompressed; form <= kExplicit; ++form) {
-        if (form == kExplicit && tt.eloc > kExplicitMaxEdges) continue;
-        const char *xf = form == kExplicit ? "true" : "false";
+    for (int form = kCompressed; form <= kSumProduct; ++form) {
+        if ((form == kSumProduct) != sp) continue;
+        if (form != kCompressed && tt.eloc > kExplicitMaxEdges) continue;
         for (int pm = 0; pm < 2; ++pm)
             o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_" << form << pm
-              << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << xf
+              << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << form
               << ">(a, w); }\n";
         o << "extern \"C\" __global__ void __launch_bounds__(" << wg << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
-          << ", " << (wg == 64 ? "true" : "false") << ", " << xf << ">(a, w, x); }\n";
+          << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
     }
     return o.str();
 }
@@ -164,10 +165,12 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
     return ok;
 }
 
-std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::string &err) {
-    const std::string src = source(c, t);
+std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, std::string &err) {
+    const std::string src = source(c, t, sp);
     if (src.empty()) {
-        err = "no local position map";
+        err = sp ? "sum-product needs a local position map and at most " + std::to_string(kExplicitMaxEdges) +
+                       " edges per view"
+                 : "no local position map";
         return nullptr;
     }
     {
@@ -179,8 +182,9 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::strin
     if (!compile(src, obj, err)) return nullptr;
     auto k = std::make_shared<Kernels>();
     hipError_t e = hipModuleLoadData(&k->module, obj.data());
-    for (int form = kCompressed; form <= kExplicit && e == hipSuccess; ++form) {
-        if (form == kExplicit && c.t[t].eloc > kExplicitMaxEdges) break;
+    for (int form = kCompressed; form <= kSumProduct && e == hipSuccess; ++form) {
+        if ((form == kSumProduct) != sp) continue;
+        if (form != kCompressed && c.t[t].eloc > kExplicitMaxEdges) continue;
         const std::string f = std::to_string(form);
         for (int pm = 0; pm < 2 && e == hipSuccess; ++pm)
             e = hipModuleGetFunction(&k->local[form - 1][pm], k->module, ("lead_spec_local_" + f + std::to_string(pm)).c_str());

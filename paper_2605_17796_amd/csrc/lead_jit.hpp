@@ -16,8 +16,11 @@
 namespace lead {
 namespace jit {
 
-// Check-state forms of the specialised kernels (lead_schedule.specialized).
-enum Form { kCompressed = 1, kExplicit = 2 };
+// Check-state forms of the specialised kernels (lead_schedule.specialized):
+// min-sum with the compressed state or one register per message, and
+// sum-product (one register per message).
+enum Form { kCompressed = 1, kExplicit = 2, kSumProduct = 3 };
+constexpr int kForms = 3;
 
 // Views with at most this many local edges also get the explicit-message
 // form (one VGPR per message).
@@ -26,26 +29,28 @@ constexpr int kExplicitMaxEdges = 128;
 struct Kernels {
     hipModule_t module = nullptr;
     // [form - 1][prior mode]: Phase 1 queue kernel for per-shot / per-qubit priors
-    hipFunction_t local[2][2] = {};
-    hipFunction_t global[2] = {};  // [form - 1]: Phases 2-3
-    bool has[2] = {false, false};  // [form - 1]: compiled
-    int wg = 0;                    // workgroup size of `global`
-    int spw = 0;                   // shots per workgroup of `global`
-    bool bperm = false;            // partner values exchanged within the wave
-    int local_waves_per_cu[2][2] = {{4, 4}, {4, 4}};
-    int best_form() const { return has[1] ? kExplicit : kCompressed; }
+    hipFunction_t local[kForms][2] = {};
+    hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
+    bool has[kForms] = {};               // [form - 1]: compiled
+    int wg = 0;                          // workgroup size of `global`
+    int spw = 0;                         // shots per workgroup of `global`
+    bool bperm = false;                  // partner values exchanged within the wave
+    int local_waves_per_cu[kForms][2] = {{4, 4}, {4, 4}, {4, 4}};
+    int best_form() const { return has[2] ? kSumProduct : has[0] ? kCompressed : kExplicit; }
 };
 
-// Source text of the kernels for check type t of code c; empty when the code
-// has no local position map (the precompiled kernels serve it).
-std::string source(const Code &c, int t);
+// Source text of the kernels for check type t of code c: the min-sum forms,
+// or (sp) the sum-product form; empty when the code has no local position map
+// (the precompiled kernels serve min-sum) or, for sum-product, when a view
+// has more than kExplicitMaxEdges edges.
+std::string source(const Code &c, int t, bool sp = false);
 
 // Code object of `src` for gfx950 (compiled once per process).  Needs no GPU.
 bool compile(const std::string &src, std::vector<char> &obj, std::string &err);
 
 // Kernels of check type t of code c on the current device (device index
 // `device`), compiled and loaded on first use.
-std::shared_ptr<const Kernels> load(const Code &c, int t, int device, std::string &err);
+std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, std::string &err);
 
 // Partner tables of lead::SpecArgs for check type t: pv (order * ceil(D2/2)
 // words) and fown (order words).

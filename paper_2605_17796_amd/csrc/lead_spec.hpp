@@ -37,38 +37,37 @@ using lead::DecodeArgs;
 using lead::LocalArgs;
 using lead::SpecArgs;
 
-// Min-sum check update of check c from mu_{j->c} = clamp(S_j - m_{c->j}):
-// the smallest and second smallest |mu| (n1, n2), the position of the
-// smallest (nam), the sign bit of every mu at bit 31 (us, for the first deg
-// edges) and the parity of those signs (ps).  Returns the parity of the sign
-// bits of S over the check (the hard-decision test).
-template <class C, class Msg>
-__device__ __forceinline__ uint32_t check_scan(int c, const float (&S)[C::D * C::D], float clampv, const Msg &msg,
-                                               float &n1, float &n2, uint32_t &nam, uint32_t (&us)[C::D * C::D],
-                                               uint32_t &ps) {
-    constexpr int D2 = C::D * C::D;
-    uint32_t par = 0u;
-    n1 = kBig;
-    n2 = kBig;
-    nam = 0u;
-    ps = 0u;
-    uint32_t k = 0u;
-#pragma unroll
-    for (int j = 0; j < D2; ++j) {
-        if ((C::mask[c] >> j) & 1ull) {
-            par ^= __float_as_uint(S[j]);
-            const float mu = clampf(S[j] - msg(k), clampv);
-            us[k] = __float_as_uint(mu) & kSign;
-            ps ^= us[k];
-            const float ab = fabsf(mu);
-            n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
-            const bool lt = ab < n1;
-            nam = lt ? k : nam;
-            n1 = lt ? ab : n1;
-            ++k;
-        }
+// Compile-time loops.  Checks and edge positions are template constants, so
+// every mask test, edge number and array subscript below is a constant
+// expression (no reliance on the optimiser unrolling a loop first; an array
+// indexed by a value it could not fold would be left in scratch memory).
+template <int V>
+struct Int {
+    static constexpr int value = V;
+};
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(const F &f) {
+    if constexpr (I < N) {
+        f(Int<I>{});
+        static_for<I + 1, N>(f);
     }
-    return par;
+}
+
+constexpr int rank_below(uint64_t m, int j) {
+    int n = 0;
+    for (int i = 0; i < j; ++i) n += (int)((m >> i) & 1ull);
+    return n;
+}
+
+// f(j, k) for the edges of check c in position order: the k-th edge sits at
+// local position j.
+template <class C, int c, class F>
+__device__ __forceinline__ void for_edges(const F &f) {
+    static_for<0, C::D * C::D>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        if constexpr (((C::mask[c] >> j) & 1ull) != 0) f(Int<j>{}, Int<rank_below(C::mask[c], j)>{});
+    });
 }
 
 // Compressed check state (the precompiled kernels' form): per check
@@ -84,8 +83,9 @@ struct Compressed {
         for (int c = 0; c < R; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
     }
     // Check update of every check of the view from the sums S of the
-    // previous iteration.  Returns whether [S_j < 0] satisfies every check;
-    // `same` tells whether every check state is unchanged bit for bit.
+    // previous iteration: mu_{j->c} = clamp(S_j - m_{c->j}) and the new
+    // min-sum state.  Returns whether [S_j < 0] satisfies every check; `same`
+    // tells whether every outgoing message is unchanged bit for bit.
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same) {
         bool sat = true;
@@ -94,30 +94,37 @@ struct Compressed {
         // operands exist (a chain of boolean ands lets the compiler keep
         // every old value live until the end)
         uint32_t diff = 0u;
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            float n1, n2;
-            uint32_t nam, ps, us[C::D * C::D];
-            const uint32_t par = check_scan<C>(
-                c, S, clampv, [&](uint32_t k) { return msg_of(m1[c], m2[c], am[c], q[c], k); }, n1, n2, nam, us, ps);
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            float n1 = kBig, n2 = kBig;
+            uint32_t nam = 0u, sg = 0u, par = 0u;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value;
+                constexpr uint32_t k = decltype(kk)::value;
+                par ^= __float_as_uint(S[j]);
+                const float mu = clampf(S[j] - msg_of(m1[c], m2[c], am[c], q[c], k), clampv);
+                const float ab = fabsf(mu);
+                sg |= signbit_of(mu) << k;
+                n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
+                const bool lt = ab < n1;
+                nam = lt ? k : nam;
+                n1 = lt ? ab : n1;
+            });
             const uint32_t sc = (uint32_t)(sv >> c) & 1u;
             sat = sat && ((par >> 31) == sc);
-            // bit k of the new sign word: sign of mu_k xor the parity of all
-            // signs xor the syndrome bit
-            const uint32_t flip = (ps >> 31) ^ sc;
-            uint32_t nq = 0u;
-#pragma unroll
-            for (int k = 0; k < C::D * C::D; ++k)
-                if (k < C::deg[c]) nq |= ((us[k] >> 31) ^ flip) << k;
-            const float b1 = beta * n1, b2 = beta * n2;
+            const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
+            constexpr uint32_t all = (uint32_t)((1ull << C::deg[c]) - 1ull);
+            uint32_t nq = flip ? (sg ^ all) : sg;
+            uint32_t b1u = __float_as_uint(beta * n1), b2u = __float_as_uint(beta * n2);
             // every outgoing message unchanged (the position of the smallest
             // matters only when the two magnitudes differ)
-            uint32_t b1u = __float_as_uint(b1), b2u = __float_as_uint(b2);
             const uint32_t dterm = (nq ^ q[c]) | (b1u ^ __float_as_uint(m1[c])) | (b2u ^ __float_as_uint(m2[c])) |
                                    (b1u == b2u ? 0u : nam ^ am[c]);
             diff |= dterm;
             // the new state is written from operands that depend on the
-            // comparison (see Explicit::check)
+            // comparison: the old values are then dead when the new ones are
+            // written and can share their registers (no copies at the loop
+            // back-edge)
             asm("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam) : "v"(dterm));
             q[c] = nq;
             m1[c] = __uint_as_float(b1u);
@@ -125,19 +132,18 @@ struct Compressed {
             am[c] = nam;
             asm volatile("" : "+v"(diff));
             __builtin_amdgcn_sched_barrier(0);
-        }
+        });
         same = diff == 0u;
         return sat;
     }
     // S_j += m_{c->j} for every edge, checks in order.
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            uint32_t k = 0u;
-#pragma unroll
-            for (int j = 0; j < C::D * C::D; ++j)
-                if ((C::mask[c] >> j) & 1ull) S[j] += msg_of(m1[c], m2[c], am[c], q[c], k++);
-        }
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                S[decltype(jj)::value] += msg_of(m1[c], m2[c], am[c], q[c], (uint32_t)decltype(kk)::value);
+            });
+        });
     }
 };
 
@@ -161,85 +167,151 @@ struct Explicit {
         constexpr int D2 = C::D * C::D;
         bool sat = true;
         uint32_t diff = 0u;   // see Compressed::check
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            const int b = C::base[c];
-#pragma unroll
-            for (int k = 0; k < D2; ++k)
-                if (k < C::deg[c]) asm volatile("" : "+v"(m[b + k]));
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            constexpr int b = C::base[c];
+            for_edges<C, c>([&](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
             float n1 = kBig, n2 = kBig, mu[D2];
-            uint32_t par = 0u, ps = 0u, k = 0u;
-#pragma unroll
-            for (int j = 0; j < D2; ++j) {
-                if ((C::mask[c] >> j) & 1ull) {
-                    par ^= __float_as_uint(S[j]);
-                    mu[k] = clampf(S[j] - m[b + k], clampv);
-                    ps ^= __float_as_uint(mu[k]);
-                    n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[k]));
-                    n1 = fminf(n1, fabsf(mu[k]));
-                    ++k;
-                }
-            }
+            uint32_t par = 0u, ps = 0u;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+                par ^= __float_as_uint(S[j]);
+                mu[j] = clampf(S[j] - m[b + k], clampv);
+                ps ^= __float_as_uint(mu[j]);
+                n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[j]));
+                n1 = fminf(n1, fabsf(mu[j]));
+            });
             const uint32_t sc = (uint32_t)(sv >> c) & 1u;
             sat = sat && ((par >> 31) == sc);
             const uint32_t px = (ps ^ (sc << 31)) & kSign;
             uint32_t b1 = __float_as_uint(beta * n1), b2 = __float_as_uint(beta * n2);
             asm("" : "+v"(b1), "+v"(b2));   // keep the two products (not a product per edge)
-#pragma unroll
-            for (int e = 0; e < D2; ++e)
-                if (e < C::deg[c]) {
-                    uint32_t mag = fabsf(mu[e]) == n1 ? b2 : b1;
-                    const uint32_t sgn = (__float_as_uint(mu[e]) & kSign) ^ px;
-                    // compare first, then form the new message from operands
-                    // that depend on the comparison: the old message is then
-                    // dead when the new one is written and both can share a
-                    // register (no copy at the loop back-edge)
-                    const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + e]);
-                    diff |= dterm;
-                    asm("" : "+v"(mag) : "v"(dterm));
-                    m[b + e] = __uint_as_float(mag | sgn);
-                }
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+                uint32_t mag = fabsf(mu[j]) == n1 ? b2 : b1;
+                const uint32_t sgn = (__float_as_uint(mu[j]) & kSign) ^ px;
+                // compare first, then form the new message from operands that
+                // depend on the comparison (see Compressed::check)
+                const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + k]);
+                diff |= dterm;
+                asm("" : "+v"(mag) : "v"(dterm));
+                m[b + k] = __uint_as_float(mag | sgn);
+            });
             asm volatile("" : "+v"(diff));
             __builtin_amdgcn_sched_barrier(0);
-        }
+        });
         same = diff == 0u;
         return sat;
     }
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
-#pragma unroll
-        for (int c = 0; c < R; ++c) {
-            uint32_t k = 0u;
-#pragma unroll
-            for (int j = 0; j < C::D * C::D; ++j)
-                if ((C::mask[c] >> j) & 1ull) S[j] += m[C::base[c] + k++];
-        }
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                S[decltype(jj)::value] += m[C::base[c] + decltype(kk)::value];
+            });
+        });
     }
 };
 
-template <class C, bool X>
+// Sum-product check update with one register per message (same storage and
+// fixed-point test as Explicit).  Per check: mu_k = clamp(S_j - m_k), f_k =
+// phi(|mu_k|); the message to edge k has magnitude phi(sum_{k' != k} f_k')
+// and the min-sum sign rule.  The exclusive sums are formed without
+// cancellation: with fmax the largest f (first edge a attaining it) and
+// rest = the sum of all the others, edge a gets rest and every other edge
+// fmax + (rest - f_k) (rest - f_k is small only next to fmax).
+template <class C>
+struct ExplicitSP {
+    static constexpr int R = C::R, E = C::E;
+    float m[E];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int e = 0; e < E; ++e) m[e] = 0.f;
+    }
+    __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float, float clampv,
+                                          bool &same) {
+        constexpr int D2 = C::D * C::D;
+        bool sat = true;
+        uint32_t diff = 0u;
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            constexpr int b = C::base[c];
+            for_edges<C, c>([&](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
+            float mu[D2], f[D2], fmax = 0.f, rest = 0.f;
+            uint32_t par = 0u, ps = 0u, amax = 0u;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+                par ^= __float_as_uint(S[j]);
+                mu[j] = clampf(S[j] - m[b + k], clampv);
+                ps ^= __float_as_uint(mu[j]);
+                f[j] = phi(fabsf(mu[j]));
+                if constexpr (k == 0) {
+                    fmax = f[j];
+                    amax = (uint32_t)j;
+                } else {
+                    const bool gt = f[j] > fmax;
+                    rest += gt ? fmax : f[j];
+                    amax = gt ? (uint32_t)j : amax;
+                    fmax = gt ? f[j] : fmax;
+                }
+            });
+            const uint32_t sc = (uint32_t)(sv >> c) & 1u;
+            sat = sat && ((par >> 31) == sc);
+            const uint32_t px = (ps ^ (sc << 31)) & kSign;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+                // fmax = +inf when some |mu| is 0: every other edge's
+                // exclusive sum is then +inf (message 0)
+                const float ex = (uint32_t)j == amax ? rest : fmax == __builtin_inff() ? fmax : fmax + (rest - f[j]);
+                uint32_t mag = __float_as_uint(phi(ex));
+                const uint32_t sgn = (__float_as_uint(mu[j]) & kSign) ^ px;
+                const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + k]);
+                diff |= dterm;
+                asm("" : "+v"(mag) : "v"(dterm));
+                m[b + k] = __uint_as_float(mag | sgn);
+            });
+            asm volatile("" : "+v"(diff));
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        same = diff == 0u;
+        return sat;
+    }
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                S[decltype(jj)::value] += m[C::base[c] + decltype(kk)::value];
+            });
+        });
+    }
+};
+
+// Check-state forms (lead_schedule.specialized; 3 = sum-product).
+template <class C, int FORM>
 struct Pick {
     using type = Compressed<C>;
 };
 template <class C>
-struct Pick<C, true> {
+struct Pick<C, 2> {
     using type = Explicit<C>;
 };
-template <class C, bool X>
-using CheckState = typename Pick<C, X>::type;
+template <class C>
+struct Pick<C, 3> {
+    using type = ExplicitSP<C>;
+};
+template <class C, int FORM>
+using CheckState = typename Pick<C, FORM>::type;
 
 // Whether [S_j < 0] satisfies every check of the view.
 template <class C>
 __device__ __forceinline__ bool parity(const float (&S)[C::D * C::D], uint64_t sv) {
-    constexpr int D2 = C::D * C::D;
     bool sat = true;
-#pragma unroll
-    for (int c = 0; c < C::R; ++c) {
+    static_for<0, C::R>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
         uint32_t par = 0u;
-#pragma unroll
-        for (int j = 0; j < D2; ++j)
-            if ((C::mask[c] >> j) & 1ull) par ^= __float_as_uint(S[j]);
+        for_edges<C, c>([&](auto jj, auto) { par ^= __float_as_uint(S[decltype(jj)::value]); });
         sat = sat && ((par >> 31) == ((uint32_t)(sv >> c) & 1u));
-    }
+    });
     return sat;
 }
 
@@ -265,7 +337,7 @@ __device__ __forceinline__ uint64_t local_syndrome(const DecodeArgs &a, int64_t 
 // variable update gives S^0 = lambda exactly).  Only the output stores are
 // divergent.  Updating S or the check states under a divergent branch would
 // make the compiler keep the old and the new copies of them live at once.
-template <class C, int PM, bool X>
+template <class C, int PM, int FORM>
 __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs &w) {
     constexpr int D2 = C::D * C::D;
     constexpr int NL = PM == 0 ? 1 : D2;
@@ -280,7 +352,7 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     float S[D2];
 #pragma unroll
     for (int j = 0; j < NL; ++j) lam[j] = 0.f;
-    CheckState<C, X> st;
+    CheckState<C, FORM> st;
     st.clear();
     for (;;) {
         uint64_t need = __ballot(!valid);
@@ -408,7 +480,7 @@ __device__ __forceinline__ void store_all(const float (&X)[C::D * C::D], float *
 // view forms its partial sum P_j (lambda' on owned positions, then its
 // checks' messages in check order) and S_j = P_j + P_j' of the other
 // occurrence.
-template <class C, int WG, bool BPERM, bool X>
+template <class C, int WG, bool BPERM, int FORM>
 __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x) {
     constexpr int D2 = C::D * C::D;
     constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
@@ -508,7 +580,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     };
 #pragma unroll
     for (int j = 0; j < D2; ++j) S[j] = lam[j];
-    CheckState<C, X> st;
+    CheckState<C, FORM> st;
     st.clear();
     if (!BPERM) __syncthreads();
     bool done = !live;

@@ -1,0 +1,87 @@
+"""Sum-product BP (both stages, log-domain check update on the kernels
+compiled for the code) against the oracle's sum-product LEAD, and its
+limits."""
+import numpy as np
+import pytest
+
+from conftest import code_pair
+from gpu_common import (log, torch_dev, gpu_decoder, run_gpu, compare, oracle_decode_conditioned, bitflip_inputs)
+from lead_inputs import channel_llr, uniform_p
+
+pytestmark = pytest.mark.gpu
+
+SP = 1
+
+
+def _gpu_syndrome(dec, e):
+    torch = torch_dev()
+    s = dec.syndrome(torch.from_numpy(e.view(np.int64)).cuda())
+    torch.cuda.synchronize()
+    return s.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("name,t,p,T,alpha,min_well", [("T", 0, 0.05, 32, 1.0, 0.6), ("T", 1, 0.03, 32, 0.5, 0.6),
+                                                       ("M", 0, 0.02, 50, 1.0, 0.4), ("M", 0, 0.05, 8, 1.0, 0.4),
+                                                       ("M", 1, 0.01, 50, 0.1, 0.2)])
+def test_sum_product_matches_oracle(name, t, p, T, alpha, min_well):
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=T, max_iter_global=T, alpha=alpha, bp=SP)
+    assert dec.get_schedule()["specialized"] == 3
+    e, s, lam = bitflip_inputs(oc, 160, p, seed=71, t=t)
+    s = _gpu_syndrome(dec, e)
+    g = run_gpu(dec, s, lam, 0, lam=True)
+    orc = oracle_decode_conditioned(oc, s, lam, t=t, max_iter_local=T, max_iter_global=T, alpha=alpha, bp=SP)
+    res = compare(orc, g, oc.n)
+    well = 1 - orc["ill"].mean()
+    log(f"[sum-product] {name} t={t} p={p} T={T} alpha={alpha}: {res['bad']} differ, {res['tie']} ill-conditioned, "
+        f"well-conditioned share {well:.2f}, worst ok |dLLR| {res['worst_ok']:.2e}")
+    assert not res["unexplained"], res["detail"]
+    assert well >= min_well
+
+
+def test_sum_product_batched_and_served_equal_alone():
+    import paper_2605_17796_amd as P
+    torch = torch_dev()
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_local=50, max_iter_global=50, bp=SP, max_shots=4096)
+    ps = uniform_p(300, 0.02, 0.08, 4)
+    e, _, _ = bitflip_inputs(oc, 300, 0.05, seed=4)
+    s = torch.from_numpy(_gpu_syndrome(dec, e).view(np.int64)).cuda()
+    pr = torch.from_numpy(channel_llr(ps).astype(np.float32)).cuda()
+    a = dec.decode(s, pr, lam=True)
+    out = dec.alloc_outputs(300, lam=True)
+    g = P.Batch([(dec, s, pr, out, P.LEAD_PRIOR_PER_SHOT)]).capture()
+    g.replay()
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam", "stats"):
+        assert torch.equal(a[k], out[k]), k
+    server = P.Server([dec], max_batch_shots=128)
+    tk = server.submit(0, s.cpu().numpy().view(np.uint64), pr.cpu().numpy())
+    server.wait(tk)
+    r = server.result(tk, 0, 300)
+    server.close()
+    assert np.array_equal(r["ehat"], a["ehat"].cpu().numpy().view(np.uint64))
+    assert np.array_equal(r["stats"], a["stats"].cpu().numpy())
+
+
+def test_sum_product_limits():
+    """Views above 128 local edges (PSL(2,7)), the plain per-round form and the
+    GLOBAL stage are min-sum only."""
+    import paper_2605_17796_amd as P
+    torch = torch_dev()
+    spec, oc = code_pair("L")
+    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
+        gpu_decoder(spec, bp=SP)
+    spec, oc = code_pair("T")
+    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
+        gpu_decoder(spec, bp=SP, stage=2)
+    code, dec = gpu_decoder(spec, bp=SP)
+    s = torch.zeros((4, 1), dtype=torch.int64, device="cuda")
+    lam = torch.full((4,), 2.9, dtype=torch.float32, device="cuda")
+    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
+        dec.decode(s, lam, plain=True)
+    # switching flavours on a live decoder
+    dec.set_params(bp=0)
+    assert dec.get_schedule()["specialized"] in (1, 2)
+    dec.set_params(bp=SP)
+    assert dec.get_schedule()["specialized"] == 3
