@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch leg")
     ap.add_argument("--no-served", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the sum-product / alpha sweep / depolarising legs")
     ap.add_argument("--no-baseline-decoder", action="store_true",
                     help="skip the global-BP-only (single-stage) comparison leg")
     ap.add_argument("--roofline-only", action="store_true",
@@ -364,6 +366,55 @@ def main():
                      "mean_global_iterations": round(float(lst[:, 1].mean()), 2)},
             "note": "same 10^5 syndromes; I = I_g + mean local iterations x r/m (the paper's iteration measure)"}
 
+    # ---- variants on the same GPU: sum-product BP on the headline batches;
+    #      alpha sweep at p = 0.02; PSL(2,7) under depolarising noise
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        sdec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
+                         alpha=1.0, bp=1)
+        sout = sdec.alloc_outputs(shots)
+        sdec.decode(synd_pool[0], lam, out=sout)
+        sw, _ = timed(torch, lambda i: sdec.decode(synd_pool[i % pool_batches], lam, out=sout), 2)
+        sst = sout["stats"].cpu().numpy()
+        variants["sum_product_A5_p005"] = {"shots_per_s": round(2 * shots / sw, 1),
+                                          "converged": round(float(sst[:, 0].mean()), 4),
+                                          "mean_global_iters": round(float(sst[:, 1].mean()), 2)}
+        del sdec, sout
+        s02 = syndromes(torch, dec, n, shots, 0.02, seed=1500)
+        lam02 = torch.full((shots,), float(channel_llr(0.02)), dtype=torch.float32, device="cuda")
+        sweep = []
+        for alpha in (1.0, 0.5, 0.1, 0.01):
+            dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=alpha)
+            dec.decode(s02, lam02, out=out)
+            aw, _ = timed(torch, lambda i: dec.decode(s02, lam02, out=out), 1)
+            ast = out["stats"].cpu().numpy()
+            sweep.append({"alpha": alpha, "shots_per_s": round(shots / aw, 1),
+                          "converged": round(float(ast[:, 0].mean()), 4),
+                          "mean_global_iters": round(float(ast[:, 1].mean()), 2)})
+        dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=1.0)
+        variants["alpha_sweep_A5_p002"] = sweep
+        from lead_inputs import depolarizing_packed
+        lshots, ldist, pdep = 200_000, 20_000, 0.03
+        lcode = P.Code.from_spec(__import__("lead_inputs").standard("L"))
+        xs, zs = depolarizing_packed(ldist, lcode.n, pdep, seed=2500)
+        reps = lshots // ldist
+        lam_d = torch.full((lshots,), float(channel_llr(2 * pdep / 3)), dtype=torch.float32, device="cuda")
+        parts, ltime = {}, 0.0
+        for t, e in ((0, xs), (1, zs)):
+            ld = P.Decoder(lcode, t=t, max_shots=lshots, max_iter_local=ROUNDS["L"], max_iter_global=ROUNDS["L"])
+            ls = ld.syndrome(torch.from_numpy(e.view(np.int64)).cuda()).repeat(reps, 1).contiguous()
+            lo_ = ld.alloc_outputs(lshots, post=False)
+            ld.decode(ls, lam_d, out=lo_)
+            lw, _ = timed(torch, lambda i: ld.decode(ls, lam_d, out=lo_), 1)
+            ltime += lw
+            lst = lo_["stats"].cpu().numpy()
+            parts["XZ"[t] + "_errors"] = {"converged": round(float(lst[:, 0].mean()), 4),
+                                          "mean_global_iters": round(float(lst[:, 1].mean()), 2)}
+            del ld, ls, lo_
+        variants["PSL27_depolarising"] = {"p": pdep, "shots": lshots, "distinct_error_draws": ldist,
+                                          "shots_per_s_both_parts": round(lshots / ltime, 1), **parts}
+
     # ---- mixed-code batch (D6 / A5 / PSL(2,7)): one graph launch vs plain
     mixed = None
     decs_named = {"M": (code, dec)}
@@ -446,6 +497,7 @@ def main():
                          "mean_local_iters": round(float(st[:, 2].mean() / info.order), 2)},
         "plain_form": plain,
         "single_stage_baseline": base_leg,
+        "variants": variants,
         "mixed_batch": mixed,
         "served": served,
         "cpu_baseline": cpu,
