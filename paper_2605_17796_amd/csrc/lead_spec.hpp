@@ -585,21 +585,32 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     if (!BPERM) __syncthreads();
     bool done = !live;
     int itg = 0, gconv = 0, gfix = 0;
+    // lanes of this lane's shot within the wave (one-wave workgroups)
+    const uint64_t smask = lane_ok ? ((a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull)) << (sl * a.N)) : 0ull;
     for (int t = 1; t <= a.Tg; ++t) {
         // computed by every lane (see local_body); done lanes discard it
         bool same;
         const bool sat = st.check(S, sv, a.beta, a.clampv, same);
-        if (!done && !sat) shf[sl * 8 + (t & 1)] = 1;
-        if (!done && !same) shf[sl * 8 + SF_CHG] = t;
-        __syncthreads();
+        bool shot_sat, shot_same;
+        if constexpr (BPERM) {
+            // the shot's flags are ballots over its lanes: no LDS, no barrier
+            const uint64_t unsat = __ballot(!done && !sat), chg = __ballot(!done && !same);
+            shot_sat = (unsat & smask) == 0ull;
+            shot_same = (chg & smask) == 0ull;
+        } else {
+            if (!done && !sat) shf[sl * 8 + (t & 1)] = 1;
+            if (!done && !same) shf[sl * 8 + SF_CHG] = t;
+            __syncthreads();
+            shot_sat = shf[sl * 8 + (t & 1)] == 0;
+            shot_same = shf[sl * 8 + SF_CHG] != t;
+        }
         if (!done && t > 1) {
-            const bool shot_sat = shf[sl * 8 + (t & 1)] == 0;
             if (shot_sat && a.early_exit) {
                 done = true;
                 gconv = 1;
                 itg = t - 1;
                 emit();
-            } else if (a.fixed_stop && shf[sl * 8 + SF_CHG] != t) {
+            } else if (a.fixed_stop && shot_same) {
                 done = true;
                 gconv = shot_sat ? 1 : 0;
                 itg = a.Tg;
@@ -607,8 +618,12 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
                 emit();
             }
         }
-        if (!__syncthreads_or(done ? 0 : 1)) break;
-        if (lane_ok && v == 0) shf[sl * 8 + ((t + 1) & 1)] = 0;
+        if constexpr (BPERM) {
+            if (__ballot(!done) == 0ull) break;
+        } else {
+            if (!__syncthreads_or(done ? 0 : 1)) break;
+            if (lane_ok && v == 0) shf[sl * 8 + ((t + 1) & 1)] = 0;
+        }
         // partial sums of this view, then S_j = P_j + P of the other occurrence
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] = owned(j) ? lam[j] : 0.f;
@@ -620,10 +635,17 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         for (int j = 0; j < D2; ++j) S[j] += Q[j];
     }
     const bool ran_out = !done;
-    if (ran_out && !parity<C>(S, sv)) shf[sl * 8 + SF_FINAL] = 1;
-    __syncthreads();
+    const bool psat = parity<C>(S, sv);
+    bool shot_final;
+    if constexpr (BPERM) {
+        shot_final = (__ballot(ran_out && !psat) & smask) == 0ull;
+    } else {
+        if (ran_out && !psat) shf[sl * 8 + SF_FINAL] = 1;
+        __syncthreads();
+        shot_final = shf[sl * 8 + SF_FINAL] == 0;
+    }
     if (ran_out) {
-        gconv = shf[sl * 8 + SF_FINAL] == 0 ? 1 : 0;
+        gconv = shot_final ? 1 : 0;
         itg = a.Tg;
         emit();
     }
