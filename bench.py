@@ -47,7 +47,7 @@ CSRC = os.path.join(ROOT, "paper_2605_17796_amd", "csrc")
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("lead_spec.hpp", "lead_device.hpp", "lead_args.hpp", "lead_jit.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lead_spec_global_A5_p005_traffic.json")
 # schedule of the headline when the autotuner is skipped (--schedule overrides)
-DEFAULT_SCHEDULE = {"specialized": 1, "local_chunk": 64}
+DEFAULT_SCHEDULE = {"specialized": 2, "local_chunk": 64}
 
 
 def kernel_hash() -> str:

@@ -224,7 +224,7 @@ typedef struct {
                                      0: the precompiled kernels.  Reads back as
                                      the form in use (a form that was not
                                      compiled is replaced by the other). The
-                                     default is 1.                              */
+                                     default is 2 where compiled, else 1.       */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);

@@ -373,7 +373,7 @@ class Decoder:
         self.params = lead_params_make(**params)
         lead_decoder_set_params(self._h, self.params)
 
-    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=1):
+    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=2):
         lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves,
                                                          specialized))
 

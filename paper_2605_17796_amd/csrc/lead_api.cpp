@@ -503,7 +503,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             if (e == hipSuccess)
                 e = hipMemcpy(d->d_fown, fown.data(), sizeof(uint64_t) * fown.size(), hipMemcpyHostToDevice);
         }
-        d->sched.specialized = spec_form(d.get(), lead::jit::kCompressed);
+        d->sched.specialized = spec_form(d.get(), lead::jit::kExplicit);
         if (e == hipErrorNotSupported) {
             (void)hipFree(d->d_view);
             (void)hipFree(d->d_own);
@@ -575,7 +575,7 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
         if (k && !d->d_pv) return fail(LEAD_E_UNSUPPORTED, "no partner tables");
         d->spec = k;
         d->params = *params;
-        d->sched.specialized = spec_form(d, lead::jit::kCompressed);
+        d->sched.specialized = spec_form(d, lead::jit::kExplicit);
         if (sum_product(d)) d->sched.fused = 0;
         return LEAD_OK;
     }

@@ -106,7 +106,10 @@ std::string source(const Code &c, int t, bool sp) {
             o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_" << form << pm
               << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << form
               << ">(a, w); }\n";
-        o << "extern \"C\" __global__ void __launch_bounds__(" << wg << ") lead_spec_global_" << form
+        // explicit forms: at least two waves per SIMD for the per-shot kernel
+        // (its rounds wait on ds_bpermute, which a lone wave cannot hide)
+        o << "extern \"C\" __global__ void __launch_bounds__(" << wg << (form == kCompressed ? "" : ", 2")
+          << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
     }

@@ -36,7 +36,7 @@ struct Kernels {
     int spw = 0;                         // shots per workgroup of `global`
     bool bperm = false;                  // partner values exchanged within the wave
     int local_waves_per_cu[kForms][2] = {{4, 4}, {4, 4}, {4, 4}};
-    int best_form() const { return has[2] ? kSumProduct : has[0] ? kCompressed : kExplicit; }
+    int best_form() const { return has[2] ? kSumProduct : has[1] ? kExplicit : kCompressed; }
 };
 
 // Source text of the kernels for check type t of code c: the min-sum forms,
