@@ -587,6 +587,51 @@ int oracle_bp(int rows, int cols, const uint8_t *H, const uint8_t *s, const doub
 }
 
 /* ------------------------------------------------------------------ */
+/* OSD-0 on a local view (local post-processing of the BP output)       */
+/* ------------------------------------------------------------------ */
+
+/* Ordered statistics decoding of order 0 for H e = s (H: rows x cols, dense,
+ * cols <= 64, rows <= 64).  The variables are ranked by their BP posterior
+ * LLR, most likely in error first (L ascending; equal L in position order);
+ * Gaussian elimination over GF(2) takes the columns in that order and keeps
+ * the first `rank` linearly independent ones (the information set); the
+ * estimate is the solution supported on the information set.  Returns 0, or
+ * -1 when s is not in the column space of H (e is then all zero). */
+int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L, uint8_t *e) {
+    int order[64], pivcol[64];
+    uint8_t M[64][65];
+    if (rows > 64 || cols > 64) return -1;
+    for (int j = 0; j < cols; j++) order[j] = j;
+    for (int a = 1; a < cols; a++) {          /* stable insertion sort */
+        int x = order[a], b = a;
+        while (b > 0 && L[order[b - 1]] > L[x]) { order[b] = order[b - 1]; b--; }
+        order[b] = x;
+    }
+    for (int r = 0; r < rows; r++) {
+        for (int j = 0; j < cols; j++) M[r][j] = H[(size_t)r * cols + j];
+        M[r][cols] = s[r];
+    }
+    int rank = 0;
+    for (int t = 0; t < cols && rank < rows; t++) {
+        int c = order[t], pr = -1;
+        for (int r = rank; r < rows; r++)
+            if (M[r][c]) { pr = r; break; }
+        if (pr < 0) continue;                 /* dependent on the columns before it */
+        if (pr != rank)
+            for (int j = 0; j <= cols; j++) { uint8_t tmp = M[pr][j]; M[pr][j] = M[rank][j]; M[rank][j] = tmp; }
+        for (int r = 0; r < rows; r++)
+            if (r != rank && M[r][c])
+                for (int j = 0; j <= cols; j++) M[r][j] ^= M[rank][j];
+        pivcol[rank++] = c;
+    }
+    memset(e, 0, (size_t)cols);
+    for (int r = rank; r < rows; r++)
+        if (M[r][cols]) return -1;
+    for (int k = 0; k < rank; k++) e[pivcol[k]] = M[k][cols];
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* LEAD (Algorithm 1)                                                   */
 /* ------------------------------------------------------------------ */
 
@@ -642,7 +687,7 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
         wl.rng = p->perturb_seed * 0x100000001B3ull + (uint64_t)shot * 2;
         wg.rng = p->perturb_seed * 0x100000001B3ull + (uint64_t)shot * 2 + 1;
 
-        int it_sum = 0, it_max = 0, nconv = 0;
+        int it_sum = 0, it_max = 0, nconv = 0, nosd = 0;
 
         /* Phase 1: local decoding on every vertex of the decoded side */
         for (int v = 0; v < N; v++) {
@@ -655,6 +700,12 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             it_sum += it_v;
             if (it_v > it_max) it_max = it_v;
             nconv += conv_v;
+            /* local post-processing: OSD-0 where BP left the local syndrome
+             * unsatisfied; its estimate replaces BP's decisions */
+            if (p->local_osd && !conv_v && oracle_osd0(r, D2, c->hloc[type], sv, Lv, ev) == 0) {
+                conv_v = 1;
+                nosd++;
+            }
             /* soft output as error probabilities, then the confidence boost:
              * if H_v e_v = s_v, p_{v,j} <- max(p_{v,j}, 0.5) where e_{v,j} = 1 */
             double *pv = pall + (size_t)v * D2;
@@ -687,8 +738,8 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             }
         }
         if (stats) {
-            int32_t *st = stats + (size_t)shot * 5;
-            st[0] = conv; st[1] = it_g; st[2] = it_sum; st[3] = it_max; st[4] = nconv;
+            int32_t *st = stats + (size_t)shot * 6;
+            st[0] = conv; st[1] = it_g; st[2] = it_sum; st[3] = it_max; st[4] = nconv; st[5] = nosd;
         }
         if (margin_out) margin_out[shot] = margin;
     }

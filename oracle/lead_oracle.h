@@ -57,6 +57,11 @@ typedef struct {
      * determined to the tolerance by FP32-sized rounding. */
     double perturb;
     uint64_t perturb_seed;
+    /* 1: a local BP run that ends with H_v e_v != s_v is followed by OSD-0
+     * on the view (ordered statistics decoding of order 0 with the BP
+     * posteriors as reliabilities); its estimate satisfies the local
+     * syndrome, so the view counts as converged for the confidence boost. */
+    int    local_osd;
 } oracle_params;
 
 /* info[] layout for oracle_info */
@@ -82,13 +87,17 @@ void oracle_syndrome(const oracle_code *c, int type, int shots, const uint64_t *
 
 /* Full LEAD decode of `shots` syndromes.  prior: shots x n channel LLRs.
  * Outputs (any may be NULL): ehat packed, post (L_post), lam (lambda'),
- * stats shots x 5 {converged, global_iters, local_iters_sum, local_iters_max,
- * local_converged_views}, margin (min |mu|,|L| seen), local_llr
+ * stats shots x 6 {converged, global_iters, local_iters_sum, local_iters_max,
+ * local_converged_views (by BP), views resolved by OSD-0}, margin (min |mu|,
+ * |L| seen), local_llr
  * (shots x order x delta^2 local posteriors). */
 int  oracle_decode(const oracle_code *c, int type, const oracle_params *p, int shots,
                    const uint64_t *synd, int synd_words, const double *prior,
                    uint64_t *ehat, int ehat_words, double *post, double *lam,
                    int32_t *stats, double *margin, double *local_llr);
+
+/* OSD-0 of H e = s with reliabilities L (see lead_oracle.c); 0 or -1. */
+int  oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L, uint8_t *e);
 
 /* Phase 2 (soft-information regularisation) alone: phat_i = alpha * mean of
  * pv over the views holding qubit i; lam_i = clamp(ln(1-phat_i) - ln phat_i).

@@ -24,13 +24,15 @@ class Params(C.Structure):
     _fields_ = [("alpha", C.c_double), ("bp", C.c_int), ("ms_scale", C.c_double),
                 ("max_iter_local", C.c_int), ("max_iter_global", C.c_int),
                 ("llr_clamp", C.c_double), ("early_exit", C.c_int), ("stage", C.c_int),
-                ("boost", C.c_int), ("perturb", C.c_double), ("perturb_seed", C.c_uint64)]
+                ("boost", C.c_int), ("perturb", C.c_double), ("perturb_seed", C.c_uint64),
+                ("local_osd", C.c_int)]
 
 
 def params(alpha=1.0, bp=MINSUM, ms_scale=0.75, max_iter_local=32, max_iter_global=32,
-           llr_clamp=30.0, early_exit=1, stage=FULL, boost=1, perturb=0.0, perturb_seed=0) -> Params:
+           llr_clamp=30.0, early_exit=1, stage=FULL, boost=1, perturb=0.0, perturb_seed=0,
+           local_osd=0) -> Params:
     return Params(alpha, bp, ms_scale, max_iter_local, max_iter_global, llr_clamp,
-                  early_exit, stage, boost, perturb, perturb_seed)
+                  early_exit, stage, boost, perturb, perturb_seed, local_osd)
 
 
 _lib = None
@@ -63,6 +65,8 @@ def lib():
         L.oracle_bp.argtypes = [C.c_int, C.c_int, P, P, P, C.POINTER(Params), C.c_int, P, P,
                                 C.POINTER(C.c_int)]
         L.oracle_global_bp.restype = C.c_int
+        L.oracle_osd0.restype = C.c_int
+        L.oracle_osd0.argtypes = [C.c_int, C.c_int, P, P, P, P]
         L.oracle_global_bp.argtypes = [C.c_void_p, C.c_int, C.POINTER(Params), C.c_int, P,
                                        C.c_int, P, P, C.c_int, P, P]
         L.oracle_logical_failure.restype = C.c_int
@@ -192,7 +196,7 @@ class OracleCode:
         ehat = np.zeros((shots, ew), dtype=np.uint64)
         post = np.zeros((shots, n), dtype=np.float64)
         lam = np.zeros((shots, n), dtype=np.float64)
-        stats = np.zeros((shots, 5), dtype=np.int32)
+        stats = np.zeros((shots, 6), dtype=np.int32)
         margin = np.zeros(shots, dtype=np.float64)
         loc = (np.zeros((shots, self.info.order, self.info.delta ** 2), dtype=np.float64)
                if want_local else None)
@@ -200,7 +204,8 @@ class OracleCode:
                                  _p(post), _p(lam), _p(stats), _p(margin), _p(loc))
         if rc != 0:
             raise OracleError(rc, "oracle_decode failed")
-        out = dict(ehat=ehat, post=post, lam=lam, stats=stats, margin=margin)
+        out = dict(ehat=ehat, post=post, lam=lam, stats=np.ascontiguousarray(stats[:, :5]), osd_views=stats[:, 5].copy(),
+                   margin=margin)
         if want_local:
             out["local"] = loc
         return out
@@ -254,3 +259,15 @@ def bp(H: np.ndarray, s: np.ndarray, lam: np.ndarray, max_iter: int, p: Params =
     it = lib().oracle_bp(rows, cols, _p(H), _p(s), _p(lam), C.byref(p), max_iter, _p(L), _p(e),
                          C.byref(conv))
     return L, e, bool(conv.value), it
+
+
+def osd0(H: np.ndarray, s: np.ndarray, L: np.ndarray):
+    """OSD-0 of H e = s with reliabilities L (most likely in error first:
+    L ascending, ties in position order).  Returns (e, ok)."""
+    H = np.ascontiguousarray(H, dtype=np.uint8)
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    rows, cols = H.shape
+    e = np.zeros(cols, dtype=np.uint8)
+    rc = lib().oracle_osd0(rows, cols, _p(H), _p(s), _p(L), _p(e))
+    return e, rc == 0

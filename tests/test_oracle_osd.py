@@ -1,0 +1,105 @@
+"""Pins of the oracle's local post-processing (OSD-0 on the views whose local
+BP run did not reach H_v e_v = s_v; the paper's BP-LSD family of local
+decoders): brute force over the information set, the stopping structure
+inside LEAD, and the confidence boost it makes live."""
+import numpy as np
+import pytest
+
+from conftest import code_pair
+from lead_inputs import bitflip_packed, channel_llr
+
+
+def _gf2_rank(rows):
+    rows = [int(r) for r in rows if r]
+    rank = 0
+    while rows:
+        piv = max(rows)
+        top = piv.bit_length() - 1
+        rows = [r ^ piv if (r >> top) & 1 else r for r in rows if r != piv]
+        rows = [r for r in rows if r]
+        rank += 1
+    return rank
+
+
+def _col_ints(H):
+    return [int(sum(int(H[i, j]) << i for i in range(H.shape[0]))) for j in range(H.shape[1])]
+
+
+def brute_osd0(H, s, L):
+    """Information set = the first columns, in order of L ascending (ties by
+    position), that raise the GF(2) rank; the estimate is the one pattern on
+    the information set whose syndrome is s (enumerated)."""
+    cols = _col_ints(H)
+    order = sorted(range(H.shape[1]), key=lambda j: (L[j], j))
+    info, chosen = [], []
+    for j in order:
+        if _gf2_rank(chosen + [cols[j]]) > len(chosen):
+            chosen.append(cols[j])
+            info.append(j)
+    target = int(sum(int(s[i]) << i for i in range(H.shape[0])))
+    sols = []
+    for mask in range(1 << len(info)):
+        acc = 0
+        for b, j in enumerate(info):
+            if (mask >> b) & 1:
+                acc ^= cols[j]
+        if acc == target:
+            e = np.zeros(H.shape[1], dtype=np.uint8)
+            for b, j in enumerate(info):
+                e[j] = (mask >> b) & 1
+            sols.append(e)
+    return sols
+
+
+@pytest.mark.parametrize("name", ["appendix", "T", "M"])
+def test_osd0_is_the_information_set_solution(name):
+    from oracle import oracle as o
+    _, oc = code_pair(name)
+    rng = np.random.default_rng(11)
+    for t in (0, 1):
+        H = oc.hloc(t)
+        for trial in range(12):
+            s = rng.integers(0, 2, size=H.shape[0]).astype(np.uint8)
+            # reliabilities with ties (saturated values) and distinct values
+            L = np.round(rng.uniform(-3, 3, size=H.shape[1]), 1 if trial % 2 else 6)
+            L[rng.random(H.shape[1]) < 0.2] = 30.0
+            e, ok = o.osd0(H, s, L)
+            sols = brute_osd0(H, s, L)
+            assert ok and len(sols) == 1
+            assert np.array_equal(e, sols[0])
+            assert np.array_equal((H.astype(int) @ e) % 2, s)
+
+
+def test_osd0_reports_unreachable_syndrome():
+    from oracle import oracle as o
+    H = np.array([[1, 1, 0], [1, 1, 0]], dtype=np.uint8)     # rank 1
+    e, ok = o.osd0(H, np.array([1, 0], dtype=np.uint8), np.zeros(3))
+    assert not ok and not e.any()
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_local_osd_in_lead(name):
+    """With OSD-0 every view ends with a local estimate: views BP resolved plus
+    views OSD resolved = all views; shots whose views all converged under BP
+    decode exactly as without OSD; elsewhere the boost can only lower the
+    local LLRs it touches, so the regularised priors lambda' do not rise."""
+    from oracle import oracle as o
+    spec, oc = code_pair(name)
+    T = {"T": 32, "M": 50}[name]
+    shots = 40
+    e = bitflip_packed(shots, oc.n, 0.05, seed=23)
+    s = oc.syndrome(e)
+    lam = np.full(shots, float(channel_llr(0.05)))
+    base = oc.decode(s, lam, p=o.params(max_iter_local=T, max_iter_global=T))
+    osd = oc.decode(s, lam, p=o.params(max_iter_local=T, max_iter_global=T, local_osd=1))
+    N = spec.order
+    assert np.array_equal(osd["stats"][:, 4] + osd["osd_views"], np.full(shots, N))
+    assert np.array_equal(osd["stats"][:, 2:5], base["stats"][:, 2:5])   # BP runs unchanged
+    same = osd["osd_views"] == 0
+    assert (~same).any()
+    if name == "T":
+        assert same.any()
+    for k in ("post", "lam"):
+        assert np.array_equal(osd[k][same], base[k][same])
+    assert np.all(osd["lam"] <= base["lam"] + 1e-12)
+    assert np.any(osd["lam"] < base["lam"] - 1e-6)
