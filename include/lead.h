@@ -134,6 +134,16 @@ typedef struct {
                                  would repeat it); results and reported
                                  iteration counts are identical to running to
                                  the cap                                       */
+    int32_t local_post;       /* 1: a local BP run that ends with H_v e_v != s_v
+                                 is followed by OSD-0 on its view (ordered
+                                 statistics decoding of order 0: variables
+                                 ranked by posterior LLR, most likely in
+                                 error first, ties in position order; the
+                                 solution supported on the first independent
+                                 columns).  The view then counts as converged
+                                 and the confidence boost applies to its
+                                 estimate.  Kernels compiled for the code
+                                 only (not plain, not stage GLOBAL).  0: none */
     int32_t bp;               /* lead_bp.  Sum-product runs on the kernels
                                  compiled for the code with one register per
                                  message (views of at most 128 local edges),
@@ -152,7 +162,7 @@ typedef struct {
     int32_t local_fixed_views;      /* local runs ended at a message fixed point   */
     int32_t global_fixed_iter;      /* iteration at which global BP reached a fixed
                                        point (0: it did not)                       */
-    int32_t reserved;
+    int32_t local_osd_views;        /* vertices resolved by OSD-0 (local_post = 1) */
 } lead_shot_stats;
 
 /* Creates a decoder for the checks of type `t` and uploads the device tables

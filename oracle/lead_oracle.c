@@ -592,7 +592,9 @@ int oracle_bp(int rows, int cols, const uint8_t *H, const uint8_t *s, const doub
 
 /* Ordered statistics decoding of order 0 for H e = s (H: rows x cols, dense,
  * cols <= 64, rows <= 64).  The variables are ranked by their BP posterior
- * LLR, most likely in error first (L ascending; equal L in position order);
+ * LLR, most likely in error first: by round(64 L) ascending, equal keys in
+ * position order (reliabilities that agree to 1/64 count as equal, so exact
+ * ties of symmetric positions stay ties under last-digit rounding);
  * Gaussian elimination over GF(2) takes the columns in that order and keeps
  * the first `rank` linearly independent ones (the information set); the
  * estimate is the solution supported on the information set.  Returns 0, or
@@ -601,10 +603,14 @@ int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const do
     int order[64], pivcol[64];
     uint8_t M[64][65];
     if (rows > 64 || cols > 64) return -1;
-    for (int j = 0; j < cols; j++) order[j] = j;
+    double key[64];
+    for (int j = 0; j < cols; j++) {
+        order[j] = j;
+        key[j] = nearbyint(L[j] * 64.0);       /* round half to even */
+    }
     for (int a = 1; a < cols; a++) {          /* stable insertion sort */
         int x = order[a], b = a;
-        while (b > 0 && L[order[b - 1]] > L[x]) { order[b] = order[b - 1]; b--; }
+        while (b > 0 && key[order[b - 1]] > key[x]) { order[b] = order[b - 1]; b--; }
         order[b] = x;
     }
     for (int r = 0; r < rows; r++) {

@@ -263,7 +263,7 @@ def bp(H: np.ndarray, s: np.ndarray, lam: np.ndarray, max_iter: int, p: Params =
 
 def osd0(H: np.ndarray, s: np.ndarray, L: np.ndarray):
     """OSD-0 of H e = s with reliabilities L (most likely in error first:
-    L ascending, ties in position order).  Returns (e, ok)."""
+    round(64 L) ascending, ties in position order).  Returns (e, ok)."""
     H = np.ascontiguousarray(H, dtype=np.uint8)
     s = np.ascontiguousarray(s, dtype=np.uint8)
     L = np.ascontiguousarray(L, dtype=np.float64)

@@ -49,7 +49,8 @@ class lead_code_info(C.Structure):
 class lead_params(C.Structure):
     _fields_ = [("alpha", C.c_float), ("ms_scale", C.c_float), ("max_iter_local", C.c_int32),
                 ("max_iter_global", C.c_int32), ("llr_clamp", C.c_float), ("early_exit", C.c_int32),
-                ("stage", C.c_int32), ("boost", C.c_int32), ("fixed_point_stop", C.c_int32), ("bp", C.c_int32)]
+                ("stage", C.c_int32), ("boost", C.c_int32), ("fixed_point_stop", C.c_int32), ("local_post", C.c_int32),
+                ("bp", C.c_int32)]
 
 
 class lead_schedule(C.Structure):
@@ -79,7 +80,7 @@ class lead_server_stats(C.Structure):
 
 
 STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views",
-                "local_fixed_views", "global_fixed_iter")
+                "local_fixed_views", "global_fixed_iter", "local_osd_views")
 
 SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
            "lead_code_specialize", "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
@@ -206,9 +207,10 @@ def lead_code_destroy(code):
 
 
 def lead_params_make(alpha=1.0, ms_scale=0.75, max_iter_local=32, max_iter_global=32, llr_clamp=30.0,
-                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1, fixed_point_stop=1, bp=LEAD_BP_MINSUM) -> lead_params:
+                     early_exit=1, stage=LEAD_STAGE_FULL, boost=1, fixed_point_stop=1, local_post=0,
+                     bp=LEAD_BP_MINSUM) -> lead_params:
     return lead_params(alpha, ms_scale, max_iter_local, max_iter_global, llr_clamp, early_exit, stage, boost,
-                       fixed_point_stop, bp)
+                       fixed_point_stop, local_post, bp)
 
 
 def lead_decoder_create(code, t, params: lead_params, max_shots: int):

@@ -86,6 +86,9 @@ lead_status check_params(const lead_params *p) {
     if (p->bp != LEAD_BP_MINSUM && p->bp != LEAD_BP_SUMPRODUCT) return fail(LEAD_E_ARG, "bad bp");
     if (p->bp == LEAD_BP_SUMPRODUCT && p->stage == LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL runs min-sum only");
+    if (p->local_post != 0 && p->local_post != 1) return fail(LEAD_E_ARG, "bad local_post");
+    if (p->local_post && p->stage == LEAD_STAGE_GLOBAL)
+        return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL has no local phase to post-process");
     return LEAD_OK;
 }
 
@@ -96,6 +99,9 @@ int default_spw(int N) { return std::max(1, 64 / N); }
 bool use_spec(const lead_decoder *d) { return d->spec && d->sched.specialized && !d->sched.fused; }
 
 bool sum_product(const lead_decoder *d) { return d->params.bp == LEAD_BP_SUMPRODUCT; }
+
+// Sum-product and OSD-0 run only on the kernels compiled for the code.
+bool needs_spec(const lead_decoder *d) { return sum_product(d) || d->params.local_post != 0; }
 
 // The specialised form a schedule asks for, or the one compiled when it
 // asks for the other (0: precompiled kernels).  Sum-product has one form.
@@ -123,8 +129,8 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
     a.spw = k.spw;
     lead::SpecArgs x{d->d_pv, d->d_fown};
     const int D2 = d->D * d->D, ew32 = (d->n + 31) / 32;
-    const size_t lds = (k.bperm ? 0 : sizeof(float) * (size_t)D2 * k.wg) + sizeof(int) * (size_t)k.spw * 8 +
-                       sizeof(uint32_t) * (size_t)k.spw * ew32;
+    const size_t lds = (k.bperm ? 0 : sizeof(float) * (size_t)D2 * k.wg) + sizeof(int) * (size_t)k.spw * 9 +
+                       sizeof(uint32_t) * (size_t)k.spw * ew32;   // 9: the kernel's per-shot flag stride
     const int64_t grid = (a.shots + k.spw - 1) / k.spw;
     void *gargs[] = {&a, &w, &x};
     e = hipModuleLaunchKernel(k.global[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
@@ -178,6 +184,7 @@ lead::DecodeArgs base_args(const lead_decoder *d) {
     a.stage = d->params.stage;
     a.boost = d->params.boost ? 1 : 0;
     a.fixed_stop = d->params.fixed_point_stop ? 1 : 0;
+    a.local_osd = d->params.local_post ? 1 : 0;
     for (int c = 0; c < lead::kMaxChecks; ++c) a.mask[c] = c < d->r ? d->mask[c] : 0;
     return a;
 }
@@ -492,7 +499,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
     if (e == hipSuccess) {
         std::string jerr;
         d->spec = lead::jit::load(c, t, d->device, sum_product(d.get()), jerr);
-        if (!d->spec && sum_product(d.get())) e = hipErrorNotSupported;
+        if (!d->spec && needs_spec(d.get())) e = hipErrorNotSupported;
         if (d->spec) {
             std::vector<uint32_t> pv;
             std::vector<uint64_t> fown;
@@ -510,7 +517,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             (void)hipFree(d->d_Lv);
             (void)hipFree(d->d_vflag);
             (void)hipFree(d->d_counter);
-            return fail(LEAD_E_UNSUPPORTED, "sum-product: " + jerr);
+            return fail(LEAD_E_UNSUPPORTED, "sum-product or OSD-0 needs the kernels compiled for the code: " + jerr);
         }
     }
     if (e != hipSuccess) {
@@ -576,10 +583,15 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
         d->spec = k;
         d->params = *params;
         d->sched.specialized = spec_form(d, lead::jit::kExplicit);
-        if (sum_product(d)) d->sched.fused = 0;
+        if (needs_spec(d)) d->sched.fused = 0;
         return LEAD_OK;
     }
+    if (params->local_post && !d->spec) return fail(LEAD_E_UNSUPPORTED, "OSD-0 needs the kernels compiled for the code");
     d->params = *params;
+    if (needs_spec(d)) {
+        d->sched.fused = 0;
+        if (!d->sched.specialized) d->sched.specialized = spec_form(d, lead::jit::kExplicit);
+    }
     return LEAD_OK;
 }
 
@@ -598,7 +610,10 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
     d->sched.local_waves = sc->local_waves;
     d->sched.specialized = spec_form(d, sc->specialized);
-    if (sum_product(d)) d->sched.fused = 0;   // sum-product runs the work-queue form only
+    if (needs_spec(d)) {   // sum-product and OSD-0 run the kernels compiled for the code only
+        d->sched.fused = 0;
+        if (!d->sched.specialized) d->sched.specialized = spec_form(d, lead::jit::kExplicit);
+    }
     return LEAD_OK;
 }
 
@@ -657,7 +672,7 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
                               float *post, float *lam, lead_shot_stats *stats, void *stream) {
     lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
     if (st != LEAD_OK || shots == 0) return st;
-    if (sum_product(d)) return fail(LEAD_E_UNSUPPORTED, "the plain form runs min-sum only");
+    if (needs_spec(d)) return fail(LEAD_E_UNSUPPORTED, "the plain form runs min-sum without OSD-0 only");
     if (d->params.stage == LEAD_STAGE_LOCAL)
         return lead_decode(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream);
     hipStream_t s = (hipStream_t)stream;
@@ -820,7 +835,7 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
     float best_ms = 1e30f;
     if (e == hipSuccess) {
         std::vector<lead_schedule> cand;
-        for (int fused = 0; fused < 2 && !sum_product(d); ++fused)
+        for (int fused = 0; fused < 2 && !needs_spec(d); ++fused)
             for (int spw : {1, 2, 4, 8, 16, 21})
                 for (int chunk : {64, 256, 1024}) {
                     if (fused && chunk != 256) continue;

@@ -19,7 +19,7 @@ constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
 // lead_shot_stats).
 struct ShotStats {
     int32_t converged, global_iters, local_iters_sum, local_iters_max, local_converged_views, local_fixed_views,
-        global_fixed_iter, reserved;
+        global_fixed_iter, local_osd_views;
 };
 
 // Everything a decode launch needs, passed by value in the kernel argument
@@ -39,6 +39,7 @@ struct DecodeArgs {
     float alpha, beta, clampv;
     int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
     int32_t global_only;       // no Phase 1; lambda' = the channel prior
+    int32_t local_osd;         // OSD-0 after local BP runs that miss the local syndrome
     uint64_t mask[kMaxChecks];
 };
 
@@ -46,6 +47,7 @@ struct DecodeArgs {
 struct LocalArgs {
     float *Lv;                 // [shots][N][D2] clamped local posteriors
     uint32_t *vflag;           // [shots][N] iterations | converged << 16 | fixed point << 17
+                               //            | resolved by OSD-0 << 18
     int64_t *counter;          // work-queue head
     int64_t items;             // shots * N
     int32_t chunk;             // items a wave takes at a time

@@ -325,6 +325,74 @@ __device__ __forceinline__ uint64_t local_syndrome(const DecodeArgs &a, int64_t 
     return (a.r >= 64) ? x : (x & ((1ull << a.r) - 1ull));
 }
 
+// OSD-0 of the view (local post-processing): positions are taken by
+// round(64 L) of the clamped posterior LLR ascending (most likely in error
+// first; equal keys in position order, so reliabilities that agree to 1/64
+// count as equal), each column (the r-bit set of the view's checks on that position)
+// is reduced against a GF(2) basis kept by lowest set bit and joins it when
+// independent, until the basis has rank r; the estimate is the combination
+// of basis columns that gives the local syndrome (a bit mask over
+// positions).  ok = false when the syndrome is not reached (H_v not of full
+// row rank).
+template <class C>
+__device__ __forceinline__ uint64_t osd0(const float (&L)[C::D * C::D], uint64_t sv, bool &ok) {
+    constexpr int D2 = C::D * C::D, R = C::R;
+    uint32_t bvec[R];
+    uint64_t bcomb[R];
+#pragma unroll
+    for (int b = 0; b < R; ++b) { bvec[b] = 0u; bcomb[b] = 0ull; }
+    uint32_t have = 0u;
+    uint64_t left = D2 == 64 ? ~0ull : ((1ull << D2) - 1ull);
+    float key[D2];
+#pragma unroll
+    for (int j = 0; j < D2; ++j) key[j] = __builtin_rintf(L[j] * 64.f);   // exact scaling, round half to even
+    int nb = 0;
+    for (int step = 0; step < D2 && nb < R; ++step) {
+        float best = __builtin_inff();
+        int bj = -1;
+        static_for<0, D2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            const bool lt = ((left >> j) & 1ull) && (bj < 0 || key[j] < best);
+            best = lt ? key[j] : best;
+            bj = lt ? j : bj;
+        });
+        left &= ~(1ull << bj);
+        uint32_t col = 0u;
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            col |= (uint32_t)((C::mask[c] >> bj) & 1ull) << c;
+        });
+        uint64_t comb = 1ull << bj;
+        bool placed = false;
+        static_for<0, R>([&](auto bb) {
+            constexpr int b = decltype(bb)::value;
+            if (!placed && ((col >> b) & 1u)) {
+                if ((have >> b) & 1u) {
+                    col ^= bvec[b];
+                    comb ^= bcomb[b];
+                } else {
+                    bvec[b] = col;
+                    bcomb[b] = comb;
+                    have |= 1u << b;
+                    placed = true;
+                }
+            }
+        });
+        nb += placed ? 1 : 0;
+    }
+    uint32_t x = (uint32_t)sv;
+    uint64_t e = 0ull;
+    static_for<0, R>([&](auto bb) {
+        constexpr int b = decltype(bb)::value;
+        if (((x >> b) & 1u) && ((have >> b) & 1u)) {
+            x ^= bvec[b];
+            e ^= bcomb[b];
+        }
+    });
+    ok = x == 0u;
+    return ok ? e : 0ull;
+}
+
 // Phase 1 as a work queue over (shot, vertex) items: a lane runs the local BP
 // of one item with S in VGPRs and takes the next item as soon as its run
 // ends.  Stopping rules and outputs are those of the precompiled local
@@ -415,9 +483,29 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
         }
         if (valid && fin) {
             float *out = w.Lv + item * D2;
+            float Lc[D2];
 #pragma unroll
-            for (int j = 0; j < D2; ++j) out[j] = clampf(S[j], a.clampv);
-            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
+            for (int j = 0; j < D2; ++j) Lc[j] = clampf(S[j], a.clampv);
+            uint32_t osd = 0u;
+            if (a.local_osd && !conv) {
+                // OSD-0 estimate; the view then counts as converged, and the
+                // confidence boost (p <- max(p, 1/2) on its errors, i.e.
+                // L <- min(L, 0)) applies to it
+                bool ok;
+                const uint64_t e = osd0<C>(Lc, sv, ok);
+                if (ok) {
+                    conv = 1;
+                    osd = 1u;
+                    if (a.boost) {
+#pragma unroll
+                        for (int j = 0; j < D2; ++j)
+                            if ((e >> j) & 1ull) Lc[j] = fminf(Lc[j], 0.f);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < D2; ++j) out[j] = Lc[j];
+            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17) | (osd << 18);
             valid = false;
         }
         ++t;
@@ -425,7 +513,8 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
 }
 
 // Per-shot LDS flags (the precompiled kernel's layout).
-enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5, SF_CHG = 6, SF_NFIX = 7 };
+enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5, SF_CHG = 6, SF_NFIX = 7,
+       SF_NOSD = 8, SF_STRIDE = 9 };
 
 // Partner addresses: for local position j, the byte address of the lane
 // that holds the other occurrence of the qubit (lane * 4).  Within one wave
@@ -489,19 +578,19 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     float *buf = lds;
     int *shf = reinterpret_cast<int *>(lds + (BPERM ? 0 : D2 * WG));
     const int ew32 = (a.n + 31) >> 5;
-    uint32_t *ebits = reinterpret_cast<uint32_t *>(shf + a.spw * 8);
+    uint32_t *ebits = reinterpret_cast<uint32_t *>(shf + a.spw * SF_STRIDE);
     const int tid = threadIdx.x;
     const int sl = tid / a.N, v = tid - sl * a.N;
     const bool lane_ok = sl < a.spw;
     const int64_t shot = (int64_t)blockIdx.x * a.spw + sl;
     const bool live = lane_ok && shot < a.shots;
-    for (int i = tid; i < a.spw * 8; i += WG) shf[i] = 0;
+    for (int i = tid; i < a.spw * SF_STRIDE; i += WG) shf[i] = 0;
     for (int i = tid; i < a.spw * ew32; i += WG) ebits[i] = 0u;
 
     float S[D2];
     uint32_t pa[NW];
     uint64_t sv = 0, fown = 0;
-    int it_v = 0, conv_v = 0, fixed_v = 0;
+    int it_v = 0, conv_v = 0, fixed_v = 0, osd_v = 0;
     if (live) {
         sv = local_syndrome(a, shot, v);
         const int64_t item = shot * a.N + v;
@@ -512,6 +601,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         it_v = (int)(f & 0xffffu);
         conv_v = (int)((f >> 16) & 1u);
         fixed_v = (int)((f >> 17) & 1u);
+        osd_v = (int)((f >> 18) & 1u);
         const uint32_t base = (uint32_t)(sl * a.N);
         using A = PartnerAddr<BPERM>;
 #pragma unroll
@@ -531,10 +621,11 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     }
     __syncthreads();
     if (live) {
-        atomicAdd(&shf[sl * 8 + SF_ITSUM], it_v);
-        atomicMax(&shf[sl * 8 + SF_ITMAX], it_v);
-        atomicAdd(&shf[sl * 8 + SF_NCONV], conv_v);
-        if (fixed_v) atomicAdd(&shf[sl * 8 + SF_NFIX], 1);
+        atomicAdd(&shf[sl * SF_STRIDE + SF_ITSUM], it_v);
+        atomicMax(&shf[sl * SF_STRIDE + SF_ITMAX], it_v);
+        atomicAdd(&shf[sl * SF_STRIDE + SF_NCONV], conv_v & (osd_v ^ 1));   // converged by BP
+        if (fixed_v) atomicAdd(&shf[sl * SF_STRIDE + SF_NFIX], 1);
+        if (osd_v) atomicAdd(&shf[sl * SF_STRIDE + SF_NOSD], 1);
     }
     auto owned = [&](int j) { return C::sigma[j] > j || (C::sigma[j] == j && ((fown >> j) & 1ull)); };
 
@@ -558,10 +649,11 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         __syncthreads();
         if (live && v == 0 && a.stats) {
             lead::ShotStats s = {};
-            s.local_iters_sum = shf[sl * 8 + SF_ITSUM];
-            s.local_iters_max = shf[sl * 8 + SF_ITMAX];
-            s.local_converged_views = shf[sl * 8 + SF_NCONV];
-            s.local_fixed_views = shf[sl * 8 + SF_NFIX];
+            s.local_iters_sum = shf[sl * SF_STRIDE + SF_ITSUM];
+            s.local_iters_max = shf[sl * SF_STRIDE + SF_ITMAX];
+            s.local_converged_views = shf[sl * SF_STRIDE + SF_NCONV];
+            s.local_fixed_views = shf[sl * SF_STRIDE + SF_NFIX];
+            s.local_osd_views = shf[sl * SF_STRIDE + SF_NOSD];
             reinterpret_cast<lead::ShotStats *>(a.stats)[shot] = s;
         }
         return;
@@ -598,11 +690,11 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             shot_sat = (unsat & smask) == 0ull;
             shot_same = (chg & smask) == 0ull;
         } else {
-            if (!done && !sat) shf[sl * 8 + (t & 1)] = 1;
-            if (!done && !same) shf[sl * 8 + SF_CHG] = t;
+            if (!done && !sat) shf[sl * SF_STRIDE + (t & 1)] = 1;
+            if (!done && !same) shf[sl * SF_STRIDE + SF_CHG] = t;
             __syncthreads();
-            shot_sat = shf[sl * 8 + (t & 1)] == 0;
-            shot_same = shf[sl * 8 + SF_CHG] != t;
+            shot_sat = shf[sl * SF_STRIDE + (t & 1)] == 0;
+            shot_same = shf[sl * SF_STRIDE + SF_CHG] != t;
         }
         if (!done && t > 1) {
             if (shot_sat && a.early_exit) {
@@ -622,7 +714,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             if (__ballot(!done) == 0ull) break;
         } else {
             if (!__syncthreads_or(done ? 0 : 1)) break;
-            if (lane_ok && v == 0) shf[sl * 8 + ((t + 1) & 1)] = 0;
+            if (lane_ok && v == 0) shf[sl * SF_STRIDE + ((t + 1) & 1)] = 0;
         }
         // partial sums of this view, then S_j = P_j + P of the other occurrence
 #pragma unroll
@@ -640,9 +732,9 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     if constexpr (BPERM) {
         shot_final = (__ballot(ran_out && !psat) & smask) == 0ull;
     } else {
-        if (ran_out && !psat) shf[sl * 8 + SF_FINAL] = 1;
+        if (ran_out && !psat) shf[sl * SF_STRIDE + SF_FINAL] = 1;
         __syncthreads();
-        shot_final = shf[sl * 8 + SF_FINAL] == 0;
+        shot_final = shf[sl * SF_STRIDE + SF_FINAL] == 0;
     }
     if (ran_out) {
         gconv = shot_final ? 1 : 0;
@@ -661,10 +753,11 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             lead::ShotStats s = {};
             s.converged = gconv;
             s.global_iters = itg;
-            s.local_iters_sum = shf[sl * 8 + SF_ITSUM];
-            s.local_iters_max = shf[sl * 8 + SF_ITMAX];
-            s.local_converged_views = shf[sl * 8 + SF_NCONV];
-            s.local_fixed_views = shf[sl * 8 + SF_NFIX];
+            s.local_iters_sum = shf[sl * SF_STRIDE + SF_ITSUM];
+            s.local_iters_max = shf[sl * SF_STRIDE + SF_ITMAX];
+            s.local_converged_views = shf[sl * SF_STRIDE + SF_NCONV];
+            s.local_fixed_views = shf[sl * SF_STRIDE + SF_NFIX];
+            s.local_osd_views = shf[sl * SF_STRIDE + SF_NOSD];
             s.global_fixed_iter = gfix;
             reinterpret_cast<lead::ShotStats *>(a.stats)[shot] = s;
         }

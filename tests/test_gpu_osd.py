@@ -1,0 +1,62 @@
+"""OSD-0 local post-processing (local_post = 1) on the kernels compiled for
+the code, against the oracle's LEAD with OSD-0, and across kernel forms."""
+import numpy as np
+import pytest
+
+from conftest import code_pair
+from gpu_common import (log, torch_dev, gpu_decoder, run_gpu, compare, oracle_decode_conditioned, bitflip_inputs)
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_syndrome(dec, e):
+    torch = torch_dev()
+    s = dec.syndrome(torch.from_numpy(e.view(np.int64)).cuda())
+    torch.cuda.synchronize()
+    return s.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("name,t,p,T,bp,min_well", [("T", 0, 0.05, 32, 0, 0.6), ("T", 1, 0.03, 32, 0, 0.6),
+                                                    ("M", 0, 0.02, 50, 0, 0.3), ("M", 0, 0.05, 8, 0, 0.3),
+                                                    ("T", 0, 0.05, 32, 1, 0.6), ("M", 0, 0.02, 50, 1, 0.3)])
+def test_local_osd_matches_oracle(name, t, p, T, bp, min_well):
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=T, max_iter_global=T, local_post=1, bp=bp)
+    e, s, lam = bitflip_inputs(oc, 160, p, seed=81, t=t)
+    s = _gpu_syndrome(dec, e)
+    g = run_gpu(dec, s, lam, 0, lam=True)
+    orc = oracle_decode_conditioned(oc, s, lam, t=t, max_iter_local=T, max_iter_global=T, local_osd=1, bp=bp)
+    res = compare(orc, g, oc.n)
+    well = ~orc["ill"]
+    assert np.array_equal(g["stats"][well, 7], orc["osd_views"][well])
+    log(f"[osd] {name} t={t} p={p} T={T} bp={bp}: {res['bad']} differ, {res['tie']} ill-conditioned, "
+        f"well-conditioned share {well.mean():.2f}, OSD views per shot {orc['osd_views'].mean():.1f}, "
+        f"worst ok |dLLR| {res['worst_ok']:.2e}")
+    assert not res["unexplained"], res["detail"]
+    assert well.mean() >= min_well
+
+
+def test_local_osd_forms_identical_and_limits():
+    import paper_2605_17796_amd as P
+    torch = torch_dev()
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_local=50, max_iter_global=50, local_post=1, max_shots=2048)
+    e, s, lam = bitflip_inputs(oc, 400, 0.05, seed=5)
+    s = _gpu_syndrome(dec, e)
+    runs = {}
+    for form in (2, 1):
+        dec.set_schedule(specialized=form)
+        assert dec.get_schedule()["specialized"] == form
+        runs[form] = run_gpu(dec, s, lam, 0, lam=True)
+    for k in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(runs[1][k], runs[2][k]), k
+    # the precompiled kernels have no OSD-0: schedules keep the compiled form
+    dec.set_schedule(specialized=0, fused=1)
+    sc = dec.get_schedule()
+    assert sc["fused"] == 0 and sc["specialized"] in (1, 2)
+    st = torch.from_numpy(s.view(np.int64)).cuda()
+    pr = torch.from_numpy(lam).cuda()
+    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
+        dec.decode(st, pr, plain=True)
+    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
+        gpu_decoder(spec, local_post=1, stage=2)

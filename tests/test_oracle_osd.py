@@ -26,11 +26,11 @@ def _col_ints(H):
 
 
 def brute_osd0(H, s, L):
-    """Information set = the first columns, in order of L ascending (ties by
-    position), that raise the GF(2) rank; the estimate is the one pattern on
-    the information set whose syndrome is s (enumerated)."""
+    """Information set = the first columns, in order of round(64 L)
+    ascending (ties by position), that raise the GF(2) rank; the estimate is
+    the one pattern on the information set whose syndrome is s (enumerated)."""
     cols = _col_ints(H)
-    order = sorted(range(H.shape[1]), key=lambda j: (L[j], j))
+    order = sorted(range(H.shape[1]), key=lambda j: (np.rint(64.0 * L[j]), j))
     info, chosen = [], []
     for j in order:
         if _gf2_rank(chosen + [cols[j]]) > len(chosen):
@@ -60,7 +60,7 @@ def test_osd0_is_the_information_set_solution(name):
         H = oc.hloc(t)
         for trial in range(12):
             s = rng.integers(0, 2, size=H.shape[0]).astype(np.uint8)
-            # reliabilities with ties (saturated values) and distinct values
+            # reliabilities with ties (saturated values, equal keys) and distinct values
             L = np.round(rng.uniform(-3, 3, size=H.shape[1]), 1 if trial % 2 else 6)
             L[rng.random(H.shape[1]) < 0.2] = 30.0
             e, ok = o.osd0(H, s, L)
