@@ -381,6 +381,17 @@ def main():
                                           "converged": round(float(sst[:, 0].mean()), 4),
                                           "mean_global_iters": round(float(sst[:, 1].mean()), 2)}
         del sdec, sout
+        odec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
+                         ms_scale=0.75, alpha=1.0, local_post=1)
+        oout = odec.alloc_outputs(shots)
+        odec.decode(synd_pool[0], lam, out=oout)
+        ow, _ = timed(torch, lambda i: odec.decode(synd_pool[i % pool_batches], lam, out=oout), 2)
+        ost = oout["stats"].cpu().numpy()
+        variants["local_osd0_A5_p005"] = {"shots_per_s": round(2 * shots / ow, 1),
+                                         "converged": round(float(ost[:, 0].mean()), 4),
+                                         "mean_global_iters": round(float(ost[:, 1].mean()), 2),
+                                         "osd_views_per_shot": round(float(ost[:, 7].mean()), 2)}
+        del odec, oout
         s02 = syndromes(torch, dec, n, shots, 0.02, seed=1500)
         lam02 = torch.full((shots,), float(channel_llr(0.02)), dtype=torch.float32, device="cuda")
         sweep = []
