@@ -600,10 +600,11 @@ int oracle_bp(int rows, int cols, const uint8_t *H, const uint8_t *s, const doub
  * estimate is the solution supported on the information set.  Returns 0, or
  * -1 when s is not in the column space of H (e is then all zero). */
 int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L, uint8_t *e) {
-    int order[64], pivcol[64];
-    uint8_t M[64][65];
-    if (rows > 64 || cols > 64) return -1;
-    double key[64];
+    const int words = cols / 64 + 1;          /* bit `cols` holds s */
+    int *order = (int *)malloc(sizeof(int) * (size_t)cols);
+    int *pivcol = (int *)malloc(sizeof(int) * (size_t)(rows > 0 ? rows : 1));
+    double *key = (double *)malloc(sizeof(double) * (size_t)cols);
+    uint64_t *M = (uint64_t *)calloc((size_t)rows * words, sizeof(uint64_t));
     for (int j = 0; j < cols; j++) {
         order[j] = j;
         key[j] = nearbyint(L[j] * 64.0);       /* round half to even */
@@ -613,28 +614,42 @@ int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const do
         while (b > 0 && key[order[b - 1]] > key[x]) { order[b] = order[b - 1]; b--; }
         order[b] = x;
     }
+    /* augmented rows [H | s], bit-packed */
     for (int r = 0; r < rows; r++) {
-        for (int j = 0; j < cols; j++) M[r][j] = H[(size_t)r * cols + j];
-        M[r][cols] = s[r];
+        uint64_t *row = M + (size_t)r * words;
+        for (int j = 0; j < cols; j++)
+            if (H[(size_t)r * cols + j]) row[j >> 6] |= 1ull << (j & 63);
+        if (s[r]) row[cols >> 6] |= 1ull << (cols & 63);
     }
     int rank = 0;
     for (int t = 0; t < cols && rank < rows; t++) {
-        int c = order[t], pr = -1;
+        const int c = order[t];
+        int pr = -1;
         for (int r = rank; r < rows; r++)
-            if (M[r][c]) { pr = r; break; }
+            if ((M[(size_t)r * words + (c >> 6)] >> (c & 63)) & 1) { pr = r; break; }
         if (pr < 0) continue;                 /* dependent on the columns before it */
+        uint64_t *P = M + (size_t)rank * words;
         if (pr != rank)
-            for (int j = 0; j <= cols; j++) { uint8_t tmp = M[pr][j]; M[pr][j] = M[rank][j]; M[rank][j] = tmp; }
-        for (int r = 0; r < rows; r++)
-            if (r != rank && M[r][c])
-                for (int j = 0; j <= cols; j++) M[r][j] ^= M[rank][j];
+            for (int w = 0; w < words; w++) {
+                uint64_t tmp = M[(size_t)pr * words + w];
+                M[(size_t)pr * words + w] = P[w];
+                P[w] = tmp;
+            }
+        for (int r = 0; r < rows; r++) {
+            uint64_t *row = M + (size_t)r * words;
+            if (r != rank && ((row[c >> 6] >> (c & 63)) & 1))
+                for (int w = 0; w < words; w++) row[w] ^= P[w];
+        }
         pivcol[rank++] = c;
     }
-    memset(e, 0, (size_t)cols);
+    int ok = 1;
     for (int r = rank; r < rows; r++)
-        if (M[r][cols]) return -1;
-    for (int k = 0; k < rank; k++) e[pivcol[k]] = M[k][cols];
-    return 0;
+        if ((M[(size_t)r * words + (cols >> 6)] >> (cols & 63)) & 1) ok = 0;
+    memset(e, 0, (size_t)cols);
+    if (ok)
+        for (int k = 0; k < rank; k++) e[pivcol[k]] = (uint8_t)((M[(size_t)k * words + (cols >> 6)] >> (cols & 63)) & 1);
+    free(order); free(pivcol); free(key); free(M);
+    return ok ? 0 : -1;
 }
 
 /* ------------------------------------------------------------------ */
@@ -735,6 +750,9 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
         if (p->stage == OR_STAGE_FULL) {
             /* Phase 3: global BP with the regularised prior */
             it_g = bp_run(glob, s, lamp, p, p->max_iter_global, Lg, eg, &conv, &margin, &wg);
+            /* global post-processing: OSD-0 on H_t with the global posteriors
+             * where global BP left the syndrome unsatisfied */
+            if (p->global_osd && !conv && oracle_osd0(m, n, c->H[type], s, Lg, eg) == 0) conv = 2;
             if (post)
                 for (int i = 0; i < n; i++) post[(size_t)shot * n + i] = Lg[i];
             if (ehat) {

@@ -62,6 +62,9 @@ typedef struct {
      * posteriors as reliabilities); its estimate satisfies the local
      * syndrome, so the view counts as converged for the confidence boost. */
     int    local_osd;
+    /* 1: where global BP ends with H e != s, OSD-0 on H with the global
+     * posteriors as reliabilities replaces e (stats converged = 2). */
+    int    global_osd;
 } oracle_params;
 
 /* info[] layout for oracle_info */
@@ -87,7 +90,7 @@ void oracle_syndrome(const oracle_code *c, int type, int shots, const uint64_t *
 
 /* Full LEAD decode of `shots` syndromes.  prior: shots x n channel LLRs.
  * Outputs (any may be NULL): ehat packed, post (L_post), lam (lambda'),
- * stats shots x 6 {converged, global_iters, local_iters_sum, local_iters_max,
+ * stats shots x 6 {converged (1: by global BP, 2: by OSD-0), global_iters, local_iters_sum, local_iters_max,
  * local_converged_views (by BP), views resolved by OSD-0}, margin (min |mu|,
  * |L| seen), local_llr
  * (shots x order x delta^2 local posteriors). */

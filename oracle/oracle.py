@@ -25,14 +25,14 @@ class Params(C.Structure):
                 ("max_iter_local", C.c_int), ("max_iter_global", C.c_int),
                 ("llr_clamp", C.c_double), ("early_exit", C.c_int), ("stage", C.c_int),
                 ("boost", C.c_int), ("perturb", C.c_double), ("perturb_seed", C.c_uint64),
-                ("local_osd", C.c_int)]
+                ("local_osd", C.c_int), ("global_osd", C.c_int)]
 
 
 def params(alpha=1.0, bp=MINSUM, ms_scale=0.75, max_iter_local=32, max_iter_global=32,
            llr_clamp=30.0, early_exit=1, stage=FULL, boost=1, perturb=0.0, perturb_seed=0,
-           local_osd=0) -> Params:
+           local_osd=0, global_osd=0) -> Params:
     return Params(alpha, bp, ms_scale, max_iter_local, max_iter_global, llr_clamp,
-                  early_exit, stage, boost, perturb, perturb_seed, local_osd)
+                  early_exit, stage, boost, perturb, perturb_seed, local_osd, global_osd)
 
 
 _lib = None

@@ -103,3 +103,70 @@ def test_local_osd_in_lead(name):
         assert np.array_equal(osd[k][same], base[k][same])
     assert np.all(osd["lam"] <= base["lam"] + 1e-12)
     assert np.any(osd["lam"] < base["lam"] - 1e-6)
+
+
+def _greedy_information_set(H, L):
+    """Columns in order of round(64 L) ascending (ties by position) that
+    raise the GF(2) rank, with an incremental basis keyed by lowest set bit."""
+    cols = _col_ints(H)
+    order = sorted(range(H.shape[1]), key=lambda j: (np.rint(64.0 * L[j]), j))
+    basis, info = {}, []
+    for j in order:
+        v = cols[j]
+        while v:
+            low = v & -v
+            if low in basis:
+                v ^= basis[low]
+            else:
+                basis[low] = v
+                info.append(j)
+                break
+    return set(info)
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_osd0_on_the_global_matrix(name):
+    """OSD-0 on H_t (rank below the row count): the estimate reproduces the
+    syndrome and lies on the greedy information set, where the solution is
+    unique because those columns are independent."""
+    from oracle import oracle as o
+    _, oc = code_pair(name)
+    rng = np.random.default_rng(13)
+    for t in (0, 1):
+        H = oc.H(t)
+        for trial in range(3):
+            e0 = (rng.random(H.shape[1]) < 0.05).astype(np.uint8)
+            s = (H.astype(np.int64) @ e0 % 2).astype(np.uint8)
+            L = rng.uniform(-2, 5, size=H.shape[1])
+            L[rng.random(H.shape[1]) < 0.3] = 30.0
+            e, ok = o.osd0(H, s, L)
+            assert ok
+            assert np.array_equal((H.astype(np.int64) @ e) % 2, s)
+            info = _greedy_information_set(H, L)
+            assert set(np.nonzero(e)[0]) <= info
+            assert len(info) == oc.info.rank[t]
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_global_osd_in_lead(name):
+    """With OSD-0 after global BP every shot ends with H e = s: shots global BP
+    resolved are unchanged, the others report converged = 2."""
+    from oracle import oracle as o
+    spec, oc = code_pair(name)
+    T = {"T": 32, "M": 50}[name]
+    shots = 30
+    e = bitflip_packed(shots, oc.n, 0.05, seed=29)
+    s = oc.syndrome(e)
+    lam = np.full(shots, float(channel_llr(0.05)))
+    base = oc.decode(s, lam, p=o.params(max_iter_local=T, max_iter_global=T))
+    gosd = oc.decode(s, lam, p=o.params(max_iter_local=T, max_iter_global=T, global_osd=1))
+    conv = base["stats"][:, 0] == 1
+    assert np.array_equal(gosd["stats"][conv, 0], base["stats"][conv, 0])
+    assert np.all(gosd["stats"][~conv, 0] == 2) and (~conv).any()
+    assert np.array_equal(gosd["ehat"][conv], base["ehat"][conv])
+    assert np.array_equal(gosd["post"], base["post"])
+    H = oc.H()
+    from lead_inputs import unpack_bits
+    eh = unpack_bits(gosd["ehat"], oc.n)
+    sb = unpack_bits(s, oc.m())
+    assert np.array_equal((eh.astype(np.int64) @ H.T) % 2, sb)
