@@ -699,6 +699,7 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
     double *lamp = (double *)malloc(sizeof(double) * (size_t)n);
     double *Lg = (double *)malloc(sizeof(double) * (size_t)n);
     uint8_t *eg = (uint8_t *)malloc((size_t)n);
+    uint8_t *eo = (uint8_t *)malloc((size_t)n);
 
     for (int shot = 0; shot < shots; shot++) {
         const uint64_t *sw = synd + (size_t)shot * synd_words;
@@ -751,8 +752,12 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             /* Phase 3: global BP with the regularised prior */
             it_g = bp_run(glob, s, lamp, p, p->max_iter_global, Lg, eg, &conv, &margin, &wg);
             /* global post-processing: OSD-0 on H_t with the global posteriors
-             * where global BP left the syndrome unsatisfied */
-            if (p->global_osd && !conv && oracle_osd0(m, n, c->H[type], s, Lg, eg) == 0) conv = 2;
+             * where global BP left the syndrome unsatisfied (when s is not
+             * in the column space of H_t, BP's estimate stays) */
+            if (p->global_osd && !conv && oracle_osd0(m, n, c->H[type], s, Lg, eo) == 0) {
+                memcpy(eg, eo, (size_t)n);
+                conv = 2;
+            }
             if (post)
                 for (int i = 0; i < n; i++) post[(size_t)shot * n + i] = Lg[i];
             if (ehat) {
@@ -768,7 +773,7 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
         if (margin_out) margin_out[shot] = margin;
     }
     free(s); free(sv); free(lamv); free(Lv); free(ev); free(pall);
-    free(lamp); free(Lg); free(eg);
+    free(lamp); free(Lg); free(eg); free(eo);
     work_free(&wl); work_free(&wg);
     return 0;
 }
@@ -783,11 +788,17 @@ int oracle_global_bp(const oracle_code *c, int type, const oracle_params *p, int
     uint8_t *s = (uint8_t *)malloc((size_t)m);
     double *Lg = (double *)malloc(sizeof(double) * (size_t)n);
     uint8_t *eg = (uint8_t *)malloc((size_t)n);
+    uint8_t *eo = (uint8_t *)malloc((size_t)n);
     for (int shot = 0; shot < shots; shot++) {
         const uint64_t *sw = synd + (size_t)shot * synd_words;
         for (int i = 0; i < m; i++) s[i] = (uint8_t)get_bit(sw, i);
         int conv = 0;
         int it = bp_run(glob, s, prior + (size_t)shot * n, p, p->max_iter_global, Lg, eg, &conv, NULL, &wg);
+        /* BP followed by OSD-0 where BP misses the syndrome */
+        if (p->global_osd && !conv && oracle_osd0(m, n, c->H[type], s, Lg, eo) == 0) {
+            memcpy(eg, eo, (size_t)n);
+            conv = 2;
+        }
         if (post) for (int i = 0; i < n; i++) post[(size_t)shot * n + i] = Lg[i];
         if (ehat) {
             uint64_t *ew = ehat + (size_t)shot * ehat_words;
@@ -796,7 +807,7 @@ int oracle_global_bp(const oracle_code *c, int type, const oracle_params *p, int
         }
         if (stats) { stats[(size_t)shot * 2] = conv; stats[(size_t)shot * 2 + 1] = it; }
     }
-    free(s); free(Lg); free(eg);
+    free(s); free(Lg); free(eg); free(eo);
     work_free(&wg);
     return 0;
 }

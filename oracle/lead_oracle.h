@@ -20,7 +20,8 @@
  *                  syndromes never converge, boost is a no-op for BP, local
  *                  slices against computation trees, equivariance under the
  *                  centre of D_6
- *   oracle_global_bp  the same BP routine as oracle_bp; no separate pin
+ *   oracle_global_bp  the same BP routine as oracle_bp, and oracle_osd0;
+ *                  no separate pin
  *   margin output  diagnostic only: parity unpinned
  */
 #ifndef LEAD_ORACLE_H
@@ -113,7 +114,10 @@ void oracle_aggregate(int n, int nviews, int vsize, const int32_t *view, const d
 int  oracle_bp(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *lam,
                const oracle_params *p, int max_iter, double *L, uint8_t *e, int *conv);
 
-/* Standalone global BP with channel priors (no local phase). */
+/* Standalone global BP with channel priors (no local phase), followed by
+ * OSD-0 on H_t where BP misses the syndrome when p->global_osd is set
+ * (converged = 2 then; a syndrome outside the column space keeps BP's
+ * estimate). */
 int  oracle_global_bp(const oracle_code *c, int type, const oracle_params *p, int shots,
                       const uint64_t *synd, int synd_words, const double *prior,
                       uint64_t *ehat, int ehat_words, double *post, int32_t *stats);

@@ -170,3 +170,51 @@ def test_global_osd_in_lead(name):
     eh = unpack_bits(gosd["ehat"], oc.n)
     sb = unpack_bits(s, oc.m())
     assert np.array_equal((eh.astype(np.int64) @ H.T) % 2, sb)
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_global_osd_keeps_bp_on_unreachable_syndromes(name):
+    """A syndrome outside the column space of H_t (random bits, rank < m) has
+    no OSD-0 solution: the estimate and the stopping report stay BP's."""
+    from oracle import oracle as o
+    _, oc = code_pair(name)
+    rng = np.random.default_rng(31)
+    shots = 6
+    H = oc.H()
+    sb = (rng.random((shots, H.shape[0])) < 0.3).astype(np.uint8)
+    from lead_inputs import pack_bits
+    s = pack_bits(sb)
+    lam = np.full(shots, float(channel_llr(0.05)))
+    base = oc.decode(s, lam, p=o.params(max_iter_local=10, max_iter_global=10))
+    gosd = oc.decode(s, lam, p=o.params(max_iter_local=10, max_iter_global=10, global_osd=1))
+    unreach = np.array([not o.osd0(H, sb[i], np.zeros(H.shape[1]))[1] for i in range(shots)])
+    assert unreach.sum() >= shots // 2
+    assert np.all(base["stats"][unreach, 0] == 0)
+    assert np.array_equal(gosd["stats"][unreach], base["stats"][unreach])
+    assert np.array_equal(gosd["ehat"][unreach], base["ehat"][unreach])
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_global_bp_then_osd(name):
+    """BP-OSD-0 on H_t alone: shots BP resolves are untouched; the others
+    take the OSD-0 solution of H_t e = s ranked by BP's posteriors."""
+    from oracle import oracle as o
+    from lead_inputs import unpack_bits
+    _, oc = code_pair(name)
+    shots = 24
+    e = bitflip_packed(shots, oc.n, 0.06, seed=37)
+    s = oc.syndrome(e)
+    lam = np.full(shots, float(channel_llr(0.06)))
+    base = oc.global_bp(s, lam, p=o.params(max_iter_global=12))
+    gosd = oc.global_bp(s, lam, p=o.params(max_iter_global=12, global_osd=1))
+    conv = base["stats"][:, 0] == 1
+    assert (~conv).any()
+    assert np.array_equal(gosd["ehat"][conv], base["ehat"][conv])
+    assert np.all(gosd["stats"][~conv, 0] == 2)
+    assert np.array_equal(gosd["post"], base["post"])
+    H = oc.H()
+    sb = unpack_bits(s, oc.m())
+    eh = unpack_bits(gosd["ehat"], oc.n)
+    for i in np.nonzero(~conv)[0]:
+        ref, ok = o.osd0(H, sb[i], base["post"][i])
+        assert ok and np.array_equal(eh[i], ref)
