@@ -392,6 +392,19 @@ def main():
                                          "mean_global_iters": round(float(ost[:, 1].mean()), 2),
                                          "osd_views_per_shot": round(float(ost[:, 7].mean()), 2)}
         del odec, oout
+        # OSD-0 on H_t after global BP: LEAD with it, and BP-OSD-0 on H_t alone
+        for key, kw in (("global_osd0_A5_p005", {}), ("bp_osd0_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL})):
+            gd2 = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
+                            ms_scale=0.75, alpha=1.0, global_post=1, **kw)
+            go2 = gd2.alloc_outputs(shots)
+            gd2.decode(synd_pool[0], lam, out=go2)
+            w2, _ = timed(torch, lambda i: gd2.decode(synd_pool[i % pool_batches], lam, out=go2), 2)
+            st2 = go2["stats"].cpu().numpy()
+            variants[key] = {"shots_per_s": round(2 * shots / w2, 1),
+                             "converged_by_bp": round(float((st2[:, 0] == 1).mean()), 4),
+                             "resolved_by_osd": round(float((st2[:, 0] == 2).mean()), 4),
+                             "mean_global_iters": round(float(st2[:, 1].mean()), 2)}
+            del gd2, go2
         s02 = syndromes(torch, dec, n, shots, 0.02, seed=1500)
         lam02 = torch.full((shots,), float(channel_llr(0.02)), dtype=torch.float32, device="cuda")
         sweep = []

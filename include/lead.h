@@ -150,11 +150,25 @@ typedef struct {
                                  in lead_decode, batches and the server;
                                  lead_decode_plain and stage GLOBAL are
                                  min-sum only (LEAD_E_UNSUPPORTED)            */
+    int32_t global_post;      /* 1: a shot whose global BP ends with H e != s
+                                 is followed by OSD-0 on H_t with the global
+                                 posteriors as reliabilities (ranked as for
+                                 local_post, round(64 L) ascending, ties in
+                                 qubit order); it then reports converged = 2
+                                 and its estimate is the OSD-0 solution.  A
+                                 syndrome outside the column space of H_t
+                                 keeps BP's estimate and report.  Stages FULL
+                                 and GLOBAL, kernels compiled for the code,
+                                 codes with ceil(m/256) * ceil(n/64) <= 64
+                                 (LEAD_E_UNSUPPORTED otherwise, and from
+                                 lead_decode_plain).  0: none                  */
 } lead_params;
 
 /* Per-shot statistics (32 bytes). */
 typedef struct {
-    int32_t converged;              /* global H e = s reached (0 in LOCAL stage)   */
+    int32_t converged;              /* 1: global BP reached H e = s; 2: reached by
+                                       OSD-0 after it (global_post); 0 otherwise,
+                                       and in the LOCAL stage                    */
     int32_t global_iters;           /* global BP iterations run                    */
     int32_t local_iters_sum;        /* sum over vertices of local iterations       */
     int32_t local_iters_max;

@@ -44,6 +44,11 @@ struct lead_decoder {
     std::shared_ptr<const lead::jit::Kernels> spec;
     uint32_t *d_pv = nullptr;
     uint64_t *d_fown = nullptr;
+    // global OSD-0: H_t as row lists, and posterior / statistics buffers for
+    // calls that do not ask for them (ws_shots shots)
+    int32_t *d_rptr = nullptr, *d_ridx = nullptr;
+    float *d_gpost = nullptr;
+    lead_shot_stats *d_gstats = nullptr;
     // schedule and split-path workspace (for ws_shots shots)
     lead_schedule sched{};
     int64_t ws_shots = 0;
@@ -89,6 +94,9 @@ lead_status check_params(const lead_params *p) {
     if (p->local_post != 0 && p->local_post != 1) return fail(LEAD_E_ARG, "bad local_post");
     if (p->local_post && p->stage == LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL has no local phase to post-process");
+    if (p->global_post != 0 && p->global_post != 1) return fail(LEAD_E_ARG, "bad global_post");
+    if (p->global_post && p->stage == LEAD_STAGE_LOCAL)
+        return fail(LEAD_E_UNSUPPORTED, "stage LOCAL has no global BP to post-process");
     return LEAD_OK;
 }
 
@@ -102,6 +110,25 @@ bool sum_product(const lead_decoder *d) { return d->params.bp == LEAD_BP_SUMPROD
 
 // Sum-product and OSD-0 run only on the kernels compiled for the code.
 bool needs_spec(const lead_decoder *d) { return sum_product(d) || d->params.local_post != 0; }
+
+bool osd_ready(const lead_decoder *d) { return d->spec && d->spec->osd && d->d_rptr; }
+
+// Posterior and statistics buffers of the global OSD-0 for calls that pass
+// none (allocated once, when global_post is first set).
+hipError_t ensure_osd_workspace(lead_decoder *d) {
+    hipError_t e = hipSuccess;
+    if (!d->d_gpost) e = hipMalloc(&d->d_gpost, sizeof(float) * (size_t)d->ws_shots * d->n);
+    if (e == hipSuccess && !d->d_gstats) e = hipMalloc(&d->d_gstats, sizeof(lead_shot_stats) * (size_t)d->ws_shots);
+    return e;
+}
+
+// OSD-0 on H_t for the shots of `a` that global BP left unresolved: one
+// 256-lane workgroup per shot (the others exit at once).
+hipError_t launch_osd(const lead_decoder *d, lead::DecodeArgs a, hipStream_t s) {
+    lead::OsdArgs o{d->d_rptr, d->d_ridx};
+    void *args[] = {&a, &o};
+    return hipModuleLaunchKernel(d->spec->osd, (unsigned)a.shots, 1, 1, 256, 1, 1, 0, s, args, nullptr);
+}
 
 // The specialised form a schedule asks for, or the one compiled when it
 // asks for the other (0: precompiled kernels).  Sum-product has one form.
@@ -250,8 +277,10 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
     // global BP alone runs on the fused per-shot kernel (there is no Phase 1)
     const bool gonly = d->params.stage == LEAD_STAGE_GLOBAL;
     const bool split = !d->sched.fused && !gonly;
+    // global OSD-0 after global BP (its buffers hold ws_shots shots)
+    const bool gpost = d->params.global_post && stage != LEAD_STAGE_LOCAL;
     // equal chunks of at most ws_shots (no small tail launch)
-    const int64_t nchunks = split ? (shots + d->ws_shots - 1) / d->ws_shots : 1;
+    const int64_t nchunks = split || gpost ? (shots + d->ws_shots - 1) / d->ws_shots : 1;
     const int64_t step = (shots + nchunks - 1) / nchunks;
     for (int64_t off = 0; off < shots; off += step) {
         const int64_t cnt = std::min(step, shots - off);
@@ -270,8 +299,13 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         a.global_only = gonly ? 1 : 0;
         const lead::LocalArgs w = local_args(d, cnt, mode);
         std::array<hipEvent_t, 3> *ev = split ? timing_events(d, s) : nullptr;
+        if (gpost) {
+            if (!a.post) a.post = d->d_gpost;
+            if (!a.stats) a.stats = d->d_gstats;
+        }
         hipError_t e = split && use_spec(d) ? launch_spec(d, a, w, s, ev)
                                    : lead::launch_decode(d->D, d->r, a, w, split, s, ev ? ev->data() : nullptr);
+        if (e == hipSuccess && gpost) e = launch_osd(d, a, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -509,6 +543,23 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             if (e == hipSuccess) e = hipMemcpy(d->d_pv, pv.data(), sizeof(uint32_t) * pv.size(), hipMemcpyHostToDevice);
             if (e == hipSuccess)
                 e = hipMemcpy(d->d_fown, fown.data(), sizeof(uint64_t) * fown.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess && d->spec->osd) {
+                e = hipMalloc(&d->d_rptr, sizeof(int32_t) * tt.csr_ptr.size());
+                if (e == hipSuccess) e = hipMalloc(&d->d_ridx, sizeof(int32_t) * std::max<size_t>(tt.csr_idx.size(), 1));
+                if (e == hipSuccess)
+                    e = hipMemcpy(d->d_rptr, tt.csr_ptr.data(), sizeof(int32_t) * tt.csr_ptr.size(), hipMemcpyHostToDevice);
+                if (e == hipSuccess && !tt.csr_idx.empty())
+                    e = hipMemcpy(d->d_ridx, tt.csr_idx.data(), sizeof(int32_t) * tt.csr_idx.size(),
+                                  hipMemcpyHostToDevice);
+            }
+        }
+        if (e == hipSuccess && d->params.global_post) {
+            if (!osd_ready(d.get())) {
+                jerr = d->spec ? "the code is too large for the global OSD-0 kernel" : jerr;
+                e = hipErrorNotSupported;
+            } else {
+                e = ensure_osd_workspace(d.get());
+            }
         }
         d->sched.specialized = spec_form(d.get(), lead::jit::kExplicit);
         if (e == hipErrorNotSupported) {
@@ -517,6 +568,10 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             (void)hipFree(d->d_Lv);
             (void)hipFree(d->d_vflag);
             (void)hipFree(d->d_counter);
+            (void)hipFree(d->d_pv);
+            (void)hipFree(d->d_fown);
+            (void)hipFree(d->d_rptr);
+            (void)hipFree(d->d_ridx);
             return fail(LEAD_E_UNSUPPORTED, "sum-product or OSD-0 needs the kernels compiled for the code: " + jerr);
         }
     }
@@ -528,6 +583,10 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
         (void)hipFree(d->d_counter);
         (void)hipFree(d->d_pv);
         (void)hipFree(d->d_fown);
+        (void)hipFree(d->d_rptr);
+        (void)hipFree(d->d_ridx);
+        (void)hipFree(d->d_gpost);
+        (void)hipFree(d->d_gstats);
         return hip_fail(e, "device allocation");
     }
     *out = d.release();
@@ -574,12 +633,18 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
     if (!d) return fail(LEAD_E_ARG, "decoder is NULL");
     lead_status st = check_params(params);
     if (st != LEAD_OK) return st;
+    if (params->global_post) {
+        if (!osd_ready(d)) return fail(LEAD_E_UNSUPPORTED, "no global OSD-0 kernel for this code");
+        hipError_t e = ensure_osd_workspace(d);
+        if (e != hipSuccess) return hip_fail(e, "OSD-0 workspace allocation");
+    }
     if (params->bp != d->params.bp) {
         // the other BP flavour needs the other set of compiled kernels
         std::string jerr;
         auto k = lead::jit::load(*d->code, d->type, d->device, params->bp == LEAD_BP_SUMPRODUCT, jerr);
         if (!k && params->bp == LEAD_BP_SUMPRODUCT) return fail(LEAD_E_UNSUPPORTED, "sum-product: " + jerr);
         if (k && !d->d_pv) return fail(LEAD_E_UNSUPPORTED, "no partner tables");
+        if (params->global_post && !(k && k->osd)) return fail(LEAD_E_UNSUPPORTED, "no global OSD-0 kernel");
         d->spec = k;
         d->params = *params;
         d->sched.specialized = spec_form(d, lead::jit::kExplicit);
@@ -649,6 +714,10 @@ void lead_decoder_destroy(lead_decoder *d) {
     (void)hipFree(d->d_counter);
     (void)hipFree(d->d_pv);
     (void)hipFree(d->d_fown);
+    (void)hipFree(d->d_rptr);
+    (void)hipFree(d->d_ridx);
+    (void)hipFree(d->d_gpost);
+    (void)hipFree(d->d_gstats);
     (void)drain_timing(d);
     free_plain(d);
     delete d;
@@ -672,7 +741,8 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
                               float *post, float *lam, lead_shot_stats *stats, void *stream) {
     lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
     if (st != LEAD_OK || shots == 0) return st;
-    if (needs_spec(d)) return fail(LEAD_E_UNSUPPORTED, "the plain form runs min-sum without OSD-0 only");
+    if (needs_spec(d) || d->params.global_post)
+        return fail(LEAD_E_UNSUPPORTED, "the plain form runs min-sum without OSD-0 only");
     if (d->params.stage == LEAD_STAGE_LOCAL)
         return lead_decode(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream);
     hipStream_t s = (hipStream_t)stream;

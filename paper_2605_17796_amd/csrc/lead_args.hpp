@@ -64,4 +64,11 @@ struct SpecArgs {
     const uint64_t *fown;
 };
 
+// Tables of the global OSD-0 kernel: H_t as row lists (CSR, rows g*r + rho,
+// columns ascending).
+struct OsdArgs {
+    const int32_t *rptr;
+    const int32_t *ridx;
+};
+
 }  // namespace lead

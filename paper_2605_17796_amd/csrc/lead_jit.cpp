@@ -70,6 +70,11 @@ int workgroup_for(int order) { return ((order + 63) / 64) * 64; }
 
 }  // namespace
 
+bool osd_fits(const Code &c, int t) {
+    const int m = c.order * c.t[t].r, W = (c.n + 63) / 64, RPL = (m + 255) / 256;
+    return m > 0 && c.n > 0 && RPL * W <= kOsdMaxWords && RPL <= 32;
+}
+
 std::string source(const Code &c, int t, bool sp) {
     const TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
@@ -112,6 +117,15 @@ std::string source(const Code &c, int t, bool sp) {
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
+    }
+    if (osd_fits(c, t)) {
+        const int m = c.order * tt.r;
+        int sortn = 1;
+        while (sortn < c.n) sortn <<= 1;
+        o << "struct LeadGlobal {\n    static constexpr int M = " << m << ", NQ = " << c.n << ", W = " << (c.n + 63) / 64
+          << ", RPL = " << (m + 255) / 256 << ", RANK = " << tt.rank << ", SORTN = " << sortn << ";\n};\n"
+          << "extern \"C\" __global__ void __launch_bounds__(256) lead_spec_osd(lead::DecodeArgs a, lead::OsdArgs o) "
+             "{ lead_spec::osd_global_body<LeadGlobal>(a, o); }\n";
     }
     return o.str();
 }
@@ -200,6 +214,7 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
                 k->local_waves_per_cu[form - 1][pm] = nb;
         }
     }
+    if (e == hipSuccess && osd_fits(c, t)) e = hipModuleGetFunction(&k->osd, k->module, "lead_spec_osd");
     if (e != hipSuccess) {
         err = std::string("module load: ") + hipGetErrorString(e);
         if (k->module) (void)hipModuleUnload(k->module);

@@ -26,11 +26,17 @@ constexpr int kForms = 3;
 // form (one VGPR per message).
 constexpr int kExplicitMaxEdges = 128;
 
+// The global OSD-0 kernel keeps ceil(m/256) rows of ceil(n/64) words per lane
+// in registers; it is compiled when that product is at most this.
+constexpr int kOsdMaxWords = 64;
+bool osd_fits(const Code &c, int t);
+
 struct Kernels {
     hipModule_t module = nullptr;
     // [form - 1][prior mode]: Phase 1 queue kernel for per-shot / per-qubit priors
     hipFunction_t local[kForms][2] = {};
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
+    hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
     bool has[kForms] = {};               // [form - 1]: compiled
     int wg = 0;                          // workgroup size of `global`
     int spw = 0;                         // shots per workgroup of `global`

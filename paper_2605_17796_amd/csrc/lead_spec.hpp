@@ -764,4 +764,171 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     }
 }
 
+// ---------------------------------------------------------------------------
+// Global OSD-0 (post-processing of global BP), one 256-lane workgroup per
+// shot that global BP left with H e != s.  G fixes the global sizes:
+//   G::M (checks), G::NQ (qubits), G::W = ceil(NQ/64), G::RPL = ceil(M/256),
+//   G::RANK (GF(2) rank of H), G::SORTN (power of two >= NQ).
+// Qubits are ranked by round(64 L) of their global posterior, ascending,
+// equal keys in index order (bitonic sort of (key, index) pairs in LDS).
+// Lane l holds rows l, l + 256, ... of [H | s] with the columns permuted into
+// that order, so Gauss-Jordan elimination over columns t = 0, 1, ... selects
+// the greedy information set: a column gets a pivot exactly when it is
+// independent of the columns before it.  The pivot row is the lowest-numbered
+// row that is not yet a pivot row and has bit t (any choice gives the same
+// information set, and the solution on it is unique); it is broadcast
+// through LDS and cleared from every other row.  Once the rank is reached,
+// the estimate is e[order[t_k]] = s-bit of pivot row k, provided that every
+// row without a pivot has s-bit 0 (otherwise the syndrome is not in the
+// column space of H and BP's estimate and report stay).
+template <class G>
+__device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead::OsdArgs &o) {
+    constexpr int WG = 256, W = G::W, RPL = G::RPL, NQ = G::NQ, M = G::M, SORTN = G::SORTN;
+    static_assert(RPL <= 32 && NQ <= SORTN, "OSD-0 sizes");
+    __shared__ uint64_t keys[SORTN];
+    __shared__ uint64_t prow[W];
+    __shared__ int32_t inv[NQ];                  // qubit -> rank position
+    __shared__ int32_t wmin[2][WG / 64];         // per-wave pivot candidates, by column parity
+    __shared__ int32_t flags[2];                 // pivot s-bit, syndrome unreachable
+    __shared__ uint32_t ebits[(NQ + 31) / 32];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t shot = blockIdx.x;
+    if (shot >= a.shots) return;
+    lead::ShotStats *stp = reinterpret_cast<lead::ShotStats *>(a.stats) + shot;
+    if (stp->converged != 0) return;             // uniform per workgroup
+    const float *Lp = a.post + shot * a.n;
+
+    // ---- ranking.  Key: rint(64 L) (+0 for -0) as an order-preserving
+    // unsigned word, then the qubit index.
+    for (int i = tid; i < SORTN; i += WG) {
+        uint64_t k = ~0ull;
+        if (i < NQ) {
+            const float q = __builtin_rintf(Lp[i] * 64.f) + 0.f;
+            uint32_t u = __float_as_uint(q);
+            u = (u >> 31) ? ~u : (u | 0x80000000u);
+            k = ((uint64_t)u << 32) | (uint32_t)i;
+        }
+        keys[i] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= SORTN; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < SORTN / 2; i += WG) {
+                const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                const uint64_t x = keys[lo], y = keys[hi];
+                if ((x > y) == ((lo & size) == 0)) {
+                    keys[lo] = y;
+                    keys[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    for (int t = tid; t < NQ; t += WG) inv[(uint32_t)keys[t]] = t;
+    for (int i = tid; i < (NQ + 31) / 32; i += WG) ebits[i] = 0u;
+    __syncthreads();
+
+    // ---- this lane's rows of [H | s], columns in rank order
+    uint64_t row[RPL][W];
+    uint32_t sb = 0u, piv = 0u;
+    int pcol[RPL];
+    const uint64_t *srow = a.synd + shot * a.synd_words;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        pcol[i] = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) row[i][k] = 0ull;
+        const int r = tid + WG * i;
+        if (r < M) {
+            sb |= (uint32_t)((srow[r >> 6] >> (r & 63)) & 1ull) << i;
+            for (int x = o.rptr[r]; x < o.rptr[r + 1]; ++x) {
+                const int t = inv[o.ridx[x]];
+                const uint64_t bit = 1ull << (t & 63);
+#pragma unroll
+                for (int k = 0; k < W; ++k) row[i][k] |= (k == (t >> 6)) ? bit : 0ull;
+            }
+        }
+    }
+
+    // ---- Gauss-Jordan over the ranked columns
+    int rank = 0, par = 0;
+    for (int w = 0; w < W && rank < G::RANK; ++w) {
+        uint64_t cur[RPL];   // word w of each row, kept in step with row[][w]
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            cur[i] = row[i][0];
+#pragma unroll
+            for (int k = 1; k < W; ++k) cur[i] = (k == w) ? row[i][k] : cur[i];
+        }
+        const int bmax = (w == W - 1) ? NQ - 64 * (W - 1) : 64;
+        for (int b = 0; b < bmax && rank < G::RANK; ++b, par ^= 1) {
+            // lowest-numbered non-pivot row with bit (w, b): rows are
+            // numbered tid + 256 i, so the first i with a candidate in any
+            // wave wins, then the lowest wave, then the lowest lane
+            int cand = 0x7fffffff;
+#pragma unroll
+            for (int i = RPL - 1; i >= 0; --i) {
+                const uint64_t bal = __ballot(!((piv >> i) & 1u) && ((cur[i] >> b) & 1ull));
+                if (bal) cand = WG * i + 64 * wave + __builtin_ctzll(bal);
+            }
+            if (lane == 0) wmin[par][wave] = cand;
+            __syncthreads();
+            int p = wmin[par][0];
+#pragma unroll
+            for (int x = 1; x < WG / 64; ++x) p = min(p, wmin[par][x]);
+            if (p == 0x7fffffff) continue;       // column t depends on the ones before it
+            const int pi = p / WG;
+            if (tid == p - WG * pi) {
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+                    if (i == pi) {
+#pragma unroll
+                        for (int k = 0; k < W; ++k) prow[k] = row[i][k];
+                        flags[0] = (int)((sb >> i) & 1u);
+                        pcol[i] = 64 * w + b;
+                    }
+                piv |= 1u << pi;
+            }
+            __syncthreads();
+            const uint32_t ps = (uint32_t)flags[0];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+                if (tid + WG * i != p && ((cur[i] >> b) & 1ull)) {
+                    // the pivot row is zero on every column before t
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+                        if (k >= w) row[i][k] ^= prow[k];
+                    cur[i] ^= prow[w];
+                    sb ^= ps << i;
+                }
+            ++rank;
+        }
+    }
+
+    // ---- the estimate, or BP's when the syndrome is not reached
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+        if (tid + WG * i < M && !((piv >> i) & 1u) && ((sb >> i) & 1u)) bad = true;
+    if (tid == 0) flags[1] = 0;
+    __syncthreads();
+    if (bad) flags[1] = 1;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+        if (((piv >> i) & 1u) && ((sb >> i) & 1u)) {
+            const int q = (int)(uint32_t)keys[pcol[i]];
+            atomicOr(&ebits[q >> 5], 1u << (q & 31));
+        }
+    __syncthreads();
+    if (flags[1] != 0) return;
+    if (a.ehat) {
+        constexpr int EW32 = (NQ + 31) / 32;
+        for (int wd = tid; wd < a.ehat_words; wd += WG) {
+            const uint64_t lo = (2 * wd < EW32) ? ebits[2 * wd] : 0u;
+            const uint64_t hi = (2 * wd + 1 < EW32) ? ebits[2 * wd + 1] : 0u;
+            a.ehat[shot * a.ehat_words + wd] = lo | (hi << 32);
+        }
+    }
+    if (tid == 0) stp->converged = 2;
+}
+
 }  // namespace lead_spec
