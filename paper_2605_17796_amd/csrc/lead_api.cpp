@@ -123,11 +123,12 @@ hipError_t ensure_osd_workspace(lead_decoder *d) {
 }
 
 // OSD-0 on H_t for the shots of `a` that global BP left unresolved: one
-// 256-lane workgroup per shot (the others exit at once).
+// workgroup per shot (the others exit at once).
 hipError_t launch_osd(const lead_decoder *d, lead::DecodeArgs a, hipStream_t s) {
     lead::OsdArgs o{d->d_rptr, d->d_ridx};
     void *args[] = {&a, &o};
-    return hipModuleLaunchKernel(d->spec->osd, (unsigned)a.shots, 1, 1, 256, 1, 1, 0, s, args, nullptr);
+    return hipModuleLaunchKernel(d->spec->osd, (unsigned)a.shots, 1, 1, (unsigned)d->spec->osd_wg, 1, 1, 0, s,
+                                 args, nullptr);
 }
 
 // The specialised form a schedule asks for, or the one compiled when it

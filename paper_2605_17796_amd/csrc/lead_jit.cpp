@@ -75,6 +75,11 @@ bool osd_fits(const Code &c, int t) {
     return m > 0 && c.n > 0 && RPL * W <= kOsdMaxWords && RPL <= 32;
 }
 
+int osd_workgroup(const Code &c, int t) {
+    const int m = c.order * c.t[t].r, RPL = (m + 255) / 256;
+    return 64 * ((m + 64 * RPL - 1) / (64 * RPL));
+}
+
 std::string source(const Code &c, int t, bool sp) {
     const TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
@@ -122,10 +127,12 @@ std::string source(const Code &c, int t, bool sp) {
         const int m = c.order * tt.r;
         int sortn = 1;
         while (sortn < c.n) sortn <<= 1;
+        const int owg = osd_workgroup(c, t);
         o << "struct LeadGlobal {\n    static constexpr int M = " << m << ", NQ = " << c.n << ", W = " << (c.n + 63) / 64
-          << ", RPL = " << (m + 255) / 256 << ", RANK = " << tt.rank << ", SORTN = " << sortn << ";\n};\n"
-          << "extern \"C\" __global__ void __launch_bounds__(256) lead_spec_osd(lead::DecodeArgs a, lead::OsdArgs o) "
-             "{ lead_spec::osd_global_body<LeadGlobal>(a, o); }\n";
+          << ", RPL = " << (m + 255) / 256 << ", WG = " << owg << ", RANK = " << tt.rank << ", SORTN = " << sortn
+          << ";\n};\n"
+          << "extern \"C\" __global__ void __launch_bounds__(" << owg
+          << ") lead_spec_osd(lead::DecodeArgs a, lead::OsdArgs o) { lead_spec::osd_global_body<LeadGlobal>(a, o); }\n";
     }
     return o.str();
 }
@@ -214,7 +221,10 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
                 k->local_waves_per_cu[form - 1][pm] = nb;
         }
     }
-    if (e == hipSuccess && osd_fits(c, t)) e = hipModuleGetFunction(&k->osd, k->module, "lead_spec_osd");
+    if (e == hipSuccess && osd_fits(c, t)) {
+        e = hipModuleGetFunction(&k->osd, k->module, "lead_spec_osd");
+        k->osd_wg = osd_workgroup(c, t);
+    }
     if (e != hipSuccess) {
         err = std::string("module load: ") + hipGetErrorString(e);
         if (k->module) (void)hipModuleUnload(k->module);

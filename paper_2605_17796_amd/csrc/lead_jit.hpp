@@ -30,6 +30,9 @@ constexpr int kExplicitMaxEdges = 128;
 // in registers; it is compiled when that product is at most this.
 constexpr int kOsdMaxWords = 64;
 bool osd_fits(const Code &c, int t);
+// Workgroup size of that kernel: the fewest whole waves that hold the m rows
+// at ceil(m/256) rows per lane.
+int osd_workgroup(const Code &c, int t);
 
 struct Kernels {
     hipModule_t module = nullptr;
@@ -37,6 +40,7 @@ struct Kernels {
     hipFunction_t local[kForms][2] = {};
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
     hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
+    int osd_wg = 0;                      // its workgroup size
     bool has[kForms] = {};               // [form - 1]: compiled
     int wg = 0;                          // workgroup size of `global`
     int spw = 0;                         // shots per workgroup of `global`

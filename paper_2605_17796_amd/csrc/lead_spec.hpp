@@ -765,30 +765,35 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
 }
 
 // ---------------------------------------------------------------------------
-// Global OSD-0 (post-processing of global BP), one 256-lane workgroup per
-// shot that global BP left with H e != s.  G fixes the global sizes:
-//   G::M (checks), G::NQ (qubits), G::W = ceil(NQ/64), G::RPL = ceil(M/256),
-//   G::RANK (GF(2) rank of H), G::SORTN (power of two >= NQ).
+// Global OSD-0 (post-processing of global BP), one workgroup per shot that
+// global BP left with H e != s.  G fixes the global sizes:
+//   G::M (checks), G::NQ (qubits), G::W = ceil(NQ/64), G::RPL (rows per lane),
+//   G::WG (lanes, 64 * ceil(M / (64 RPL))), G::RANK (GF(2) rank of H),
+//   G::SORTN (power of two >= NQ).
 // Qubits are ranked by round(64 L) of their global posterior, ascending,
 // equal keys in index order (bitonic sort of (key, index) pairs in LDS).
-// Lane l holds rows l, l + 256, ... of [H | s] with the columns permuted into
+// Lane l holds rows l, l + WG, ... of [H | s] with the columns permuted into
 // that order, so Gauss-Jordan elimination over columns t = 0, 1, ... selects
 // the greedy information set: a column gets a pivot exactly when it is
 // independent of the columns before it.  The pivot row is the lowest-numbered
 // row that is not yet a pivot row and has bit t (any choice gives the same
 // information set, and the solution on it is unique); it is broadcast
-// through LDS and cleared from every other row.  Once the rank is reached,
-// the estimate is e[order[t_k]] = s-bit of pivot row k, provided that every
-// row without a pivot has s-bit 0 (otherwise the syndrome is not in the
-// column space of H and BP's estimate and report stay).
+// through LDS and XORed into every other row that has bit t.  Only the words
+// from the current one on are kept up to date: the earlier ones are never
+// read again (the result needs only the s-bits and the pivot columns).
+// Once the rank is reached, the estimate is e[order[t_k]] = s-bit of pivot
+// row k, provided that every row without a pivot has s-bit 0 (otherwise the
+// syndrome is not in the column space of H and BP's estimate and report
+// stay).
 template <class G>
 __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead::OsdArgs &o) {
-    constexpr int WG = 256, W = G::W, RPL = G::RPL, NQ = G::NQ, M = G::M, SORTN = G::SORTN;
-    static_assert(RPL <= 32 && NQ <= SORTN, "OSD-0 sizes");
+    constexpr int WG = G::WG, NWAVE = WG / 64, W = G::W, RPL = G::RPL, NQ = G::NQ, M = G::M,
+                  SORTN = G::SORTN;
+    static_assert(RPL <= 32 && NQ <= SORTN && WG % 64 == 0 && WG * RPL >= M, "OSD-0 sizes");
     __shared__ uint64_t keys[SORTN];
     __shared__ uint64_t prow[W];
     __shared__ int32_t inv[NQ];                  // qubit -> rank position
-    __shared__ int32_t wmin[2][WG / 64];         // per-wave pivot candidates, by column parity
+    __shared__ int32_t wmin[2][NWAVE];           // per-wave pivot candidates, by step parity
     __shared__ int32_t flags[2];                 // pivot s-bit, syndrome unreachable
     __shared__ uint32_t ebits[(NQ + 31) / 32];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -849,32 +854,32 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
         }
     }
 
-    // ---- Gauss-Jordan over the ranked columns
+    // ---- Gauss-Jordan over the ranked columns, one 64-column word at a
+    // time (compile-time word index, so each step touches words w.. only)
     int rank = 0, par = 0;
-    for (int w = 0; w < W && rank < G::RANK; ++w) {
-        uint64_t cur[RPL];   // word w of each row, kept in step with row[][w]
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-            cur[i] = row[i][0];
-#pragma unroll
-            for (int k = 1; k < W; ++k) cur[i] = (k == w) ? row[i][k] : cur[i];
-        }
-        const int bmax = (w == W - 1) ? NQ - 64 * (W - 1) : 64;
+    static_for<0, W>([&](auto ww) {
+        constexpr int w = decltype(ww)::value;
+        constexpr int bmax = (w == W - 1) ? NQ - 64 * (W - 1) : 64;
         for (int b = 0; b < bmax && rank < G::RANK; ++b, par ^= 1) {
             // lowest-numbered non-pivot row with bit (w, b): rows are
-            // numbered tid + 256 i, so the first i with a candidate in any
+            // numbered tid + WG i, so the first i with a candidate in any
             // wave wins, then the lowest wave, then the lowest lane
             int cand = 0x7fffffff;
 #pragma unroll
             for (int i = RPL - 1; i >= 0; --i) {
-                const uint64_t bal = __ballot(!((piv >> i) & 1u) && ((cur[i] >> b) & 1ull));
+                const uint64_t bal = __ballot(!((piv >> i) & 1u) && ((row[i][w] >> b) & 1ull));
                 if (bal) cand = WG * i + 64 * wave + __builtin_ctzll(bal);
             }
-            if (lane == 0) wmin[par][wave] = cand;
-            __syncthreads();
-            int p = wmin[par][0];
+            if (NWAVE > 1) {
+                if (lane == 0) wmin[par][wave] = cand;
+                __syncthreads();
+            }
+            int p = cand;
+            if (NWAVE > 1) {
+                p = wmin[par][0];
 #pragma unroll
-            for (int x = 1; x < WG / 64; ++x) p = min(p, wmin[par][x]);
+                for (int x = 1; x < NWAVE; ++x) p = min(p, wmin[par][x]);
+            }
             if (p == 0x7fffffff) continue;       // column t depends on the ones before it
             const int pi = p / WG;
             if (tid == p - WG * pi) {
@@ -882,7 +887,7 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
                 for (int i = 0; i < RPL; ++i)
                     if (i == pi) {
 #pragma unroll
-                        for (int k = 0; k < W; ++k) prow[k] = row[i][k];
+                        for (int k = w; k < W; ++k) prow[k] = row[i][k];
                         flags[0] = (int)((sb >> i) & 1u);
                         pcol[i] = 64 * w + b;
                     }
@@ -892,17 +897,14 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
             const uint32_t ps = (uint32_t)flags[0];
 #pragma unroll
             for (int i = 0; i < RPL; ++i)
-                if (tid + WG * i != p && ((cur[i] >> b) & 1ull)) {
-                    // the pivot row is zero on every column before t
+                if (tid + WG * i != p && ((row[i][w] >> b) & 1ull)) {
 #pragma unroll
-                    for (int k = 0; k < W; ++k)
-                        if (k >= w) row[i][k] ^= prow[k];
-                    cur[i] ^= prow[w];
+                    for (int k = w; k < W; ++k) row[i][k] ^= prow[k];
                     sb ^= ps << i;
                 }
             ++rank;
         }
-    }
+    });
 
     // ---- the estimate, or BP's when the syndrome is not reached
     bool bad = false;
