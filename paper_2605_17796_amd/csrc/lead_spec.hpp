@@ -171,31 +171,49 @@ struct Explicit {
             constexpr int c = decltype(cc)::value;
             constexpr int b = C::base[c];
             for_edges<C, c>([&](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
+            // The clamp of mu is applied to the two minima instead of to
+            // every edge: clamping is monotone, so the minimum and second
+            // minimum of the clamped magnitudes are the clamped minima, and
+            // where |mu_k| == n1 and the clamped comparison differ, both
+            // minima clamp to the same value.  Messages are bit for bit those
+            // of clamping each mu.
             float n1 = kBig, n2 = kBig, mu[D2];
-            uint32_t par = 0u, ps = 0u;
+            uint32_t par = 0u, ps = 0u, pend = 0u;
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                par ^= __float_as_uint(S[j]);
-                mu[j] = clampf(S[j] - m[b + k], clampv);
-                ps ^= __float_as_uint(mu[j]);
+                mu[j] = S[j] - m[b + k];
+                // sign parities of S and mu, two edges per three-input XOR
+                if constexpr ((k & 1) == 0) {
+                    pend = __float_as_uint(S[j]);
+                    if constexpr (k + 1 == C::deg[c]) par ^= pend;
+                } else {
+                    par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
+                }
                 n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[j]));
                 n1 = fminf(n1, fabsf(mu[j]));
             });
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+                if constexpr ((k & 1) == 0) {
+                    pend = __float_as_uint(mu[j]);
+                    if constexpr (k + 1 == C::deg[c]) ps ^= pend;
+                } else {
+                    ps = __builtin_amdgcn_bitop3_b32(ps, pend, __float_as_uint(mu[j]), 0x96);
+                }
+            });
             const uint32_t sc = (uint32_t)(sv >> c) & 1u;
             sat = sat && ((par >> 31) == sc);
-            const uint32_t px = (ps ^ (sc << 31)) & kSign;
-            uint32_t b1 = __float_as_uint(beta * n1), b2 = __float_as_uint(beta * n2);
+            const uint32_t px = ps ^ (sc << 31);   // bit 31: the sign of the product
+            uint32_t b1 = __float_as_uint(beta * fminf(n1, clampv)), b2 = __float_as_uint(beta * fminf(n2, clampv));
             asm("" : "+v"(b1), "+v"(b2));   // keep the two products (not a product per edge)
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                uint32_t mag = fabsf(mu[j]) == n1 ? b2 : b1;
-                const uint32_t sgn = (__float_as_uint(mu[j]) & kSign) ^ px;
-                // compare first, then form the new message from operands that
-                // depend on the comparison (see Compressed::check)
-                const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + k]);
-                diff |= dterm;
-                asm("" : "+v"(mag) : "v"(dterm));
-                m[b + k] = __uint_as_float(mag | sgn);
+                const uint32_t mag = fabsf(mu[j]) == n1 ? b2 : b1;
+                // sign bit from mu ^ px, magnitude bits from mag (sign 0)
+                const uint32_t t = __float_as_uint(mu[j]) ^ px;
+                const uint32_t nm = (t & kSign) | (mag & ~kSign);
+                diff = __builtin_amdgcn_bitop3_b32(diff, nm, __float_as_uint(m[b + k]), 0xf6);   // diff | (nm ^ old)
+                m[b + k] = __uint_as_float(nm);
             });
             asm volatile("" : "+v"(diff));
             __builtin_amdgcn_sched_barrier(0);
@@ -725,7 +743,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         partner_all<C, WG, BPERM, NW>(S, Q, buf, pa);
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] += Q[j];
-    }
+        }
     const bool ran_out = !done;
     const bool psat = parity<C>(S, sv);
     bool shot_final;
