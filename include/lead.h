@@ -244,7 +244,7 @@ typedef struct {
                                      lead_code_specialize; they pick their own
                                      workgroup shape): 1 with the compressed
                                      min-sum check state, 2 with one register
-                                     per message (views of at most 128 edges);
+                                     per message (views of at most 160 edges);
                                      0: the precompiled kernels.  Reads back as
                                      the form in use (a form that was not
                                      compiled is replaced by the other). The

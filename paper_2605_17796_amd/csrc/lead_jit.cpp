@@ -84,7 +84,7 @@ std::string source(const Code &c, int t, bool sp) {
     const TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
     if (tt.sigma.empty() || (int)tt.sigma.size() != D2) return std::string();
-    if (sp && tt.eloc > kExplicitMaxEdges) return std::string();
+    if (sp && tt.eloc > kSumProductMaxEdges) return std::string();
     int nfix = 0;
     for (int j = 0; j < D2; ++j) nfix += tt.sigma[j] == j;
     const int wg = workgroup_for(c.order);
@@ -118,7 +118,8 @@ std::string source(const Code &c, int t, bool sp) {
               << ">(a, w); }\n";
         // explicit forms: at least two waves per SIMD for the per-shot kernel
         // (its rounds wait on ds_bpermute, which a lone wave cannot hide)
-        o << "extern \"C\" __global__ void __launch_bounds__(" << wg << (form == kCompressed ? "" : ", 2")
+        o << "extern \"C\" __global__ void __launch_bounds__(" << wg
+          << (form == kCompressed || tt.eloc > kTwoWaveMaxEdges ? "" : ", 2")
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
@@ -192,7 +193,7 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
 std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, std::string &err) {
     const std::string src = source(c, t, sp);
     if (src.empty()) {
-        err = sp ? "sum-product needs a local position map and at most " + std::to_string(kExplicitMaxEdges) +
+        err = sp ? "sum-product needs a local position map and at most " + std::to_string(kSumProductMaxEdges) +
                        " edges per view"
                  : "no local position map";
         return nullptr;

@@ -23,8 +23,14 @@ enum Form { kCompressed = 1, kExplicit = 2, kSumProduct = 3 };
 constexpr int kForms = 3;
 
 // Views with at most this many local edges also get the explicit-message
-// form (one VGPR per message).
-constexpr int kExplicitMaxEdges = 128;
+// min-sum form (one VGPR per message), and at most kSumProductMaxEdges the
+// sum-product form.
+constexpr int kExplicitMaxEdges = 160;
+constexpr int kSumProductMaxEdges = 128;
+// Up to this many edges the explicit forms' per-shot kernel is held to two
+// waves per SIMD (256 VGPRs); above it, one wave with the whole register
+// file.
+constexpr int kTwoWaveMaxEdges = 128;
 
 // The global OSD-0 kernel keeps ceil(m/256) rows of ceil(n/64) words per lane
 // in registers; it is compiled when that product is at most this.
@@ -52,7 +58,7 @@ struct Kernels {
 // Source text of the kernels for check type t of code c: the min-sum forms,
 // or (sp) the sum-product form; empty when the code has no local position map
 // (the precompiled kernels serve min-sum) or, for sum-product, when a view
-// has more than kExplicitMaxEdges edges.
+// has more than kSumProductMaxEdges edges.
 std::string source(const Code &c, int t, bool sp = false);
 
 // Code object of `src` for gfx950 (compiled once per process).  Needs no GPU.

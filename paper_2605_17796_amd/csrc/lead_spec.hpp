@@ -96,13 +96,23 @@ struct Compressed {
         uint32_t diff = 0u;
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
+            // mu is not clamped per edge: the clamp goes to the two minima
+            // (clamping is monotone; where the unclamped and the clamped
+            // position of the smallest differ, both minima clamp to the same
+            // value and the position does not matter)
             float n1 = kBig, n2 = kBig;
-            uint32_t nam = 0u, sg = 0u, par = 0u;
+            uint32_t nam = 0u, sg = 0u, par = 0u, pend = 0u;
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value;
                 constexpr uint32_t k = decltype(kk)::value;
-                par ^= __float_as_uint(S[j]);
-                const float mu = clampf(S[j] - msg_of(m1[c], m2[c], am[c], q[c], k), clampv);
+                // sign parity of S, two edges per three-input XOR
+                if constexpr ((k & 1) == 0) {
+                    pend = __float_as_uint(S[j]);
+                    if constexpr (k + 1 == (uint32_t)C::deg[c]) par ^= pend;
+                } else {
+                    par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
+                }
+                const float mu = S[j] - msg_of(m1[c], m2[c], am[c], q[c], k);
                 const float ab = fabsf(mu);
                 sg |= signbit_of(mu) << k;
                 n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
@@ -115,7 +125,7 @@ struct Compressed {
             const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
             constexpr uint32_t all = (uint32_t)((1ull << C::deg[c]) - 1ull);
             uint32_t nq = flip ? (sg ^ all) : sg;
-            uint32_t b1u = __float_as_uint(beta * n1), b2u = __float_as_uint(beta * n2);
+            uint32_t b1u = __float_as_uint(beta * fminf(n1, clampv)), b2u = __float_as_uint(beta * fminf(n2, clampv));
             // every outgoing message unchanged (the position of the smallest
             // matters only when the two magnitudes differ)
             const uint32_t dterm = (nq ^ q[c]) | (b1u ^ __float_as_uint(m1[c])) | (b2u ^ __float_as_uint(m2[c])) |
@@ -203,15 +213,17 @@ struct Explicit {
             });
             const uint32_t sc = (uint32_t)(sv >> c) & 1u;
             sat = sat && ((par >> 31) == sc);
-            const uint32_t px = ps ^ (sc << 31);   // bit 31: the sign of the product
-            uint32_t b1 = __float_as_uint(beta * fminf(n1, clampv)), b2 = __float_as_uint(beta * fminf(n2, clampv));
+            // the two candidate messages with the sign of the whole product
+            // (check syndrome included); each edge then flips the sign by its
+            // own mu's, which takes its mu out of the product
+            const uint32_t px = (ps ^ (sc << 31)) & kSign;
+            uint32_t b1 = __float_as_uint(beta * fminf(n1, clampv)) ^ px,
+                     b2 = __float_as_uint(beta * fminf(n2, clampv)) ^ px;
             asm("" : "+v"(b1), "+v"(b2));   // keep the two products (not a product per edge)
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                const uint32_t mag = fabsf(mu[j]) == n1 ? b2 : b1;
-                // sign bit from mu ^ px, magnitude bits from mag (sign 0)
-                const uint32_t t = __float_as_uint(mu[j]) ^ px;
-                const uint32_t nm = (t & kSign) | (mag & ~kSign);
+                const uint32_t sel = fabsf(mu[j]) == n1 ? b2 : b1;
+                const uint32_t nm = __builtin_amdgcn_bitop3_b32(sel, __float_as_uint(mu[j]), kSign, 0x78);   // sel ^ (mu & sign)
                 diff = __builtin_amdgcn_bitop3_b32(diff, nm, __float_as_uint(m[b + k]), 0xf6);   // diff | (nm ^ old)
                 m[b + k] = __uint_as_float(nm);
             });

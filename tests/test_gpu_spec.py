@@ -33,12 +33,12 @@ def _priors(mode, ps, n, seed):
 
 def _forms(dec, synd, prior, mode, eloc):
     """Outputs under every kernel form: specialised with one register per
-    message (views of at most 128 edges), specialised with the compressed
+    message (views of at most 160 edges), specialised with the compressed
     check state, precompiled split, precompiled fused."""
     runs = {}
     for form in (2, 1, 0):
         dec.set_schedule(specialized=form)
-        want = form if form != 2 or eloc <= 128 else 1
+        want = form if form != 2 or eloc <= 160 else 1
         assert dec.get_schedule()["specialized"] == want
         runs[form] = run_gpu(dec, synd, prior, mode, lam=True)
     dec.set_schedule(fused=1)
