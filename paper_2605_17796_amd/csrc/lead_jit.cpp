@@ -113,7 +113,13 @@ std::string source(const Code &c, int t, bool sp) {
         if ((form == kSumProduct) != sp) continue;
         if (form != kCompressed && tt.eloc > kExplicitMaxEdges) continue;
         for (int pm = 0; pm < 2; ++pm)
-            o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_" << form << pm
+            // min-sum with one prior per shot: three waves per SIMD for
+            // views of at most kTwoWaveMaxEdges edges (the queue kernel's
+            // loads in its refill step need them; with a prior per qubit
+            // the priors would not fit)
+            o << "extern \"C\" __global__ void __launch_bounds__(64"
+              << (form != kSumProduct && pm == 0 && tt.eloc <= kTwoWaveMaxEdges ? ", 3" : "")
+              << ") lead_spec_local_" << form << pm
               << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << form
               << ">(a, w); }\n";
         // explicit forms: at least two waves per SIMD for the per-shot kernel

@@ -87,7 +87,7 @@ struct Compressed {
     // min-sum state.  Returns whether [S_j < 0] satisfies every check; `same`
     // tells whether every outgoing message is unchanged bit for bit.
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
-                                          bool &same) {
+                                          bool &same, float keep = 1.f) {
         bool sat = true;
         // bits that differ between the old and the new state, accumulated
         // as an integer so that each comparison is done as soon as its
@@ -112,7 +112,7 @@ struct Compressed {
                 } else {
                     par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
                 }
-                const float mu = S[j] - msg_of(m1[c], m2[c], am[c], q[c], k);
+                const float mu = __builtin_fmaf(-msg_of(m1[c], m2[c], am[c], q[c], k), keep, S[j]);
                 const float ab = fabsf(mu);
                 sg |= signbit_of(mu) << k;
                 n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
@@ -147,11 +147,12 @@ struct Compressed {
         return sat;
     }
     // S_j += m_{c->j} for every edge, checks in order.
-    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             for_edges<C, c>([&](auto jj, auto kk) {
-                S[decltype(jj)::value] += msg_of(m1[c], m2[c], am[c], q[c], (uint32_t)decltype(kk)::value);
+                S[decltype(jj)::value] =
+                    __builtin_fmaf(msg_of(m1[c], m2[c], am[c], q[c], (uint32_t)decltype(kk)::value), keep, S[decltype(jj)::value]);
             });
         });
     }
@@ -173,7 +174,7 @@ struct Explicit {
         for (int e = 0; e < E; ++e) m[e] = 0.f;
     }
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
-                                          bool &same) {
+                                          bool &same, float keep = 1.f) {
         constexpr int D2 = C::D * C::D;
         bool sat = true;
         uint32_t diff = 0u;   // see Compressed::check
@@ -191,7 +192,7 @@ struct Explicit {
             uint32_t par = 0u, ps = 0u, pend = 0u;
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                mu[j] = S[j] - m[b + k];
+                mu[j] = __builtin_fmaf(-m[b + k], keep, S[j]);
                 // sign parities of S and mu, two edges per three-input XOR
                 if constexpr ((k & 1) == 0) {
                     pend = __float_as_uint(S[j]);
@@ -233,11 +234,11 @@ struct Explicit {
         same = diff == 0u;
         return sat;
     }
-    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             for_edges<C, c>([&](auto jj, auto kk) {
-                S[decltype(jj)::value] += m[C::base[c] + decltype(kk)::value];
+                S[decltype(jj)::value] = __builtin_fmaf(m[C::base[c] + decltype(kk)::value], keep, S[decltype(jj)::value]);
             });
         });
     }
@@ -259,7 +260,7 @@ struct ExplicitSP {
         for (int e = 0; e < E; ++e) m[e] = 0.f;
     }
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float, float clampv,
-                                          bool &same) {
+                                          bool &same, float keep = 1.f) {
         constexpr int D2 = C::D * C::D;
         bool sat = true;
         uint32_t diff = 0u;
@@ -272,7 +273,7 @@ struct ExplicitSP {
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
                 par ^= __float_as_uint(S[j]);
-                mu[j] = clampf(S[j] - m[b + k], clampv);
+                mu[j] = clampf(__builtin_fmaf(-m[b + k], keep, S[j]), clampv);
                 ps ^= __float_as_uint(mu[j]);
                 f[j] = phi(fabsf(mu[j]));
                 if constexpr (k == 0) {
@@ -306,17 +307,22 @@ struct ExplicitSP {
         same = diff == 0u;
         return sat;
     }
-    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D]) const {
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             for_edges<C, c>([&](auto jj, auto kk) {
-                S[decltype(jj)::value] += m[C::base[c] + decltype(kk)::value];
+                S[decltype(jj)::value] = __builtin_fmaf(m[C::base[c] + decltype(kk)::value], keep, S[decltype(jj)::value]);
             });
         });
     }
 };
 
-// Check-state forms (lead_schedule.specialized; 3 = sum-product).
+// Check-state forms (lead_schedule.specialized; 3 = sum-product).  check()
+// and accumulate() scale the stored messages by `keep`: mu = S - keep * m and
+// S += keep * m, each a single fused multiply-add with one rounding, so
+// keep = 1 is the plain subtraction / addition bit for bit and keep = 0 reads
+// the state as all-zero messages without clearing it (the stored messages
+// are always finite).
 template <class C, int FORM>
 struct Pick {
     using type = Compressed<C>;
@@ -452,6 +458,7 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     for (int j = 0; j < NL; ++j) lam[j] = 0.f;
     CheckState<C, FORM> st;
     st.clear();
+    float keep = 0.f;
     for (;;) {
         uint64_t need = __ballot(!valid);
         while (need && queue_open) {
@@ -475,6 +482,7 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
                 const int64_t shot = item / a.N;
                 const int v = (int)(item - shot * a.N);
                 sv = local_syndrome(a, shot, v);
+                keep = 0.f;   // the previous item's messages read as zero
                 if (PM == 0) {
                     lam[0] = a.prior[shot] + 0.f;
                 } else {
@@ -482,7 +490,6 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
 #pragma unroll
                     for (int j = 0; j < NL; ++j) lam[j] = a.prior[base + a.view[v * D2 + j]] + 0.f;
                 }
-                st.clear();
                 t = 1;
             }
             const int64_t taken = __popcll(need) < avail ? __popcll(need) : avail;
@@ -492,9 +499,10 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
         if (__ballot(valid) == 0ull) break;
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] = lam[PM == 0 ? 0 : j];
-        st.accumulate(S);
+        st.accumulate(S, keep);
         bool same;
-        const bool sat = st.check(S, sv, a.beta, a.clampv, same);
+        const bool sat = st.check(S, sv, a.beta, a.clampv, same, keep);
+        keep = 1.f;
         int conv = 0, it = 0, fixed = 0;
         bool fin = false;
         if (t > a.Tl) {

@@ -100,6 +100,16 @@ def test_x_checks_parity(name, p, min_well):
     _report(f"X-checks {name}", compare(orc, gpu, oc.n), min_well=min_well)
 
 
+@pytest.mark.parametrize("name,shots,clamp", [("T", 600, 3.0), ("M", 150, 4.0)])
+def test_small_clamp_parity(name, shots, clamp):
+    """A clamp that many |mu| exceed: the kernels clamp the two minima of
+    each check rather than every mu, which must give the oracle's messages
+    (it clamps every mu) wherever the clamp decides the minimum."""
+    T = 20
+    oc, gpu, orc = _decode_both(name, 0, shots, 0.05, seed=37, Tl=T, Tg=T, llr_clamp=clamp)
+    _report(f"clamp={clamp} {name}", compare(orc, gpu, oc.n), min_well=0.3)
+
+
 @pytest.mark.parametrize("alpha", [0.5, 0.01])
 def test_alpha_parity(alpha):
     oc, gpu, orc = _decode_both("T", 0, 500, 0.05, seed=19, alpha=alpha)

@@ -49,7 +49,8 @@ def _forms(dec, synd, prior, mode, eloc):
 CASES = [("T", 0, 0, {}), ("T", 1, 2, {}), ("M", 0, 0, {}), ("M", 1, 0, {}), ("M", 0, 1, {}), ("M", 0, 2, {}),
          ("M", 0, 0, dict(early_exit=0)), ("M", 0, 0, dict(fixed_point_stop=0)), ("M", 0, 0, dict(alpha=0.1)),
          ("M", 0, 0, dict(stage=1)), ("L", 0, 0, {}), ("L", 1, 1, {}), ("appendix", 0, 0, {}),
-         ("appendix", 1, 2, {})]
+         ("appendix", 1, 2, {}), ("M", 0, 0, dict(llr_clamp=4.0)), ("L", 0, 0, dict(llr_clamp=4.0)),
+         ("T", 1, 0, dict(llr_clamp=2.0))]
 
 
 @pytest.mark.parametrize("name,t,mode,params", CASES)
