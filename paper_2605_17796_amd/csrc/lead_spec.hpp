@@ -146,6 +146,9 @@ struct Compressed {
         same = diff == 0u;
         return sat;
     }
+    // The message of check c to its k-th edge.
+    template <int c, int k>
+    __device__ __forceinline__ float msg() const { return msg_of(m1[c], m2[c], am[c], q[c], (uint32_t)k); }
     // S_j += m_{c->j} for every edge, checks in order.
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
@@ -234,6 +237,8 @@ struct Explicit {
         same = diff == 0u;
         return sat;
     }
+    template <int c, int k>
+    __device__ __forceinline__ float msg() const { return m[C::base[c] + k]; }
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -307,6 +312,8 @@ struct ExplicitSP {
         same = diff == 0u;
         return sat;
     }
+    template <int c, int k>
+    __device__ __forceinline__ float msg() const { return m[C::base[c] + k]; }
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -550,6 +557,47 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     }
 }
 
+// The first check (in check order) with an edge at local position j, or -1.
+template <class C>
+constexpr int first_check(int j) {
+    for (int c = 0; c < C::R; ++c)
+        if ((C::mask[c] >> j) & 1ull) return c;
+    return -1;
+}
+
+// Partial sums of a view for one global round: P_j = (lambda'_j where the
+// view owns position j, else 0) + its checks' messages to j in check order.
+// Where the view does not own j the zero start is dropped: 0 + m equals m
+// except that -0 becomes +0, and such a P_j is only ever added to the owner's
+// P, which is never -0 (it starts from lambda', itself never -0), so every
+// sum S_j comes out the same.
+template <class C, class ST>
+__device__ __forceinline__ void partial_sums(const ST &st, const float (&lam)[C::D * C::D], uint64_t fown,
+                                             float (&P)[C::D * C::D]) {
+    static_for<0, C::D * C::D>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        if constexpr (first_check<C>(j) < 0) {
+            if constexpr (C::sigma[j] > j) P[j] = lam[j];
+            else if constexpr (C::sigma[j] < j) P[j] = 0.f;
+            else P[j] = ((fown >> j) & 1ull) ? lam[j] : 0.f;
+        }
+    });
+    static_for<0, C::R>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        for_edges<C, c>([&](auto jj, auto kk) {
+            constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+            const float m = st.template msg<c, k>();
+            if constexpr (first_check<C>(j) == c) {
+                if constexpr (C::sigma[j] > j) P[j] = lam[j] + m;
+                else if constexpr (C::sigma[j] < j) P[j] = m;
+                else P[j] = ((fown >> j) & 1ull) ? lam[j] + m : m;
+            } else {
+                P[j] += m;
+            }
+        });
+    });
+}
+
 // Per-shot LDS flags (the precompiled kernel's layout).
 enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5, SF_CHG = 6, SF_NFIX = 7,
        SF_NOSD = 8, SF_STRIDE = 9 };
@@ -755,14 +803,33 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             if (lane_ok && v == 0) shf[sl * SF_STRIDE + ((t + 1) & 1)] = 0;
         }
         // partial sums of this view, then S_j = P_j + P of the other occurrence
+        partial_sums<C>(st, lam, fown, S);
+        if constexpr (BPERM) {
+            // the owner of a qubit adds its partner's P (fixed points of
+            // sigma: both occurrences, as ownership is known only at run
+            // time); the other occurrence then reads the owner's sum, which
+            // is the same sum with the operands swapped (IEEE addition is
+            // commutative)
+            float Q[D2];
+            static_for<0, D2>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                if constexpr (C::sigma[j] >= j) Q[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, j>(pa));
+            });
+            static_for<0, D2>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                if constexpr (C::sigma[j] >= j) S[j] += Q[j];
+            });
+            static_for<0, D2>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                if constexpr (C::sigma[j] < j) S[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, j>(pa));
+            });
+        } else {
+            float Q[D2];
+            store_all<C, WG, BPERM>(S, buf);
+            partner_all<C, WG, BPERM, NW>(S, Q, buf, pa);
 #pragma unroll
-        for (int j = 0; j < D2; ++j) S[j] = owned(j) ? lam[j] : 0.f;
-        st.accumulate(S);
-        float Q[D2];
-        store_all<C, WG, BPERM>(S, buf);
-        partner_all<C, WG, BPERM, NW>(S, Q, buf, pa);
-#pragma unroll
-        for (int j = 0; j < D2; ++j) S[j] += Q[j];
+            for (int j = 0; j < D2; ++j) S[j] += Q[j];
+        }
         }
     const bool ran_out = !done;
     const bool psat = parity<C>(S, sv);
