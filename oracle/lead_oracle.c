@@ -587,32 +587,52 @@ int oracle_bp(int rows, int cols, const uint8_t *H, const uint8_t *s, const doub
 }
 
 /* ------------------------------------------------------------------ */
-/* OSD-0 on a local view (local post-processing of the BP output)       */
+/* Ordered statistics decoding (post-processing of local and global BP) */
 /* ------------------------------------------------------------------ */
 
-/* Ordered statistics decoding of order 0 for H e = s (H: rows x cols, dense,
- * cols <= 64, rows <= 64).  The variables are ranked by their BP posterior
- * LLR, most likely in error first: by round(64 L) ascending, equal keys in
- * position order (reliabilities that agree to 1/64 count as equal, so exact
- * ties of symmetric positions stay ties under last-digit rounding);
- * Gaussian elimination over GF(2) takes the columns in that order and keeps
- * the first `rank` linearly independent ones (the information set); the
- * estimate is the solution supported on the information set.  Returns 0, or
- * -1 when s is not in the column space of H (e is then all zero). */
-int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L, uint8_t *e) {
+/* Cost unit of the combination sweep: the weight ln(1/p_j) of setting bit j,
+ * with p_j = 1 / (1 + e^{lambda_j}) the probability the decoder's prior
+ * gives it, in units of 1/64 and rounded to the nearest integer, so that
+ * candidate costs are exact integer sums:
+ *   ln(1/p) = ln(1 + e^lambda) = max(lambda, 0) + log1p(e^{-|lambda|}). */
+long oracle_osd_weight(double lambda) {
+    const double w = (lambda > 0.0 ? lambda : 0.0) + log1p(exp(-fabs(lambda)));
+    return (long)nearbyint(64.0 * w);
+}
+
+/* Ordered statistics decoding of H e = s (H: rows x cols, dense).  The
+ * variables are ranked by their BP posterior LLR L, most likely in error
+ * first: by round(64 L) ascending, equal keys in position order
+ * (reliabilities that agree to 1/64 count as equal, so exact ties of
+ * symmetric positions stay ties under last-digit rounding).  Gauss-Jordan
+ * elimination over GF(2) takes the columns in that order; the first `rank`
+ * linearly independent ones form the information set S, the others (in rank
+ * order) the set T.
+ *   order 0 (OSD-0): the estimate is the solution supported on S.
+ *   order lambda >= 1 (combination sweep): candidates are the OSD-0
+ *   solution, then for every column t of T the solution with e_T = {t},
+ *   then for every pair a < b among the first lambda columns of T the one
+ *   with e_T = {a, b} (e_S follows from e_T: e_S = s' + A e_T in the reduced
+ *   system [I | A | s']).  The estimate is the first candidate of least cost
+ *   sum over set bits of oracle_osd_weight(prior[j]).
+ * Returns 0, or -1 when s is not in the column space of H (e is then all
+ * zero). */
+int oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L,
+               const double *prior, int order, uint8_t *e) {
     const int words = cols / 64 + 1;          /* bit `cols` holds s */
-    int *order = (int *)malloc(sizeof(int) * (size_t)cols);
+    int *ord = (int *)malloc(sizeof(int) * (size_t)cols);
     int *pivcol = (int *)malloc(sizeof(int) * (size_t)(rows > 0 ? rows : 1));
-    double *key = (double *)malloc(sizeof(double) * (size_t)cols);
+    uint8_t *ispiv = (uint8_t *)calloc((size_t)(cols > 0 ? cols : 1), 1);
+    double *key = (double *)malloc(sizeof(double) * (size_t)(cols > 0 ? cols : 1));
     uint64_t *M = (uint64_t *)calloc((size_t)rows * words, sizeof(uint64_t));
     for (int j = 0; j < cols; j++) {
-        order[j] = j;
+        ord[j] = j;
         key[j] = nearbyint(L[j] * 64.0);       /* round half to even */
     }
     for (int a = 1; a < cols; a++) {          /* stable insertion sort */
-        int x = order[a], b = a;
-        while (b > 0 && key[order[b - 1]] > key[x]) { order[b] = order[b - 1]; b--; }
-        order[b] = x;
+        int x = ord[a], b = a;
+        while (b > 0 && key[ord[b - 1]] > key[x]) { ord[b] = ord[b - 1]; b--; }
+        ord[b] = x;
     }
     /* augmented rows [H | s], bit-packed */
     for (int r = 0; r < rows; r++) {
@@ -623,7 +643,7 @@ int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const do
     }
     int rank = 0;
     for (int t = 0; t < cols && rank < rows; t++) {
-        const int c = order[t];
+        const int c = ord[t];
         int pr = -1;
         for (int r = rank; r < rows; r++)
             if ((M[(size_t)r * words + (c >> 6)] >> (c & 63)) & 1) { pr = r; break; }
@@ -640,16 +660,61 @@ int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const do
             if (r != rank && ((row[c >> 6] >> (c & 63)) & 1))
                 for (int w = 0; w < words; w++) row[w] ^= P[w];
         }
+        ispiv[c] = 1;
         pivcol[rank++] = c;
     }
+#define OSD_BIT(r, j) ((int)((M[(size_t)(r) * words + ((j) >> 6)] >> ((j) & 63)) & 1))
     int ok = 1;
     for (int r = rank; r < rows; r++)
-        if ((M[(size_t)r * words + (cols >> 6)] >> (cols & 63)) & 1) ok = 0;
+        if (OSD_BIT(r, cols)) ok = 0;
     memset(e, 0, (size_t)cols);
-    if (ok)
-        for (int k = 0; k < rank; k++) e[pivcol[k]] = (uint8_t)((M[(size_t)k * words + (cols >> 6)] >> (cols & 63)) & 1);
-    free(order); free(pivcol); free(key); free(M);
+    if (ok) {
+        for (int k = 0; k < rank; k++) e[pivcol[k]] = (uint8_t)OSD_BIT(k, cols);
+        if (order > 0 && rank < cols) {
+            /* T in rank order */
+            int nt = 0;
+            int *T = (int *)malloc(sizeof(int) * (size_t)cols);
+            long *q = (long *)malloc(sizeof(long) * (size_t)cols);
+            for (int t = 0; t < cols; t++)
+                if (!ispiv[ord[t]]) T[nt++] = ord[t];
+            for (int j = 0; j < cols; j++) q[j] = oracle_osd_weight(prior[j]);
+            /* cost of the candidate with e_T = {a} or {a, b} (b < 0: none) */
+            long best = 0;
+            int ba = -1, bb = -1;
+            for (int k = 0; k < rank; k++)
+                if (OSD_BIT(k, cols)) best += q[pivcol[k]];
+            for (int x = 0; x < nt; x++) {
+                const int a = T[x];
+                long c = q[a];
+                for (int k = 0; k < rank; k++)
+                    if (OSD_BIT(k, cols) ^ OSD_BIT(k, a)) c += q[pivcol[k]];
+                if (c < best) { best = c; ba = a; bb = -1; }
+            }
+            const int lam = order < nt ? order : nt;
+            for (int x = 0; x < lam; x++)
+                for (int y = x + 1; y < lam; y++) {
+                    const int a = T[x], b = T[y];
+                    long c = q[a] + q[b];
+                    for (int k = 0; k < rank; k++)
+                        if (OSD_BIT(k, cols) ^ OSD_BIT(k, a) ^ OSD_BIT(k, b)) c += q[pivcol[k]];
+                    if (c < best) { best = c; ba = a; bb = b; }
+                }
+            if (ba >= 0) {
+                for (int k = 0; k < rank; k++)
+                    e[pivcol[k]] = (uint8_t)(OSD_BIT(k, cols) ^ OSD_BIT(k, ba) ^ (bb >= 0 ? OSD_BIT(k, bb) : 0));
+                e[ba] = 1;
+                if (bb >= 0) e[bb] = 1;
+            }
+            free(T); free(q);
+        }
+    }
+#undef OSD_BIT
+    free(ord); free(pivcol); free(ispiv); free(key); free(M);
     return ok ? 0 : -1;
+}
+
+int oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L, uint8_t *e) {
+    return oracle_osd(rows, cols, H, s, L, NULL, 0, e);
 }
 
 /* ------------------------------------------------------------------ */
@@ -754,7 +819,7 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             /* global post-processing: OSD-0 on H_t with the global posteriors
              * where global BP left the syndrome unsatisfied (when s is not
              * in the column space of H_t, BP's estimate stays) */
-            if (p->global_osd && !conv && oracle_osd0(m, n, c->H[type], s, Lg, eo) == 0) {
+            if (p->global_osd && !conv && oracle_osd(m, n, c->H[type], s, Lg, lamp, p->osd_order, eo) == 0) {
                 memcpy(eg, eo, (size_t)n);
                 conv = 2;
             }
@@ -795,7 +860,8 @@ int oracle_global_bp(const oracle_code *c, int type, const oracle_params *p, int
         int conv = 0;
         int it = bp_run(glob, s, prior + (size_t)shot * n, p, p->max_iter_global, Lg, eg, &conv, NULL, &wg);
         /* BP followed by OSD-0 where BP misses the syndrome */
-        if (p->global_osd && !conv && oracle_osd0(m, n, c->H[type], s, Lg, eo) == 0) {
+        if (p->global_osd && !conv &&
+            oracle_osd(m, n, c->H[type], s, Lg, prior + (size_t)shot * n, p->osd_order, eo) == 0) {
             memcpy(eg, eo, (size_t)n);
             conv = 2;
         }

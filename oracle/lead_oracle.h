@@ -63,9 +63,13 @@ typedef struct {
      * posteriors as reliabilities); its estimate satisfies the local
      * syndrome, so the view counts as converged for the confidence boost. */
     int    local_osd;
-    /* 1: where global BP ends with H e != s, OSD-0 on H with the global
+    /* 1: where global BP ends with H e != s, OSD on H with the global
      * posteriors as reliabilities replaces e (stats converged = 2). */
     int    global_osd;
+    /* order of that OSD: 0 = OSD-0, lambda >= 1 = combination sweep of order
+     * lambda, candidate costs from the global decoder's prior (lambda' in
+     * LEAD, the channel prior in global BP alone); see oracle_osd. */
+    int    osd_order;
 } oracle_params;
 
 /* info[] layout for oracle_info */
@@ -102,6 +106,12 @@ int  oracle_decode(const oracle_code *c, int type, const oracle_params *p, int s
 
 /* OSD-0 of H e = s with reliabilities L (see lead_oracle.c); 0 or -1. */
 int  oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L, uint8_t *e);
+/* OSD of order `order` (0: OSD-0; >= 1: combination sweep) with candidate
+ * costs from the prior LLRs `prior` (unused at order 0; see lead_oracle.c). */
+int  oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L,
+                const double *prior, int order, uint8_t *e);
+/* Cost of setting a bit whose prior LLR is lambda: round(64 ln(1 + e^lambda)). */
+long oracle_osd_weight(double lambda);
 
 /* Phase 2 (soft-information regularisation) alone: phat_i = alpha * mean of
  * pv over the views holding qubit i; lam_i = clamp(ln(1-phat_i) - ln phat_i).

@@ -218,3 +218,135 @@ def test_global_bp_then_osd(name):
     for i in np.nonzero(~conv)[0]:
         ref, ok = o.osd0(H, sb[i], base["post"][i])
         assert ok and np.array_equal(eh[i], ref)
+
+
+def test_osd_weight_closed_form():
+    """The sweep's cost of a bit is round(64 ln(1/p)) with p = 1/(1 + e^lam)."""
+    import math
+    from oracle import oracle as o
+    for lam in (-30.0, -7.25, -1.0, -1e-9, 0.0, 0.3, 2.944438979, 9.5, 30.0):
+        p = 1.0 / (1.0 + math.exp(lam))
+        assert o.osd_weight(lam) == int(np.rint(64.0 * -math.log(p)))
+
+
+def _sweep_by_brute_force(H, s, L, prior, order):
+    """The combination sweep from its definition: information set S and the
+    other columns T in rank order; candidate supports e_T = {}, {t} for every
+    t in T, {a, b} for pairs among the first `order` columns of T; each
+    completed on S by enumerating every pattern on S; the first candidate of
+    least total cost wins."""
+    from oracle import oracle as o
+    rows, ncol = H.shape
+    cols = _col_ints(H)
+    ranked = sorted(range(ncol), key=lambda j: (np.rint(64.0 * L[j]), j))
+    info = _greedy_information_set(H, L)
+    S = [j for j in ranked if j in info]
+    T = [j for j in ranked if j not in info]
+    target = int(sum(int(s[i]) << i for i in range(rows)))
+    w = [o.osd_weight(prior[j]) for j in range(ncol)]
+    cands = [()] + [(t,) for t in T]
+    lam = min(order, len(T))
+    cands += [(T[x], T[y]) for x in range(lam) for y in range(x + 1, lam)]
+    best, best_e = None, None
+    for sup in cands:
+        acc = target
+        for t in sup:
+            acc ^= cols[t]
+        sol = None
+        for mask in range(1 << len(S)):
+            v = 0
+            for b, j in enumerate(S):
+                if (mask >> b) & 1:
+                    v ^= cols[j]
+            if v == acc:
+                sol = mask
+                break
+        assert sol is not None
+        e = np.zeros(ncol, dtype=np.uint8)
+        for b, j in enumerate(S):
+            e[j] = (sol >> b) & 1
+        for t in sup:
+            e[t] = 1
+        c = sum(w[j] for j in range(ncol) if e[j])
+        if best is None or c < best:
+            best, best_e = c, e
+    return best_e, best
+
+
+@pytest.mark.parametrize("name", ["appendix", "T", "M"])
+@pytest.mark.parametrize("order", [1, 3, 5])
+def test_osd_cs_is_the_cheapest_candidate(name, order):
+    """Combination sweep against brute force over its candidate set, on the
+    local check matrices (rank below the number of columns)."""
+    from oracle import oracle as o
+    _, oc = code_pair(name)
+    rng = np.random.default_rng(17 + order)
+    for t in (0, 1):
+        H = oc.hloc(t)
+        if np.linalg.matrix_rank(H) > 14:
+            continue
+        for trial in range(4):
+            e0 = (rng.random(H.shape[1]) < 0.2).astype(np.uint8)
+            s = (H.astype(np.int64) @ e0 % 2).astype(np.uint8)
+            L = rng.uniform(-3, 6, size=H.shape[1])
+            prior = rng.uniform(-1, 5, size=H.shape[1])
+            e, ok = o.osd(H, s, L, prior=prior, order=order)
+            assert ok
+            ref, _ = _sweep_by_brute_force(H, s, L, prior, order)
+            assert np.array_equal(e, ref)
+            e0_, _ = o.osd(H, s, L, order=0)
+            assert np.array_equal(e0_, o.osd0(H, s, L)[0])
+            c = lambda x: sum(o.osd_weight(prior[j]) for j in np.nonzero(x)[0])
+            assert c(e) <= c(e0_)
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_osd_cs_on_random_sparse_matrices(name):
+    """Small random sparse matrices with dependent rows and columns: the sweep
+    equals brute force and reproduces the syndrome."""
+    from oracle import oracle as o
+    rng = np.random.default_rng(101 if name == "T" else 202)
+    for trial in range(12):
+        rows, ncol = int(rng.integers(6, 11)), int(rng.integers(10, 17))
+        H = (rng.random((rows, ncol)) < 0.3).astype(np.uint8)
+        H[-1] = H[0] ^ H[1]
+        e0 = (rng.random(ncol) < 0.25).astype(np.uint8)
+        s = (H.astype(np.int64) @ e0 % 2).astype(np.uint8)
+        L = np.round(rng.uniform(-2, 4, size=ncol) * 4) / 4   # exact ties included
+        prior = rng.uniform(0, 4, size=ncol)
+        for order in (0, 2, 3):
+            e, ok = o.osd(H, s, L, prior=prior, order=order)
+            assert ok and np.array_equal((H.astype(np.int64) @ e) % 2, s)
+            if order:
+                assert np.array_equal(e, _sweep_by_brute_force(H, s, L, prior, order)[0])
+
+
+@pytest.mark.parametrize("name", ["T", "M"])
+def test_global_osd_cs_in_lead(name):
+    """LEAD with OSD-CS of order 3 after global BP: every unresolved shot takes
+    the sweep's estimate on the global posteriors with lambda' as the prior,
+    never costlier than OSD-0's; resolved shots are untouched."""
+    from oracle import oracle as o
+    from lead_inputs import unpack_bits
+    _, oc = code_pair(name)
+    T = {"T": 16, "M": 12}[name]
+    shots = 16
+    e = bitflip_packed(shots, oc.n, 0.06, seed=41)
+    s = oc.syndrome(e)
+    lam = np.full(shots, float(channel_llr(0.06)))
+    kw = dict(max_iter_local=T, max_iter_global=T, global_osd=1)
+    o0 = oc.decode(s, lam, p=o.params(**kw))
+    o3 = oc.decode(s, lam, p=o.params(osd_order=3, **kw))
+    assert np.array_equal(o3["post"], o0["post"]) and np.array_equal(o3["lam"], o0["lam"])
+    assert np.array_equal(o3["stats"], o0["stats"])
+    H = oc.H()
+    sb = unpack_bits(s, oc.m())
+    e3, e0 = unpack_bits(o3["ehat"], oc.n), unpack_bits(o0["ehat"], oc.n)
+    res = o0["stats"][:, 0] == 2
+    assert res.any()
+    assert np.array_equal(e3[~res], e0[~res])
+    for i in np.nonzero(res)[0]:
+        ref, ok = o.osd(H, sb[i], o0["post"][i], prior=o0["lam"][i], order=3)
+        assert ok and np.array_equal(e3[i], ref)
+        c = lambda x: sum(o.osd_weight(o0["lam"][i][j]) for j in np.nonzero(x)[0])
+        assert c(e3[i]) <= c(e0[i])
