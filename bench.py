@@ -393,7 +393,9 @@ def main():
                                          "osd_views_per_shot": round(float(ost[:, 7].mean()), 2)}
         del odec, oout
         # OSD-0 on H_t after global BP: LEAD with it, and BP-OSD-0 on H_t alone
-        for key, kw in (("global_osd0_A5_p005", {}), ("bp_osd0_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL})):
+        for key, kw in (("global_osd0_A5_p005", {}), ("bp_osd0_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL}),
+                        ("global_osd_cs3_A5_p005", {"osd_order": 3}),
+                        ("bp_osd_cs3_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL, "osd_order": 3})):
             gd2 = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
                             ms_scale=0.75, alpha=1.0, global_post=1, **kw)
             go2 = gd2.alloc_outputs(shots)
@@ -418,26 +420,45 @@ def main():
                           "mean_global_iters": round(float(ast[:, 1].mean()), 2)})
         dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=1.0)
         variants["alpha_sweep_A5_p002"] = sweep
+        # A5 at the four bit-flip rates of the mid-code workload (10^5 shots each)
+        sweep_p = []
+        for pi, pp in enumerate((0.02, 0.04, 0.06, 0.08)):
+            sp_ = syndromes(torch, dec, n, shots, pp, seed=1600 + pi, distinct=20000)
+            lp_ = torch.full((shots,), float(channel_llr(pp)), dtype=torch.float32, device="cuda")
+            dec.decode(sp_, lp_, out=out)
+            pw_, _ = timed(torch, lambda i: dec.decode(sp_, lp_, out=out), 1)
+            pst = out["stats"].cpu().numpy()
+            sweep_p.append({"p": pp, "shots_per_s": round(shots / pw_, 1), "converged": round(float(pst[:, 0].mean()), 4),
+                            "mean_global_iters": round(float(pst[:, 1].mean()), 2)})
+            del sp_, lp_
+        variants["p_sweep_A5"] = sweep_p
+        # PSL(2,7) under depolarising noise: X and Z errors decoded independently
         from lead_inputs import depolarizing_packed
-        lshots, ldist, pdep = 200_000, 20_000, 0.03
+        lshots, ldist = 200_000, 20_000
         lcode = P.Code.from_spec(__import__("lead_inputs").standard("L"))
-        xs, zs = depolarizing_packed(ldist, lcode.n, pdep, seed=2500)
-        reps = lshots // ldist
-        lam_d = torch.full((lshots,), float(channel_llr(2 * pdep / 3)), dtype=torch.float32, device="cuda")
-        parts, ltime = {}, 0.0
-        for t, e in ((0, xs), (1, zs)):
-            ld = P.Decoder(lcode, t=t, max_shots=lshots, max_iter_local=ROUNDS["L"], max_iter_global=ROUNDS["L"])
-            ls = ld.syndrome(torch.from_numpy(e.view(np.int64)).cuda()).repeat(reps, 1).contiguous()
-            lo_ = ld.alloc_outputs(lshots, post=False)
-            ld.decode(ls, lam_d, out=lo_)
-            lw, _ = timed(torch, lambda i: ld.decode(ls, lam_d, out=lo_), 1)
-            ltime += lw
-            lst = lo_["stats"].cpu().numpy()
-            parts["XZ"[t] + "_errors"] = {"converged": round(float(lst[:, 0].mean()), 4),
-                                          "mean_global_iters": round(float(lst[:, 1].mean()), 2)}
-            del ld, ls, lo_
-        variants["PSL27_depolarising"] = {"p": pdep, "shots": lshots, "distinct_error_draws": ldist,
-                                          "shots_per_s_both_parts": round(lshots / ltime, 1), **parts}
+        ldecs = [P.Decoder(lcode, t=t, max_shots=lshots, max_iter_local=ROUNDS["L"], max_iter_global=ROUNDS["L"])
+                 for t in (0, 1)]
+        lo_ = ldecs[0].alloc_outputs(lshots, post=False)
+        dep = []
+        for pi, pdep in enumerate((0.01, 0.03, 0.05)):
+            xs, zs = depolarizing_packed(ldist, lcode.n, pdep, seed=2500 + pi)
+            reps = lshots // ldist
+            lam_d = torch.full((lshots,), float(channel_llr(2 * pdep / 3)), dtype=torch.float32, device="cuda")
+            parts, ltime = {}, 0.0
+            for t, e in ((0, xs), (1, zs)):
+                ld = ldecs[t]
+                ls = ld.syndrome(torch.from_numpy(e.view(np.int64)).cuda()).repeat(reps, 1).contiguous()
+                ld.decode(ls, lam_d, out=lo_)
+                lw, _ = timed(torch, lambda i: ld.decode(ls, lam_d, out=lo_), 1)
+                ltime += lw
+                lst = lo_["stats"].cpu().numpy()
+                parts["XZ"[t] + "_errors"] = {"converged": round(float(lst[:, 0].mean()), 4),
+                                              "mean_global_iters": round(float(lst[:, 1].mean()), 2)}
+                del ls
+            dep.append({"p": pdep, "shots": lshots, "distinct_error_draws": ldist,
+                        "shots_per_s_both_parts": round(lshots / ltime, 1), **parts})
+        del ldecs, lo_
+        variants["PSL27_depolarising"] = dep
 
     # ---- mixed-code batch (D6 / A5 / PSL(2,7)): one graph launch vs plain
     mixed = None

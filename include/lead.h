@@ -162,6 +162,20 @@ typedef struct {
                                  codes with ceil(m/256) * ceil(n/64) <= 64
                                  (LEAD_E_UNSUPPORTED otherwise, and from
                                  lead_decode_plain).  0: none                  */
+    int32_t osd_order;        /* order lambda of that OSD, 0..8 (needs
+                                 global_post = 1).  0: OSD-0.  lambda >= 1:
+                                 combination sweep (the paper runs its
+                                 global BP-OSD in this mode at order 3):
+                                 candidates are the OSD-0 solution, the
+                                 solution with one bit set on each column
+                                 outside the information set, and the one
+                                 with two bits set on each pair among the
+                                 first lambda of those columns (rank order);
+                                 the estimate is the first candidate of least
+                                 cost sum over set bits of
+                                 round(64 ln(1 + e^{lambda'_j})), lambda' the
+                                 global decoder's prior (the channel prior in
+                                 stage GLOBAL).                               */
 } lead_params;
 
 /* Per-shot statistics (32 bytes). */

@@ -50,7 +50,7 @@ class lead_params(C.Structure):
     _fields_ = [("alpha", C.c_float), ("ms_scale", C.c_float), ("max_iter_local", C.c_int32),
                 ("max_iter_global", C.c_int32), ("llr_clamp", C.c_float), ("early_exit", C.c_int32),
                 ("stage", C.c_int32), ("boost", C.c_int32), ("fixed_point_stop", C.c_int32), ("local_post", C.c_int32),
-                ("bp", C.c_int32), ("global_post", C.c_int32)]
+                ("bp", C.c_int32), ("global_post", C.c_int32), ("osd_order", C.c_int32)]
 
 
 class lead_schedule(C.Structure):
@@ -208,9 +208,9 @@ def lead_code_destroy(code):
 
 def lead_params_make(alpha=1.0, ms_scale=0.75, max_iter_local=32, max_iter_global=32, llr_clamp=30.0,
                      early_exit=1, stage=LEAD_STAGE_FULL, boost=1, fixed_point_stop=1, local_post=0,
-                     bp=LEAD_BP_MINSUM, global_post=0) -> lead_params:
+                     bp=LEAD_BP_MINSUM, global_post=0, osd_order=0) -> lead_params:
     return lead_params(alpha, ms_scale, max_iter_local, max_iter_global, llr_clamp, early_exit, stage, boost,
-                       fixed_point_stop, local_post, bp, global_post)
+                       fixed_point_stop, local_post, bp, global_post, osd_order)
 
 
 def lead_decoder_create(code, t, params: lead_params, max_shots: int):

@@ -47,7 +47,7 @@ struct lead_decoder {
     // global OSD-0: H_t as row lists, and posterior / statistics buffers for
     // calls that do not ask for them (ws_shots shots)
     int32_t *d_rptr = nullptr, *d_ridx = nullptr;
-    float *d_gpost = nullptr;
+    float *d_gpost = nullptr, *d_glam = nullptr;
     lead_shot_stats *d_gstats = nullptr;
     // schedule and split-path workspace (for ws_shots shots)
     lead_schedule sched{};
@@ -97,6 +97,9 @@ lead_status check_params(const lead_params *p) {
     if (p->global_post != 0 && p->global_post != 1) return fail(LEAD_E_ARG, "bad global_post");
     if (p->global_post && p->stage == LEAD_STAGE_LOCAL)
         return fail(LEAD_E_UNSUPPORTED, "stage LOCAL has no global BP to post-process");
+    if (p->osd_order < 0 || p->osd_order > lead::kMaxOsdOrder)
+        return fail(LEAD_E_ARG, "osd_order must be in 0.." + std::to_string(lead::kMaxOsdOrder));
+    if (p->osd_order > 0 && !p->global_post) return fail(LEAD_E_ARG, "osd_order needs global_post = 1");
     return LEAD_OK;
 }
 
@@ -111,7 +114,7 @@ bool sum_product(const lead_decoder *d) { return d->params.bp == LEAD_BP_SUMPROD
 // Sum-product and OSD-0 run only on the kernels compiled for the code.
 bool needs_spec(const lead_decoder *d) { return sum_product(d) || d->params.local_post != 0; }
 
-bool osd_ready(const lead_decoder *d) { return d->spec && d->spec->osd && d->d_rptr; }
+bool osd_ready(const lead_decoder *d) { return d->spec && d->spec->osd && d->spec->osd_cs && d->d_rptr; }
 
 // Posterior and statistics buffers of the global OSD-0 for calls that pass
 // none (allocated once, when global_post is first set).
@@ -119,16 +122,17 @@ hipError_t ensure_osd_workspace(lead_decoder *d) {
     hipError_t e = hipSuccess;
     if (!d->d_gpost) e = hipMalloc(&d->d_gpost, sizeof(float) * (size_t)d->ws_shots * d->n);
     if (e == hipSuccess && !d->d_gstats) e = hipMalloc(&d->d_gstats, sizeof(lead_shot_stats) * (size_t)d->ws_shots);
+    if (e == hipSuccess && !d->d_glam) e = hipMalloc(&d->d_glam, sizeof(float) * (size_t)d->ws_shots * d->n);
     return e;
 }
 
-// OSD-0 on H_t for the shots of `a` that global BP left unresolved: one
+// OSD on H_t for the shots of `a` that global BP left unresolved: one
 // workgroup per shot (the others exit at once).
 hipError_t launch_osd(const lead_decoder *d, lead::DecodeArgs a, hipStream_t s) {
     lead::OsdArgs o{d->d_rptr, d->d_ridx};
     void *args[] = {&a, &o};
-    return hipModuleLaunchKernel(d->spec->osd, (unsigned)a.shots, 1, 1, (unsigned)d->spec->osd_wg, 1, 1, 0, s,
-                                 args, nullptr);
+    return hipModuleLaunchKernel(a.osd_order > 0 ? d->spec->osd_cs : d->spec->osd, (unsigned)a.shots, 1, 1,
+                                 (unsigned)d->spec->osd_wg, 1, 1, 0, s, args, nullptr);
 }
 
 // The specialised form a schedule asks for, or the one compiled when it
@@ -213,6 +217,7 @@ lead::DecodeArgs base_args(const lead_decoder *d) {
     a.boost = d->params.boost ? 1 : 0;
     a.fixed_stop = d->params.fixed_point_stop ? 1 : 0;
     a.local_osd = d->params.local_post ? 1 : 0;
+    a.osd_order = d->params.osd_order;
     for (int c = 0; c < lead::kMaxChecks; ++c) a.mask[c] = c < d->r ? d->mask[c] : 0;
     return a;
 }
@@ -303,6 +308,7 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         if (gpost) {
             if (!a.post) a.post = d->d_gpost;
             if (!a.stats) a.stats = d->d_gstats;
+            if (!a.lam_out && d->params.osd_order > 0) a.lam_out = d->d_glam;   // the sweep's costs
         }
         hipError_t e = split && use_spec(d) ? launch_spec(d, a, w, s, ev)
                                    : lead::launch_decode(d->D, d->r, a, w, split, s, ev ? ev->data() : nullptr);
@@ -587,6 +593,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
         (void)hipFree(d->d_rptr);
         (void)hipFree(d->d_ridx);
         (void)hipFree(d->d_gpost);
+        (void)hipFree(d->d_glam);
         (void)hipFree(d->d_gstats);
         return hip_fail(e, "device allocation");
     }
@@ -645,7 +652,7 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
         auto k = lead::jit::load(*d->code, d->type, d->device, params->bp == LEAD_BP_SUMPRODUCT, jerr);
         if (!k && params->bp == LEAD_BP_SUMPRODUCT) return fail(LEAD_E_UNSUPPORTED, "sum-product: " + jerr);
         if (k && !d->d_pv) return fail(LEAD_E_UNSUPPORTED, "no partner tables");
-        if (params->global_post && !(k && k->osd)) return fail(LEAD_E_UNSUPPORTED, "no global OSD-0 kernel");
+        if (params->global_post && !(k && k->osd && k->osd_cs)) return fail(LEAD_E_UNSUPPORTED, "no global OSD kernel");
         d->spec = k;
         d->params = *params;
         d->sched.specialized = spec_form(d, lead::jit::kExplicit);
@@ -718,6 +725,7 @@ void lead_decoder_destroy(lead_decoder *d) {
     (void)hipFree(d->d_rptr);
     (void)hipFree(d->d_ridx);
     (void)hipFree(d->d_gpost);
+    (void)hipFree(d->d_glam);
     (void)hipFree(d->d_gstats);
     (void)drain_timing(d);
     free_plain(d);

@@ -139,7 +139,9 @@ std::string source(const Code &c, int t, bool sp) {
           << ", RPL = " << (m + 255) / 256 << ", WG = " << owg << ", RANK = " << tt.rank << ", SORTN = " << sortn
           << ";\n};\n"
           << "extern \"C\" __global__ void __launch_bounds__(" << owg
-          << ") lead_spec_osd(lead::DecodeArgs a, lead::OsdArgs o) { lead_spec::osd_global_body<LeadGlobal>(a, o); }\n";
+          << ") lead_spec_osd(lead::DecodeArgs a, lead::OsdArgs o) { lead_spec::osd_global_body<LeadGlobal, false>(a, o); }\n"
+          << "extern \"C\" __global__ void __launch_bounds__(" << owg
+          << ") lead_spec_osd_cs(lead::DecodeArgs a, lead::OsdArgs o) { lead_spec::osd_global_body<LeadGlobal, true>(a, o); }\n";
     }
     return o.str();
 }
@@ -230,6 +232,7 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
     }
     if (e == hipSuccess && osd_fits(c, t)) {
         e = hipModuleGetFunction(&k->osd, k->module, "lead_spec_osd");
+        if (e == hipSuccess) e = hipModuleGetFunction(&k->osd_cs, k->module, "lead_spec_osd_cs");
         k->osd_wg = osd_workgroup(c, t);
     }
     if (e != hipSuccess) {

@@ -46,6 +46,7 @@ struct Kernels {
     hipFunction_t local[kForms][2] = {};
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
     hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
+    hipFunction_t osd_cs = nullptr;      // the same with the combination sweep
     int osd_wg = 0;                      // its workgroup size
     bool has[kForms] = {};               // [form - 1]: compiled
     int wg = 0;                          // workgroup size of `global`

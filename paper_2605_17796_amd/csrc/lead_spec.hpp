@@ -890,7 +890,17 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
 // row k, provided that every row without a pivot has s-bit 0 (otherwise the
 // syndrome is not in the column space of H and BP's estimate and report
 // stay).
-template <class G>
+// CS (combination sweep of order a.osd_order): the elimination runs over
+// every word, so that pivot row k ends as [unit k | A_k | s'_k] over the
+// ranked columns; the costs of the candidates (OSD-0, one bit set on each
+// non-pivot column t, two bits set on each pair among the first osd_order
+// non-pivot columns) follow from the s-bits, A and the weights q_t =
+// round(64 ln(1 + e^{lambda'})) of the global prior read from a.lam_out:
+//   cost(e_T) = C0 + sum_{t in e_T} q_t + sum_k u_k [A_k . e_T odd],
+//   C0 = sum_{k: s'_k = 1} q_{piv k},  u_k = (s'_k ? -1 : 1) q_{piv k},
+// accumulated in LDS as integers; the least (cost, candidate index) wins,
+// i.e. the first candidate of least cost in the order listed.
+template <class G, bool CS>
 __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead::OsdArgs &o) {
     constexpr int WG = G::WG, NWAVE = WG / 64, W = G::W, RPL = G::RPL, NQ = G::NQ, M = G::M,
                   SORTN = G::SORTN;
@@ -992,7 +1002,7 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
                 for (int i = 0; i < RPL; ++i)
                     if (i == pi) {
 #pragma unroll
-                        for (int k = w; k < W; ++k) prow[k] = row[i][k];
+                        for (int k = CS ? 0 : w; k < W; ++k) prow[k] = row[i][k];
                         flags[0] = (int)((sb >> i) & 1u);
                         pcol[i] = 64 * w + b;
                     }
@@ -1004,7 +1014,7 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
             for (int i = 0; i < RPL; ++i)
                 if (tid + WG * i != p && ((row[i][w] >> b) & 1ull)) {
 #pragma unroll
-                    for (int k = w; k < W; ++k) row[i][k] ^= prow[k];
+                    for (int k = CS ? 0 : w; k < W; ++k) row[i][k] ^= prow[k];
                     sb ^= ps << i;
                 }
             ++rank;
@@ -1019,11 +1029,131 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
     if (tid == 0) flags[1] = 0;
     __syncthreads();
     if (bad) flags[1] = 1;
+    int ca = -1, cb = -1;   // non-pivot columns (rank positions) set by the sweep's choice
+    if constexpr (CS) {
+        __shared__ int32_t qw[NQ];                    // weight of rank position t
+        __shared__ int32_t acc[NQ];                   // sum of u_k over pivot rows with bit t
+        __shared__ uint32_t pbits[(NQ + 31) / 32];    // pivot columns
+        __shared__ int32_t tl[lead::kMaxOsdOrder], pairsum[lead::kMaxOsdOrder * (lead::kMaxOsdOrder - 1) / 2],
+            c0s[2];
+        __shared__ unsigned long long best;
+        const float *lp = a.lam_out + shot * a.n;
+        for (int t = tid; t < NQ; t += WG) {
+            const float x = lp[(uint32_t)keys[t]];
+            const float wgt = fmaxf(x, 0.f) + log1p_nonneg(exp_hw(-fabsf(x)));
+            qw[t] = (int32_t)__builtin_rintf(64.f * wgt);
+            acc[t] = 0;
+        }
+        for (int i = tid; i < (NQ + 31) / 32; i += WG) pbits[i] = 0u;
+        if (tid == 0) c0s[0] = 0;
+        if (tid < lead::kMaxOsdOrder * (lead::kMaxOsdOrder - 1) / 2) pairsum[tid] = 0;
+        __syncthreads();
+        int c0p = 0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+            if ((piv >> i) & 1u) {
+                const int pc = pcol[i];
+                atomicOr(&pbits[pc >> 5], 1u << (pc & 31));
+                const int32_t qv = qw[pc];
+                const int32_t u = ((sb >> i) & 1u) ? -qv : qv;
+                c0p += ((sb >> i) & 1u) ? qv : 0;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    uint64_t bits = row[i][k];
+                    if (k == (pc >> 6)) bits &= ~(1ull << (pc & 63));
+                    while (bits) {
+                        atomicAdd(&acc[64 * k + __builtin_ctzll(bits)], u);
+                        bits &= bits - 1ull;
+                    }
+                }
+            }
+        atomicAdd(&c0s[0], c0p);
+        __syncthreads();
+        const int32_t C0 = c0s[0];
+        if (tid == 0) {
+            best = (unsigned long long)(uint32_t)C0 << 32;   // OSD-0 is candidate 0
+            int nt = 0;
+            for (int t = 0; t < NQ && nt < a.osd_order; ++t)
+                if (!((pbits[t >> 5] >> (t & 31)) & 1u)) tl[nt++] = t;
+            c0s[1] = nt;
+        }
+        __syncthreads();
+        const int nt = c0s[1];
+        // pairs among the first nt non-pivot columns, in lexicographic order
+        for (int x = 0, pi = 0; x < nt; ++x)
+            for (int y = x + 1; y < nt; ++y, ++pi) {
+                const int ta = tl[x], tb = tl[y];
+                int part = 0;
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+                    if ((piv >> i) & 1u) {
+                        uint64_t wa = 0ull, wb = 0ull;
+#pragma unroll
+                        for (int k = 0; k < W; ++k) {
+                            wa = (k == (ta >> 6)) ? row[i][k] : wa;
+                            wb = (k == (tb >> 6)) ? row[i][k] : wb;
+                        }
+                        if (((wa >> (ta & 63)) ^ (wb >> (tb & 63))) & 1ull)
+                            part += ((sb >> i) & 1u) ? -qw[pcol[i]] : qw[pcol[i]];
+                    }
+                if (part) atomicAdd(&pairsum[pi], part);
+            }
+        __syncthreads();
+        unsigned long long mine = ~0ull;
+        for (int t = tid; t < NQ; t += WG)
+            if (!((pbits[t >> 5] >> (t & 31)) & 1u)) {
+                const uint32_t cost = (uint32_t)(C0 + qw[t] + acc[t]);
+                const unsigned long long key = ((unsigned long long)cost << 32) | (uint32_t)(t + 1);
+                mine = key < mine ? key : mine;
+            }
+        if (tid < nt * (nt - 1) / 2) {
+            int x = 0, r = tid;
+            while (r >= nt - 1 - x) { r -= nt - 1 - x; ++x; }
+            const int ta = tl[x], tb = tl[x + 1 + r];
+            const uint32_t cost = (uint32_t)(C0 + qw[ta] + qw[tb] + pairsum[tid]);
+            const unsigned long long key = ((unsigned long long)cost << 32) | (uint32_t)(NQ + 1 + tid);
+            mine = key < mine ? key : mine;
+        }
+        atomicMin(&best, mine);
+        __syncthreads();
+        const uint32_t idx = (uint32_t)best;
+        if (idx >= 1 && idx <= (uint32_t)NQ) {
+            ca = (int)idx - 1;
+        } else if (idx > (uint32_t)NQ) {
+            int x = 0, r = (int)idx - NQ - 1;
+            while (r >= nt - 1 - x) { r -= nt - 1 - x; ++x; }
+            ca = tl[x];
+            cb = tl[x + 1 + r];
+        }
+        if (tid == 0 && ca >= 0) {
+            const int qa = (int)(uint32_t)keys[ca];
+            atomicOr(&ebits[qa >> 5], 1u << (qa & 31));
+            if (cb >= 0) {
+                const int qb = (int)(uint32_t)keys[cb];
+                atomicOr(&ebits[qb >> 5], 1u << (qb & 31));
+            }
+        }
+    }
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
-        if (((piv >> i) & 1u) && ((sb >> i) & 1u)) {
-            const int q = (int)(uint32_t)keys[pcol[i]];
-            atomicOr(&ebits[q >> 5], 1u << (q & 31));
+        if ((piv >> i) & 1u) {
+            uint32_t bit = (sb >> i) & 1u;
+            if constexpr (CS) {
+                if (ca >= 0) {
+                    uint64_t wa = 0ull, wb = 0ull;
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        wa = (k == (ca >> 6)) ? row[i][k] : wa;
+                        wb = (cb >= 0 && k == (cb >> 6)) ? row[i][k] : wb;
+                    }
+                    bit ^= (uint32_t)((wa >> (ca & 63)) & 1ull);
+                    if (cb >= 0) bit ^= (uint32_t)((wb >> (cb & 63)) & 1ull);
+                }
+            }
+            if (bit) {
+                const int q = (int)(uint32_t)keys[pcol[i]];
+                atomicOr(&ebits[q >> 5], 1u << (q & 31));
+            }
         }
     __syncthreads();
     if (flags[1] != 0) return;

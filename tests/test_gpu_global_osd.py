@@ -136,3 +136,64 @@ def test_global_osd_paths_identical_and_limits():
         gpu_decoder(spec, global_post=1, stage=1)
     with pytest.raises(P.LeadError, match="UNSUPPORTED"):
         gpu_decoder(standard("L"), global_post=1, max_shots=64)
+
+
+@pytest.mark.parametrize("name,t,p,T,order", [("T", 0, 0.08, 8, 3), ("T", 1, 0.06, 12, 3), ("M", 0, 0.06, 8, 3),
+                                             ("M", 0, 0.04, 20, 3), ("M", 0, 0.06, 8, 1), ("M", 0, 0.06, 8, 8)])
+def test_global_osd_cs_matches_oracle(name, t, p, T, order):
+    """Combination sweep of order lambda after global BP (the paper's global
+    decoder runs it at order 3), against the oracle."""
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=T, max_iter_global=T, global_post=1, osd_order=order)
+    e, s, lam = bitflip_inputs(oc, 160, p, seed=95, t=t)
+    s = _gpu_syndrome(dec, e)
+    g = run_gpu(dec, s, lam, 0, lam=True)
+    orc = oracle_decode_conditioned(oc, s, lam, t=t, max_iter_local=T, max_iter_global=T, global_osd=1,
+                                    osd_order=order)
+    res = compare(orc, g, oc.n)
+    n_osd = _check_osd_shots(orc, g, oc.n, oc.H(t), s)
+    # the sweep changes some estimates relative to OSD-0
+    o0 = oracle_decode_conditioned(oc, s, lam, t=t, k=0, max_iter_local=T, max_iter_global=T, global_osd=1)
+    changed = int((o0["ehat"] != orc["ehat"]).any(axis=1).sum())
+    log(f"[global-osd-cs] {name} t={t} p={p} T={T} order={order}: {res['bad']} differ, {res['tie']} ill-conditioned, "
+        f"OSD-resolved {int((orc['stats'][:, 0] == 2).sum())} ({n_osd} well-conditioned), "
+        f"{changed} estimates differ from OSD-0")
+    assert not res["unexplained"], res["detail"]
+    assert n_osd > 0 and changed > 0
+
+
+def test_global_bp_osd_cs_matches_oracle():
+    """Stage GLOBAL: BP followed by OSD-CS of order 3 on H_t alone, costs from
+    the channel prior."""
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_global=12, stage=GLOBAL, global_post=1, osd_order=3)
+    e, s, lam = bitflip_inputs(oc, 160, 0.06, seed=97)
+    s = _gpu_syndrome(dec, e)
+    g = run_gpu(dec, s, lam, 0)
+    orc = oracle_global_conditioned(oc, s, lam, max_iter_global=12, global_osd=1, osd_order=3)
+    res = compare(orc, {"post": g["post"], "ehat": g["ehat"], "stats": g["stats"][:, :2]}, oc.n, what=("post",))
+    n_osd = _check_osd_shots(orc, g, oc.n, oc.H(0), s)
+    log(f"[global-bp-osd-cs] M: {res['bad']} differ, {res['tie']} ill-conditioned, {n_osd} well-conditioned OSD shots")
+    assert not res["unexplained"], res["detail"]
+    assert n_osd > 0
+
+
+def test_global_osd_cs_forms_identical_and_limits():
+    import paper_2605_17796_amd as P
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_local=10, max_iter_global=10, global_post=1, osd_order=3, max_shots=1024)
+    e, _, _ = bitflip_inputs(oc, 300, 0.06, seed=9)
+    s = _gpu_syndrome(dec, e)
+    lam = np.full(300, 2.75, dtype=np.float32)
+    runs = {}
+    for key, sched in (("f2", dict(specialized=2)), ("f1", dict(specialized=1)), ("pre", dict(specialized=0)),
+                       ("fused", dict(specialized=0, fused=1))):
+        dec.set_schedule(**sched)
+        runs[key] = run_gpu(dec, s, lam, 0, lam=key != "pre")
+    for key, r in runs.items():
+        for k in ("ehat", "post", "stats"):
+            assert np.array_equal(r[k], runs["f2"][k]), (key, k)
+    with pytest.raises(P.LeadError, match="ARG"):
+        gpu_decoder(spec, global_post=1, osd_order=9)
+    with pytest.raises(P.LeadError, match="ARG"):
+        gpu_decoder(spec, osd_order=3)
