@@ -492,7 +492,7 @@ def main():
     served = None
     if not args.no_served:
         served = {}
-        reqs_m = request_mix(torch, decs_named, 400, seed=31, codes=["M"])
+        reqs_m = request_mix(torch, decs_named, 10000, seed=31, codes=["M"])
         served["A5_only"] = [served_stream(P, [dec], reqs_m, load, seed=41) for load in (1e6, 4e6)]
         # the same requests served without batching: one request at a time,
         # copy-in, plain decode, copy-out
@@ -504,7 +504,7 @@ def main():
             pshots += s.shape[0]
         served["A5_plain_one_request_at_a_time_shots_per_s"] = round(pshots / (time.perf_counter() - t0), 1)
         if not args.no_mixed:
-            reqs_x = request_mix(torch, decs_named, 300, seed=32, codes=["T", "M", "L"])
+            reqs_x = request_mix(torch, decs_named, 2000, seed=32, codes=["T", "M", "L"])
             decs_x = [decs_named[c][1] for c in ("T", "M", "L")]
             served["mixed_3_codes"] = [served_stream(P, decs_x, reqs_x, 2e5, seed=42)]
 
