@@ -92,6 +92,7 @@ std::string source(const Code &c, int t, bool sp) {
     o << "#include \"lead_spec.hpp\"\n"
       << "struct LeadCode {\n"
       << "    static constexpr int D = " << D << ", R = " << tt.r << ", NFIX = " << nfix << ";\n"
+      << "    static constexpr bool SPLIT = " << (tt.eloc > kTwoWaveMaxEdges ? "true" : "false") << ";\n"
       << "    static constexpr uint64_t mask[" << tt.r << "] = {";
     for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";
     o << "};\n    static constexpr int sigma[" << D2 << "] = {";

@@ -191,7 +191,12 @@ struct Explicit {
             // where |mu_k| == n1 and the clamped comparison differ, both
             // minima clamp to the same value.  Messages are bit for bit those
             // of clamping each mu.
-            float n1 = kBig, n2 = kBig, mu[D2];
+            // With C::SPLIT the two smallest are tracked over the first and
+            // the second half of the edges separately and then merged
+            // (shorter dependency chains for kernels that run one wave per
+            // SIMD); min and max are exact, so n1 and n2 are the same values.
+            constexpr int h = C::SPLIT ? C::deg[c] / 2 : C::deg[c];
+            float n1 = kBig, n2 = kBig, n1b = kBig, n2b = kBig, mu[D2];
             uint32_t par = 0u, ps = 0u, pend = 0u;
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
@@ -203,9 +208,18 @@ struct Explicit {
                 } else {
                     par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
                 }
-                n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[j]));
-                n1 = fminf(n1, fabsf(mu[j]));
+                if constexpr (k < h) {
+                    n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[j]));
+                    n1 = fminf(n1, fabsf(mu[j]));
+                } else {
+                    n2b = __builtin_amdgcn_fmed3f(n1b, n2b, fabsf(mu[j]));
+                    n1b = fminf(n1b, fabsf(mu[j]));
+                }
             });
+            if constexpr (h < C::deg[c]) {
+                n2 = fminf(fmaxf(n1, n1b), fminf(n2, n2b));
+                n1 = fminf(n1, n1b);
+            }
             for_edges<C, c>([&](auto jj, auto kk) {
                 constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
                 if constexpr ((k & 1) == 0) {
@@ -762,6 +776,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     st.clear();
     if (!BPERM) __syncthreads();
     bool done = !live;
+    bool wdone = false;   // the workgroup's shot has ended (one shot per workgroup, !BPERM)
     int itg = 0, gconv = 0, gfix = 0;
     // lanes of this lane's shot within the wave (one-wave workgroups)
     const uint64_t smask = lane_ok ? ((a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull)) << (sl * a.N)) : 0ull;
@@ -776,11 +791,14 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             shot_sat = (unsat & smask) == 0ull;
             shot_same = (chg & smask) == 0ull;
         } else {
-            if (!done && !sat) shf[sl * SF_STRIDE + (t & 1)] = 1;
-            if (!done && !same) shf[sl * SF_STRIDE + SF_CHG] = t;
+            // more than 64 views: one shot per workgroup (its live lanes
+            // have sl = 0), whose flags every lane reads, so that the end of
+            // its run is known to all lanes without a second barrier
+            if (!done && !sat) shf[(t & 1)] = 1;
+            if (!done && !same) shf[SF_CHG] = t;
             __syncthreads();
-            shot_sat = shf[sl * SF_STRIDE + (t & 1)] == 0;
-            shot_same = shf[sl * SF_STRIDE + SF_CHG] != t;
+            shot_sat = shf[(t & 1)] == 0;
+            shot_same = shf[SF_CHG] != t;
         }
         if (!done && t > 1) {
             if (shot_sat && a.early_exit) {
@@ -799,8 +817,10 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         if constexpr (BPERM) {
             if (__ballot(!done) == 0ull) break;
         } else {
-            if (!__syncthreads_or(done ? 0 : 1)) break;
-            if (lane_ok && v == 0) shf[sl * SF_STRIDE + ((t + 1) & 1)] = 0;
+            // the live lanes' own decision above, taken by every lane
+            if (!wdone && t > 1 && ((shot_sat && a.early_exit) || (a.fixed_stop && shot_same))) wdone = true;
+            if (wdone) break;
+            if (tid == 0) shf[((t + 1) & 1)] = 0;
         }
         // partial sums of this view, then S_j = P_j + P of the other occurrence
         partial_sums<C>(st, lam, fown, S);
