@@ -147,8 +147,8 @@ typedef struct {
     int32_t bp;               /* lead_bp.  Sum-product runs on the kernels
                                  compiled for the code with one register per
                                  message (views of at most 128 local edges),
-                                 in lead_decode, batches and the server;
-                                 lead_decode_plain and stage GLOBAL are
+                                 in lead_decode, batches and the server,
+                                 stage GLOBAL included; lead_decode_plain is
                                  min-sum only (LEAD_E_UNSUPPORTED)            */
     int32_t global_post;      /* 1: a shot whose global BP ends with H e != s
                                  is followed by OSD-0 on H_t with the global
@@ -210,8 +210,8 @@ void lead_decoder_destroy(lead_decoder *dec);
  * work-queue kernel for Phase 1 and a per-shot kernel for Phases 2-3, both
  * compiled for the decoder's code; or one fused per-shot kernel.  Every
  * schedule gives bit-identical outputs.  In the GLOBAL stage only the global
- * BP runs (on the fused per-shot kernel), with prior lambda' = the channel
- * LLR of each qubit.
+ * BP runs (on the per-shot kernel compiled for the code, or the fused
+ * precompiled kernel), with prior lambda' = the channel LLR of each qubit.
  *   d_synd      shots x synd_words packed syndromes, synd_words >= ceil(m/64)
  *   d_prior     channel LLRs ln((1-p)/p): PER_SHOT: shots floats; SHARED: n
  *               floats; FULL: shots x n floats

@@ -89,8 +89,6 @@ lead_status check_params(const lead_params *p) {
     if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL && p->stage != LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_ARG, "bad stage");
     if (p->bp != LEAD_BP_MINSUM && p->bp != LEAD_BP_SUMPRODUCT) return fail(LEAD_E_ARG, "bad bp");
-    if (p->bp == LEAD_BP_SUMPRODUCT && p->stage == LEAD_STAGE_GLOBAL)
-        return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL runs min-sum only");
     if (p->local_post != 0 && p->local_post != 1) return fail(LEAD_E_ARG, "bad local_post");
     if (p->local_post && p->stage == LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL has no local phase to post-process");
@@ -149,14 +147,21 @@ int spec_form(const lead_decoder *d, int want) {
 hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArgs w, hipStream_t s,
                        std::array<hipEvent_t, 3> *ev) {
     const lead::jit::Kernels &k = *d->spec;
-    hipError_t e = lead::launch_reset_counter(w.counter, s);
-    if (e == hipSuccess && ev) e = hipEventRecord((*ev)[0], s);
-    if (e != hipSuccess) return e;
     const int f = d->sched.specialized - 1;
-    void *largs[] = {&a, &w};
-    e = hipModuleLaunchKernel(k.local[f][a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1, 64,
-                              1, 1, 0, s, largs, nullptr);
-    if (e == hipSuccess && ev) e = hipEventRecord((*ev)[1], s);
+    hipError_t e = hipSuccess;
+    if (a.global_only) {
+        // global BP alone: no Phase 1
+        if (ev) e = hipEventRecord((*ev)[0], s);
+        if (e == hipSuccess && ev) e = hipEventRecord((*ev)[1], s);
+    } else {
+        e = lead::launch_reset_counter(w.counter, s);
+        if (e == hipSuccess && ev) e = hipEventRecord((*ev)[0], s);
+        if (e != hipSuccess) return e;
+        void *largs[] = {&a, &w};
+        e = hipModuleLaunchKernel(k.local[f][a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1,
+                                  64, 1, 1, 0, s, largs, nullptr);
+        if (e == hipSuccess && ev) e = hipEventRecord((*ev)[1], s);
+    }
     if (e != hipSuccess) return e;
     a.spw = k.spw;
     lead::SpecArgs x{d->d_pv, d->d_fown};
@@ -280,9 +285,10 @@ hipError_t drain_timing(lead_decoder *d) {
 hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
                          const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post,
                          float *lam, lead_shot_stats *stats, int stage, hipStream_t s) {
-    // global BP alone runs on the fused per-shot kernel (there is no Phase 1)
+    // global BP alone: the per-shot kernel alone (there is no Phase 1); the
+    // precompiled form runs it fused
     const bool gonly = d->params.stage == LEAD_STAGE_GLOBAL;
-    const bool split = !d->sched.fused && !gonly;
+    const bool split = !d->sched.fused && (!gonly || use_spec(d));
     // global OSD-0 after global BP (its buffers hold ws_shots shots)
     const bool gpost = d->params.global_post && stage != LEAD_STAGE_LOCAL;
     // equal chunks of at most ws_shots (no small tail launch)

@@ -693,15 +693,21 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     int it_v = 0, conv_v = 0, fixed_v = 0, osd_v = 0;
     if (live) {
         sv = local_syndrome(a, shot, v);
-        const int64_t item = shot * a.N + v;
-        const float *in = w.Lv + item * D2;
+        if (a.global_only) {
+            // global BP alone: no local phase, lambda' is the channel prior
 #pragma unroll
-        for (int j = 0; j < D2; ++j) S[j] = in[j];
-        const uint32_t f = w.vflag[item];
-        it_v = (int)(f & 0xffffu);
-        conv_v = (int)((f >> 16) & 1u);
-        fixed_v = (int)((f >> 17) & 1u);
-        osd_v = (int)((f >> 18) & 1u);
+            for (int j = 0; j < D2; ++j) S[j] = 0.f;
+        } else {
+            const int64_t item = shot * a.N + v;
+            const float *in = w.Lv + item * D2;
+#pragma unroll
+            for (int j = 0; j < D2; ++j) S[j] = in[j];
+            const uint32_t f = w.vflag[item];
+            it_v = (int)(f & 0xffffu);
+            conv_v = (int)((f >> 16) & 1u);
+            fixed_v = (int)((f >> 17) & 1u);
+            osd_v = (int)((f >> 18) & 1u);
+        }
         const uint32_t base = (uint32_t)(sl * a.N);
         using A = PartnerAddr<BPERM>;
 #pragma unroll
@@ -733,7 +739,12 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     // both occurrences of a qubit compute the same value); the confidence
     // boost L <- min(L, 0) on L < 0 leaves L unchanged.
     float lam[D2];
-    {
+    if (a.global_only) {
+        const int64_t base = a.prior_mode == 2 ? shot * a.n : 0;   // LEAD_PRIOR_FULL
+#pragma unroll
+        for (int j = 0; j < D2; ++j)
+            lam[j] = live ? (a.prior_mode == 0 ? a.prior[shot] : a.prior[base + a.view[v * D2 + j]]) + 0.f : 0.f;
+    } else {
         float Lp[D2];
         store_all<C, WG, BPERM>(S, buf);
         partner_all<C, WG, BPERM, NW>(S, Lp, buf, pa);

@@ -64,3 +64,29 @@ def test_global_only_forms_identical():
     for k in ("ehat", "post", "lam", "stats"):
         assert torch.equal(a[k], b[k]), k
         assert torch.equal(a[k], out[k]), k
+
+
+@pytest.mark.parametrize("name,mode", [("T", 0), ("M", 0), ("M", 1), ("M", 2), ("L", 0)])
+def test_global_only_specialised_equals_fused(name, mode):
+    """Stage GLOBAL on the per-shot kernel compiled for the code (both check
+    state forms) and on the fused precompiled kernel: the same bits, for every
+    prior mode."""
+    spec, oc = code_pair(name)
+    T = {"T": 32, "M": 50, "L": 20}[name]
+    shots = {"T": 700, "M": 300, "L": 40}[name]
+    code, dec = gpu_decoder(spec, max_iter_global=T, stage=GLOBAL, max_shots=1024)
+    e, _, _ = bitflip_inputs(oc, shots, 0.04, seed=5 + mode)
+    s = _gpu_syndrome(dec, e)
+    rng = np.random.default_rng(mode)
+    prior = {0: channel_llr(uniform_p(shots, 0.02, 0.06, 8)).astype(np.float32),
+             1: channel_llr(rng.uniform(0.02, 0.06, oc.n)).astype(np.float32),
+             2: channel_llr(rng.uniform(0.02, 0.06, (shots, oc.n))).astype(np.float32)}[mode]
+    runs = {}
+    for key, sched in (("f2", dict(specialized=2)), ("f1", dict(specialized=1)), ("fused", dict(specialized=0, fused=1))):
+        dec.set_schedule(**sched)
+        runs[key] = run_gpu(dec, s, prior, mode, lam=True)
+    for key in ("f1", "fused"):
+        for k in ("ehat", "post", "lam", "stats"):
+            assert np.array_equal(runs["f2"][k], runs[key][k]), (key, k)
+    log(f"[global-only forms] {name} mode={mode}: {shots} shots identical, converged "
+        f"{runs['f2']['stats'][:, 0].mean():.3f}")

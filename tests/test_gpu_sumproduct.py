@@ -64,17 +64,34 @@ def test_sum_product_batched_and_served_equal_alone():
     assert np.array_equal(r["stats"], a["stats"].cpu().numpy())
 
 
+@pytest.mark.parametrize("name,p,T", [("T", 0.05, 10), ("M", 0.03, 12)])
+def test_sum_product_global_only_matches_oracle(name, p, T):
+    """Sum-product global BP alone (stage GLOBAL, channel priors), at caps
+    short enough that FP32 rounding is not amplified beyond the tolerance on
+    shots that do not converge (global BP alone leaves many of them)."""
+    from gpu_common import oracle_global_conditioned
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, max_iter_global=T, stage=2, bp=SP)
+    e, s, lam = bitflip_inputs(oc, 200, p, seed=73)
+    s = _gpu_syndrome(dec, e)
+    g = run_gpu(dec, s, lam, 0, lam=True)
+    assert np.array_equal(g["lam"], np.broadcast_to(lam[:, None], g["lam"].shape))
+    orc = oracle_global_conditioned(oc, s, lam, max_iter_global=T, bp=SP)
+    res = compare(orc, {"post": g["post"], "ehat": g["ehat"], "stats": g["stats"][:, :2]}, oc.n, what=("post",))
+    log(f"[sum-product global-only] {name} p={p} T={T}: {res['bad']} differ, {res['tie']} ill-conditioned")
+    assert not res["unexplained"], res["detail"]
+    assert res["tie"] <= 0.6 * res["shots"]
+
+
 def test_sum_product_limits():
-    """Views above 128 local edges (PSL(2,7)), the plain per-round form and the
-    GLOBAL stage are min-sum only."""
+    """Views above 128 local edges (PSL(2,7)) and the plain per-round form are
+    min-sum only."""
     import paper_2605_17796_amd as P
     torch = torch_dev()
     spec, oc = code_pair("L")
     with pytest.raises(P.LeadError, match="UNSUPPORTED"):
         gpu_decoder(spec, bp=SP)
     spec, oc = code_pair("T")
-    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
-        gpu_decoder(spec, bp=SP, stage=2)
     code, dec = gpu_decoder(spec, bp=SP)
     s = torch.zeros((4, 1), dtype=torch.int64, device="cuda")
     lam = torch.full((4,), 2.9, dtype=torch.float32, device="cuda")
