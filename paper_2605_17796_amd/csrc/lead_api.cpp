@@ -56,7 +56,8 @@ struct lead_decoder {
     int waves_per_cu[2] = {4, 4};
     float *d_Lv = nullptr;
     uint32_t *d_vflag = nullptr;
-    int64_t *d_counter = nullptr;
+    int64_t *d_counter = nullptr;          // [0] queue head, [1] local OSD list length
+    uint32_t *d_osd_list = nullptr;        // views pending local OSD-0 (ws_shots * N)
     // phase timing: event triples (before Phase 1, between, after Phases 2-3)
     bool timing = false;
     std::vector<std::array<hipEvent_t, 3>> tev;
@@ -160,6 +161,9 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
         void *largs[] = {&a, &w};
         e = hipModuleLaunchKernel(k.local[f][a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1,
                                   64, 1, 1, 0, s, largs, nullptr);
+        // local OSD-0 of the views the queue kernel listed (lanes stride over the list)
+        if (e == hipSuccess && a.local_osd)
+            e = hipModuleLaunchKernel(k.local_osd, (unsigned)(8 * d->cus), 1, 1, 64, 1, 1, 0, s, largs, nullptr);
         if (e == hipSuccess && ev) e = hipEventRecord((*ev)[1], s);
     }
     if (e != hipSuccess) return e;
@@ -181,6 +185,7 @@ lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode
     w.Lv = d->d_Lv;
     w.vflag = d->d_vflag;
     w.counter = d->d_counter;
+    w.osd_list = d->d_osd_list;
     w.items = shots * d->N;
     w.chunk = d->sched.local_chunk;
     const int pm = mode == LEAD_PRIOR_PER_SHOT ? 0 : 1;
@@ -540,7 +545,8 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
     if (e == hipSuccess) e = hipMemcpy(d->d_own, own.data(), sizeof(uint32_t) * own.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d->d_Lv, sizeof(float) * (size_t)d->ws_shots * d->N * D2);
     if (e == hipSuccess) e = hipMalloc(&d->d_vflag, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
-    if (e == hipSuccess) e = hipMalloc(&d->d_counter, sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&d->d_counter, 2 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&d->d_osd_list, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
     // kernels for this code's check structure (the precompiled ones serve
     // when they cannot be built)
     if (e == hipSuccess) {
@@ -581,6 +587,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             (void)hipFree(d->d_Lv);
             (void)hipFree(d->d_vflag);
             (void)hipFree(d->d_counter);
+            (void)hipFree(d->d_osd_list);
             (void)hipFree(d->d_pv);
             (void)hipFree(d->d_fown);
             (void)hipFree(d->d_rptr);
@@ -594,6 +601,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
         (void)hipFree(d->d_Lv);
         (void)hipFree(d->d_vflag);
         (void)hipFree(d->d_counter);
+        (void)hipFree(d->d_osd_list);
         (void)hipFree(d->d_pv);
         (void)hipFree(d->d_fown);
         (void)hipFree(d->d_rptr);
@@ -726,6 +734,7 @@ void lead_decoder_destroy(lead_decoder *d) {
     (void)hipFree(d->d_Lv);
     (void)hipFree(d->d_vflag);
     (void)hipFree(d->d_counter);
+    (void)hipFree(d->d_osd_list);
     (void)hipFree(d->d_pv);
     (void)hipFree(d->d_fown);
     (void)hipFree(d->d_rptr);

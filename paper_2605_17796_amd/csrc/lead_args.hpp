@@ -50,7 +50,8 @@ struct LocalArgs {
     float *Lv;                 // [shots][N][D2] clamped local posteriors
     uint32_t *vflag;           // [shots][N] iterations | converged << 16 | fixed point << 17
                                //            | resolved by OSD-0 << 18
-    int64_t *counter;          // work-queue head
+    int64_t *counter;          // [0] work-queue head, [1] entries of osd_list
+    uint32_t *osd_list;        // items whose local BP missed the local syndrome (local OSD-0 pending)
     int64_t items;             // shots * N
     int32_t chunk;             // items a wave takes at a time
     int32_t waves;             // waves launched

@@ -131,6 +131,8 @@ std::string source(const Code &c, int t, bool sp) {
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
     }
+    o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_osd(lead::DecodeArgs a, lead::LocalArgs w) "
+         "{ lead_spec::local_osd_body<LeadCode>(a, w); }\n";
     if (osd_fits(c, t)) {
         const int m = c.order * tt.r;
         int sortn = 1;
@@ -231,6 +233,7 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
                 k->local_waves_per_cu[form - 1][pm] = nb;
         }
     }
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->local_osd, k->module, "lead_spec_local_osd");
     if (e == hipSuccess && osd_fits(c, t)) {
         e = hipModuleGetFunction(&k->osd, k->module, "lead_spec_osd");
         if (e == hipSuccess) e = hipModuleGetFunction(&k->osd_cs, k->module, "lead_spec_osd_cs");

@@ -45,6 +45,7 @@ struct Kernels {
     // [form - 1][prior mode]: Phase 1 queue kernel for per-shot / per-qubit priors
     hipFunction_t local[kForms][2] = {};
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
+    hipFunction_t local_osd = nullptr;   // OSD-0 on the views listed by the queue kernel
     hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
     hipFunction_t osd_cs = nullptr;      // the same with the combination sweep
     int osd_wg = 0;                      // its workgroup size

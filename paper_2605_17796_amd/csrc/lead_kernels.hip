@@ -300,7 +300,10 @@ __global__ void __launch_bounds__(64) local_kernel(DecodeArgs a, LocalArgs w) {
 
 // Work queue reset before a local_kernel launch (a kernel rather than a
 // memset, so that the launch sequence can be captured in a graph).
-__global__ void reset_counter_kernel(int64_t *counter) { *counter = 0; }
+__global__ void reset_counter_kernel(int64_t *counter) {
+    counter[0] = 0;   // work-queue head
+    counter[1] = 0;   // local OSD-0 list
+}
 
 // Phases 2-3 of a shot group (and, for SPLIT = false, Phase 1 as well: every
 // lane runs its view's local BP in place, and the wave waits for its slowest

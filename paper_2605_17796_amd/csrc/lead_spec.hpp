@@ -545,26 +545,13 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
             float Lc[D2];
 #pragma unroll
             for (int j = 0; j < D2; ++j) Lc[j] = clampf(S[j], a.clampv);
-            uint32_t osd = 0u;
-            if (a.local_osd && !conv) {
-                // OSD-0 estimate; the view then counts as converged, and the
-                // confidence boost (p <- max(p, 1/2) on its errors, i.e.
-                // L <- min(L, 0)) applies to it
-                bool ok;
-                const uint64_t e = osd0<C>(Lc, sv, ok);
-                if (ok) {
-                    conv = 1;
-                    osd = 1u;
-                    if (a.boost) {
-#pragma unroll
-                        for (int j = 0; j < D2; ++j)
-                            if ((e >> j) & 1ull) Lc[j] = fminf(Lc[j], 0.f);
-                    }
-                }
-            }
 #pragma unroll
             for (int j = 0; j < D2; ++j) out[j] = Lc[j];
-            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17) | (osd << 18);
+            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
+            // a view that missed its local syndrome is post-processed by
+            // local_osd_body with every lane busy, not here with one
+            if (a.local_osd && !conv)
+                w.osd_list[atomicAdd(reinterpret_cast<unsigned long long *>(w.counter + 1), 1ull)] = (uint32_t)item;
             valid = false;
         }
         ++t;
@@ -610,6 +597,38 @@ __device__ __forceinline__ void partial_sums(const ST &st, const float (&lam)[C:
             }
         });
     });
+}
+
+// Local post-processing of the views listed by the queue kernel: OSD-0 on
+// the view (osd0 above); where it reaches the local syndrome the view counts
+// as converged, is flagged as resolved by OSD-0, and the confidence boost
+// (p <- max(p, 1/2) on its errors, i.e. L <- min(L, 0)) is applied to its
+// stored posteriors.  Lanes stride over the list.
+template <class C>
+__device__ __forceinline__ void local_osd_body(const DecodeArgs &a, const LocalArgs &w) {
+    constexpr int D2 = C::D * C::D;
+    const int64_t count = w.counter[1];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const int64_t item = w.osd_list[i];
+        const int64_t shot = item / a.N;
+        const int v = (int)(item - shot * a.N);
+        const uint64_t sv = local_syndrome(a, shot, v);
+        float *io = w.Lv + item * D2;
+        float Lc[D2];
+#pragma unroll
+        for (int j = 0; j < D2; ++j) Lc[j] = io[j];
+        bool ok;
+        const uint64_t e = osd0<C>(Lc, sv, ok);
+        if (ok) {
+            if (a.boost) {
+#pragma unroll
+                for (int j = 0; j < D2; ++j)
+                    if ((e >> j) & 1ull) io[j] = fminf(Lc[j], 0.f);
+            }
+            w.vflag[item] |= (1u << 16) | (1u << 18);
+        }
+    }
 }
 
 // Per-shot LDS flags (the precompiled kernel's layout).
