@@ -1021,11 +1021,31 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
 
     // ---- Gauss-Jordan over the ranked columns, one 64-column word at a
     // time (compile-time word index, so each step touches words w.. only)
+    __shared__ uint64_t cmw[2][NWAVE];   // per-wave OR of the non-pivot rows' current word
     int rank = 0, par = 0;
     static_for<0, W>([&](auto ww) {
         constexpr int w = decltype(ww)::value;
-        constexpr int bmax = (w == W - 1) ? NQ - 64 * (W - 1) : 64;
-        for (int b = 0; b < bmax && rank < G::RANK; ++b, par ^= 1) {
+        if (rank >= G::RANK) return;
+        // columns of this word that some non-pivot row has: the others can
+        // take no pivot in it (a row added to another is a non-pivot row up
+        // to then, so a column no non-pivot row has keeps none)
+        uint64_t any = 0ull;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) any |= ((piv >> i) & 1u) ? 0ull : row[i][w];
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)any, sh);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(any >> 32), sh);
+            any |= ((uint64_t)hi << 32) | lo;
+        }
+        if (NWAVE > 1) {
+            if (lane == 0) cmw[w & 1][wave] = any;
+            __syncthreads();
+#pragma unroll
+            for (int x = 0; x < NWAVE; ++x) any |= cmw[w & 1][x];
+        }
+        for (uint64_t todo = any; todo && rank < G::RANK; todo &= todo - 1ull, par ^= 1) {
+            const int b = __builtin_ctzll(todo);
             // lowest-numbered non-pivot row with bit (w, b): rows are
             // numbered tid + WG i, so the first i with a candidate in any
             // wave wins, then the lowest wave, then the lowest lane
