@@ -196,8 +196,9 @@ typedef struct {
 /* Creates a decoder for the checks of type `t` and uploads the device tables
  * of the code to the current HIP device.  `max_shots` bounds the batch size
  * of every later call.  The decoder allocates a workspace for min(max_shots,
- * 32768) shots (local posteriors: order * delta^2 floats per shot); larger
- * batches are decoded chunk by chunk on the same stream.  lead_decode_plain
+ * W) shots, W = max(32768, the shots whose local posteriors (order * delta^2
+ * floats per shot) and flags fit in 1 GiB); larger batches are decoded chunk
+ * by chunk on the same stream.  lead_decode_plain
  * allocates its per-round state (for max_shots shots) on first use. */
 lead_status lead_decoder_create(const lead_code *code, lead_check_type t, const lead_params *params,
                                 int64_t max_shots, lead_decoder **out);
@@ -263,6 +264,9 @@ typedef struct {
                                      the form in use (a form that was not
                                      compiled is replaced by the other). The
                                      default is 2 where compiled, else 1.       */
+    int32_t chunk_shots;          /* shots per launch of the work-queue form
+                                     (at most the workspace); 0: the workspace.
+                                     Larger launches leave fewer kernel tails. */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);

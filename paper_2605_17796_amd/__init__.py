@@ -55,7 +55,7 @@ class lead_params(C.Structure):
 
 class lead_schedule(C.Structure):
     _fields_ = [("shots_per_workgroup", C.c_int32), ("fused", C.c_int32), ("local_chunk", C.c_int32),
-                ("local_waves", C.c_int32), ("specialized", C.c_int32)]
+                ("local_waves", C.c_int32), ("specialized", C.c_int32), ("chunk_shots", C.c_int32)]
 
 
 class lead_phase_times(C.Structure):
@@ -375,9 +375,10 @@ class Decoder:
         self.params = lead_params_make(**params)
         lead_decoder_set_params(self._h, self.params)
 
-    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=2):
+    def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=2,
+                     chunk_shots=0):
         lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves,
-                                                         specialized))
+                                                         specialized, chunk_shots))
 
     def get_schedule(self) -> dict:
         sc = lead_decoder_get_schedule(self._h)

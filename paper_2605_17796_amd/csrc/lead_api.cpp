@@ -102,7 +102,11 @@ lead_status check_params(const lead_params *p) {
     return LEAD_OK;
 }
 
+// Shots per launch of the work-queue form: at least kChunkShots, more while
+// the Phase 1 workspace (local posteriors and flags) stays within
+// kChunkBytes (fewer launches, so fewer kernel tails).
 constexpr int64_t kChunkShots = 32768;
+constexpr int64_t kChunkBytes = int64_t(1) << 30;
 
 int default_spw(int N) { return std::max(1, 64 / N); }
 
@@ -296,8 +300,9 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
     const bool split = !d->sched.fused && (!gonly || use_spec(d));
     // global OSD-0 after global BP (its buffers hold ws_shots shots)
     const bool gpost = d->params.global_post && stage != LEAD_STAGE_LOCAL;
-    // equal chunks of at most ws_shots (no small tail launch)
-    const int64_t nchunks = split || gpost ? (shots + d->ws_shots - 1) / d->ws_shots : 1;
+    // equal chunks of at most the schedule's chunk (no small tail launch)
+    const int64_t chunk = d->sched.chunk_shots > 0 ? std::min<int64_t>(d->sched.chunk_shots, d->ws_shots) : d->ws_shots;
+    const int64_t nchunks = split || gpost ? (shots + chunk - 1) / chunk : 1;
     const int64_t step = (shots + nchunks - 1) / nchunks;
     for (int64_t off = 0; off < shots; off += step) {
         const int64_t cnt = std::min(step, shots - off);
@@ -524,7 +529,8 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     e = hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, d->device);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-    d->ws_shots = std::min<int64_t>(std::max<int64_t>(max_shots, 1), kChunkShots);
+    const int64_t per_shot = (int64_t)d->N * ((int64_t)D2 * (int64_t)sizeof(float) + (int64_t)sizeof(uint32_t));
+    d->ws_shots = std::min<int64_t>(std::max<int64_t>(max_shots, 1), std::max<int64_t>(kChunkShots, kChunkBytes / per_shot));
     d->waves_per_cu[0] = lead::local_waves_per_cu(D, 0);
     d->waves_per_cu[1] = lead::local_waves_per_cu(D, 1);
     // owner lists: per view, owned local positions in increasing order
@@ -684,7 +690,7 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
 
 lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) {
     if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
-    if (sc->shots_per_workgroup < 0 || sc->local_chunk < 0 || sc->local_waves < 0)
+    if (sc->shots_per_workgroup < 0 || sc->local_chunk < 0 || sc->local_waves < 0 || sc->chunk_shots < 0)
         return fail(LEAD_E_ARG, "negative schedule field");
     const int spw = sc->shots_per_workgroup ? sc->shots_per_workgroup : default_spw(d->N);
     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup)
@@ -696,6 +702,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.fused = sc->fused ? 1 : 0;
     d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
     d->sched.local_waves = sc->local_waves;
+    d->sched.chunk_shots = sc->chunk_shots;
     d->sched.specialized = spec_form(d, sc->specialized);
     if (needs_spec(d)) {   // sum-product and OSD-0 run the kernels compiled for the code only
         d->sched.fused = 0;

@@ -188,8 +188,8 @@ def test_schedule_does_not_change_results(sched):
 
 
 def test_chunked_large_batch():
-    """Batches above the workspace (32768 shots) are decoded chunk by chunk
-    with the same results as shot-by-shot sub-batches."""
+    """Batches decoded in one launch and chunk by chunk (32768-shot chunks)
+    give the same results as shot-by-shot sub-batches."""
     torch = torch_dev()
     spec, oc = code_pair("T")
     code, dec = gpu_decoder(spec, max_shots=70000)
@@ -197,10 +197,13 @@ def test_chunked_large_batch():
     synd = torch.from_numpy(_gpu_syndrome(dec, e).view(np.int64)).cuda()
     lam = torch.full((70000,), float(channel_llr(0.05)), dtype=torch.float32, device="cuda")
     big = dec.decode(synd, lam, lam=True)
+    dec.set_schedule(chunk_shots=32768)
+    chunked = dec.decode(synd, lam, lam=True)
     idx = [0, 1, 32767, 32768, 32769, 65535, 65536, 69999]
     part = dec.decode(synd[idx].contiguous(), lam[idx].contiguous(), lam=True)
     torch.cuda.synchronize()
     for k in ("ehat", "post", "lam", "stats"):
+        assert torch.equal(big[k], chunked[k]), k
         assert torch.equal(big[k][idx], part[k]), k
 
 

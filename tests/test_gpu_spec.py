@@ -75,13 +75,15 @@ def test_specialised_equals_precompiled(name, t, mode, params):
 
 def test_specialised_ragged_and_chunked():
     """Shot counts that leave the last workgroup partly empty, and a batch
-    above the 32768-shot workspace."""
+    decoded in 13334-shot chunks."""
     torch = torch_dev()
     spec, oc = code_pair("T")
     code, dec = gpu_decoder(spec, max_shots=40000)
     synd, ps = _inputs(dec, oc, 40000, seed=5, t=0)
     prior = channel_llr(ps).astype(np.float32)
+    dec.set_schedule(chunk_shots=16384)
     full = run_gpu(dec, synd, prior, 0, lam=True)
+    dec.set_schedule()
     for n_sub in (1, 4, 5, 6, 11):
         part = run_gpu(dec, synd[:n_sub], prior[:n_sub], 0, lam=True)
         for k in ("ehat", "post", "lam", "stats"):
@@ -103,10 +105,12 @@ def test_phase_timing():
     synd, ps = _inputs(dec, oc, 40000, seed=8, t=0)
     s = torch.from_numpy(synd.view(np.int64)).cuda()
     prior = torch.from_numpy(channel_llr(ps).astype(np.float32)).cuda()
+    dec.set_schedule(chunk_shots=32768)
+    assert dec.get_schedule()["chunk_shots"] == 32768
     dec.time_phases(True)
     out = dec.decode(s, prior)
     pt = dec.phase_times()
-    assert pt["local_launches"] == 2 and pt["global_launches"] == 2      # 32768 + 7232 shots
+    assert pt["local_launches"] == 2 and pt["global_launches"] == 2      # two equal chunks of 20000
     assert pt["local_ms"] > 0 and pt["global_ms"] > 0
     g = P.Batch([(dec, s, prior, out, P.LEAD_PRIOR_PER_SHOT)]).capture()
     g.replay()
