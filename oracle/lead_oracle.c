@@ -787,9 +787,10 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             it_sum += it_v;
             if (it_v > it_max) it_max = it_v;
             nconv += conv_v;
-            /* local post-processing: OSD-0 where BP left the local syndrome
+            /* local post-processing: OSD (order osd_order, costs from the
+             * view's channel priors) where BP left the local syndrome
              * unsatisfied; its estimate replaces BP's decisions */
-            if (p->local_osd && !conv_v && oracle_osd0(r, D2, c->hloc[type], sv, Lv, ev) == 0) {
+            if (p->local_osd && !conv_v && oracle_osd(r, D2, c->hloc[type], sv, Lv, lamv, p->osd_order, ev) == 0) {
                 conv_v = 1;
                 nosd++;
             }

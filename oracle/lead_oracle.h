@@ -66,9 +66,10 @@ typedef struct {
     /* 1: where global BP ends with H e != s, OSD on H with the global
      * posteriors as reliabilities replaces e (stats converged = 2). */
     int    global_osd;
-    /* order of that OSD: 0 = OSD-0, lambda >= 1 = combination sweep of order
-     * lambda, candidate costs from the global decoder's prior (lambda' in
-     * LEAD, the channel prior in global BP alone); see oracle_osd. */
+    /* order of both OSDs: 0 = OSD-0, lambda >= 1 = combination sweep of
+     * order lambda, candidate costs from the decoder's prior (the view's
+     * channel priors locally; lambda' in LEAD's global stage, the channel
+     * prior in global BP alone); see oracle_osd. */
     int    osd_order;
 } oracle_params;
 

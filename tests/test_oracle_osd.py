@@ -350,3 +350,45 @@ def test_global_osd_cs_in_lead(name):
         assert ok and np.array_equal(e3[i], ref)
         c = lambda x: sum(o.osd_weight(o0["lam"][i][j]) for j in np.nonzero(x)[0])
         assert c(e3[i]) <= c(e0[i])
+
+
+@pytest.mark.parametrize("order", [0, 3])
+def test_local_osd_cs_in_lead(order):
+    """LEAD's local post-processing at order lambda, rebuilt view by view from
+    the oracle's own local posteriors: OSD with the view's channel priors as
+    costs on every view whose BP missed its syndrome, the confidence boost on
+    its errors, then the two-view aggregation of Algorithm 1 Phase 2."""
+    from oracle import oracle as o
+    from lead_inputs import unpack_bits
+    _, oc = code_pair("T")
+    shots, T = 12, 16
+    e = bitflip_packed(shots, oc.n, 0.06, seed=43)
+    s = oc.syndrome(e)
+    lam = np.full(shots, float(channel_llr(0.06)))
+    res = oc.decode(s, lam, p=o.params(max_iter_local=T, max_iter_global=T, local_osd=1, osd_order=order),
+                    want_local=True)
+    H = oc.hloc()
+    view = oc.views()
+    r, D2 = H.shape
+    sb = unpack_bits(s, oc.m())
+    n_osd = 0
+    for i in range(shots):
+        pv = np.zeros(view.shape)
+        for v in range(view.shape[0]):
+            sv = sb[i, v * r:(v + 1) * r]
+            Lv = res["local"][i, v]
+            ev = (Lv < 0).astype(np.uint8)
+            conv = np.array_equal((H.astype(np.int64) @ ev) % 2, sv)
+            p = 1.0 / (1.0 + np.exp(Lv))
+            if not conv:
+                eo, ok = o.osd(H, sv, Lv, prior=np.full(D2, lam[i]), order=order)
+                if ok:
+                    n_osd += 1
+                    p = np.where(eo == 1, np.maximum(p, 0.5), p)
+            pv[v] = p
+        phat = np.zeros(oc.n)
+        np.add.at(phat, view.ravel(), pv.ravel())
+        phat = phat / 2.0
+        ref = np.clip(np.log(1.0 - phat) - np.log(phat), -30.0, 30.0)
+        assert np.allclose(res["lam"][i], ref, rtol=0, atol=1e-9)
+    assert n_osd > 0
