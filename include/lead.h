@@ -135,12 +135,13 @@ typedef struct {
                                  iteration counts are identical to running to
                                  the cap                                       */
     int32_t local_post;       /* 1: a local BP run that ends with H_v e_v != s_v
-                                 is followed by OSD-0 on its view (ordered
-                                 statistics decoding of order 0: variables
-                                 ranked by posterior LLR, most likely in
-                                 error first, ties in position order; the
-                                 solution supported on the first independent
-                                 columns).  The view then counts as converged
+                                 is followed by OSD on its view (ordered
+                                 statistics decoding: variables ranked by
+                                 posterior LLR, most likely in error first,
+                                 ties in position order; the solution
+                                 supported on the first independent columns,
+                                 or with osd_order > 0 the sweep's cheapest
+                                 candidate).  The view then counts as converged
                                  and the confidence boost applies to its
                                  estimate.  Kernels compiled for the code
                                  only (not plain, not stage GLOBAL).  0: none */
@@ -162,20 +163,21 @@ typedef struct {
                                  codes with ceil(m/256) * ceil(n/64) <= 64
                                  (LEAD_E_UNSUPPORTED otherwise, and from
                                  lead_decode_plain).  0: none                  */
-    int32_t osd_order;        /* order lambda of that OSD, 0..8 (needs
-                                 global_post = 1).  0: OSD-0.  lambda >= 1:
-                                 combination sweep (the paper runs its
-                                 global BP-OSD in this mode at order 3):
-                                 candidates are the OSD-0 solution, the
-                                 solution with one bit set on each column
-                                 outside the information set, and the one
-                                 with two bits set on each pair among the
-                                 first lambda of those columns (rank order);
-                                 the estimate is the first candidate of least
-                                 cost sum over set bits of
-                                 round(64 ln(1 + e^{lambda'_j})), lambda' the
-                                 global decoder's prior (the channel prior in
-                                 stage GLOBAL).                               */
+    int32_t osd_order;        /* order lambda of the OSDs of local_post and
+                                 global_post, 0..8 (needs one of them).
+                                 0: OSD-0.  lambda >= 1: combination sweep
+                                 (the paper runs its global BP-OSD in this
+                                 mode at order 3): candidates are the OSD-0
+                                 solution, the solution with one bit set on
+                                 each column outside the information set, and
+                                 the one with two bits set on each pair among
+                                 the first lambda of those columns (rank
+                                 order); the estimate is the first candidate
+                                 of least cost sum over set bits of
+                                 round(64 ln(1 + e^{lambda_j})), lambda the
+                                 decoder's prior: the view's channel LLRs
+                                 locally; lambda' globally (the channel prior
+                                 in stage GLOBAL).                            */
 } lead_params;
 
 /* Per-shot statistics (32 bytes). */

@@ -98,7 +98,8 @@ lead_status check_params(const lead_params *p) {
         return fail(LEAD_E_UNSUPPORTED, "stage LOCAL has no global BP to post-process");
     if (p->osd_order < 0 || p->osd_order > lead::kMaxOsdOrder)
         return fail(LEAD_E_ARG, "osd_order must be in 0.." + std::to_string(lead::kMaxOsdOrder));
-    if (p->osd_order > 0 && !p->global_post) return fail(LEAD_E_ARG, "osd_order needs global_post = 1");
+    if (p->osd_order > 0 && !p->global_post && !p->local_post)
+        return fail(LEAD_E_ARG, "osd_order needs local_post or global_post");
     return LEAD_OK;
 }
 

@@ -14,7 +14,8 @@ using __hip_internal::uint64_t;
 namespace lead {
 
 constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
-constexpr int kMaxOsdOrder = 8;      // largest order of the global OSD's combination sweep
+constexpr int kMaxOsdOrder = 8;      // largest order of the OSD combination sweep
+constexpr int kMaxOsdOrderLocal = kMaxOsdOrder;
 
 // Per-shot statistics as the kernels write them (the layout of the public
 // lead_shot_stats).
@@ -41,7 +42,7 @@ struct DecodeArgs {
     int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
     int32_t global_only;       // no Phase 1; lambda' = the channel prior
     int32_t local_osd;         // OSD-0 after local BP runs that miss the local syndrome
-    int32_t osd_order;         // order of the combination sweep of the global OSD (0: OSD-0)
+    int32_t osd_order;         // order of the OSDs' combination sweep (0: OSD-0)
     uint64_t mask[kMaxChecks];
 };
 

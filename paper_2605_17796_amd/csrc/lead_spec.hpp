@@ -382,43 +382,72 @@ __device__ __forceinline__ uint64_t local_syndrome(const DecodeArgs &a, int64_t 
     return (a.r >= 64) ? x : (x & ((1ull << a.r) - 1ull));
 }
 
-// OSD-0 of the view (local post-processing): positions are taken by
+// Cost of setting a bit whose prior LLR is x in the combination sweep:
+// round(64 ln(1 + e^x)) = round(64 ln(1/p)), p = 1/(1 + e^x), an exact
+// integer so that candidate costs compare the same in any summation order.
+__device__ __forceinline__ int32_t osd_weight(float x) {
+    const float w = fmaxf(x, 0.f) + log1p_nonneg(exp_hw(-fabsf(x)));
+    return (int32_t)__builtin_rintf(64.f * w);
+}
+
+// The r-bit column of local position j (runtime j): the view's checks on it.
+template <class C>
+__device__ __forceinline__ uint32_t local_column(int j) {
+    uint32_t col = 0u;
+    static_for<0, C::R>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        col |= (uint32_t)((C::mask[c] >> j) & 1ull) << c;
+    });
+    return col;
+}
+
+// Position of the smallest key among `left` (equal keys: the lowest
+// position).
+template <int D2>
+__device__ __forceinline__ int take_smallest(const float (&key)[D2], uint64_t left) {
+    float best = __builtin_inff();
+    int bj = -1;
+    static_for<0, D2>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const bool lt = ((left >> j) & 1ull) && (bj < 0 || key[j] < best);
+        best = lt ? key[j] : best;
+        bj = lt ? j : bj;
+    });
+    return bj;
+}
+
+// OSD of the view (local post-processing): positions are taken by
 // round(64 L) of the clamped posterior LLR ascending (most likely in error
 // first; equal keys in position order, so reliabilities that agree to 1/64
-// count as equal), each column (the r-bit set of the view's checks on that position)
-// is reduced against a GF(2) basis kept by lowest set bit and joins it when
-// independent, until the basis has rank r; the estimate is the combination
-// of basis columns that gives the local syndrome (a bit mask over
-// positions).  ok = false when the syndrome is not reached (H_v not of full
-// row rank).
+// count as equal), each column (the r-bit set of the view's checks on that
+// position) is reduced against a GF(2) basis kept by lowest set bit and
+// joins it when independent, until the basis has rank r; the OSD-0 estimate
+// is the combination of basis columns that gives the local syndrome (a bit
+// mask over positions).  With order > 0 (combination sweep) the candidates
+// that follow are, in this order, the solutions with one non-basis position
+// t set (positions in rank order) and with two set among the first `order`
+// non-basis positions; the first candidate of least cost sum_{e_j = 1} q_j
+// wins.  ok = false when the syndrome is not reached (H_v not of full row
+// rank).
 template <class C>
-__device__ __forceinline__ uint64_t osd0(const float (&L)[C::D * C::D], uint64_t sv, bool &ok) {
+__device__ __forceinline__ uint64_t osd_local(const float (&L)[C::D * C::D], const int32_t (&q)[C::D * C::D],
+                                              uint64_t sv, int order, bool &ok) {
     constexpr int D2 = C::D * C::D, R = C::R;
     uint32_t bvec[R];
     uint64_t bcomb[R];
 #pragma unroll
     for (int b = 0; b < R; ++b) { bvec[b] = 0u; bcomb[b] = 0ull; }
     uint32_t have = 0u;
-    uint64_t left = D2 == 64 ? ~0ull : ((1ull << D2) - 1ull);
+    constexpr uint64_t all = D2 == 64 ? ~0ull : ((1ull << D2) - 1ull);
+    uint64_t left = all, piv = 0ull;
     float key[D2];
 #pragma unroll
     for (int j = 0; j < D2; ++j) key[j] = __builtin_rintf(L[j] * 64.f);   // exact scaling, round half to even
     int nb = 0;
     for (int step = 0; step < D2 && nb < R; ++step) {
-        float best = __builtin_inff();
-        int bj = -1;
-        static_for<0, D2>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            const bool lt = ((left >> j) & 1ull) && (bj < 0 || key[j] < best);
-            best = lt ? key[j] : best;
-            bj = lt ? j : bj;
-        });
+        const int bj = take_smallest<D2>(key, left);
         left &= ~(1ull << bj);
-        uint32_t col = 0u;
-        static_for<0, R>([&](auto cc) {
-            constexpr int c = decltype(cc)::value;
-            col |= (uint32_t)((C::mask[c] >> bj) & 1ull) << c;
-        });
+        uint32_t col = local_column<C>(bj);
         uint64_t comb = 1ull << bj;
         bool placed = false;
         static_for<0, R>([&](auto bb) {
@@ -435,19 +464,77 @@ __device__ __forceinline__ uint64_t osd0(const float (&L)[C::D * C::D], uint64_t
                 }
             }
         });
+        if (placed) piv |= 1ull << bj;
         nb += placed ? 1 : 0;
     }
-    uint32_t x = (uint32_t)sv;
-    uint64_t e = 0ull;
-    static_for<0, R>([&](auto bb) {
-        constexpr int b = decltype(bb)::value;
-        if (((x >> b) & 1u) && ((have >> b) & 1u)) {
-            x ^= bvec[b];
-            e ^= bcomb[b];
+    // the combination of basis columns that gives x
+    auto solve = [&](uint32_t x, uint32_t &rest) {
+        uint64_t e = 0ull;
+        static_for<0, R>([&](auto bb) {
+            constexpr int b = decltype(bb)::value;
+            if (((x >> b) & 1u) && ((have >> b) & 1u)) {
+                x ^= bvec[b];
+                e ^= bcomb[b];
+            }
+        });
+        rest = x;
+        return e;
+    };
+    uint32_t rest;
+    uint64_t e = solve((uint32_t)sv, rest);
+    ok = rest == 0u;
+    if (!ok) return 0ull;
+    if (order <= 0) return e;
+    auto cost = [&](uint64_t ee) {
+        int32_t c = 0;
+        static_for<0, D2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            c += ((ee >> j) & 1ull) ? q[j] : 0;
+        });
+        return c;
+    };
+    int32_t best = cost(e);
+    int tl[lead::kMaxOsdOrderLocal];
+#pragma unroll
+    for (int k = 0; k < lead::kMaxOsdOrderLocal; ++k) tl[k] = 0;
+    int nt = 0;
+    left = all;
+    for (int step = 0; step < D2; ++step) {
+        const int bj = take_smallest<D2>(key, left);
+        left &= ~(1ull << bj);
+        if ((piv >> bj) & 1ull) continue;
+        uint32_t r1;
+        const uint64_t ee = solve((uint32_t)sv ^ local_column<C>(bj), r1) ^ (1ull << bj);
+        const int32_t c = cost(ee);
+        if (c < best) {
+            best = c;
+            e = ee;
         }
-    });
-    ok = x == 0u;
-    return ok ? e : 0ull;
+#pragma unroll
+        for (int k = 0; k < lead::kMaxOsdOrderLocal; ++k) tl[k] = (nt == k) ? bj : tl[k];
+        ++nt;
+    }
+    const int lam = order < nt ? order : nt;
+    for (int x = 0; x < lam; ++x)
+        for (int y = x + 1; y < lam; ++y) {
+            int ta = 0, tb = 0;
+#pragma unroll
+            for (int k = 0; k < lead::kMaxOsdOrderLocal; ++k) {
+                int v = tl[k];
+                asm("" : "+v"(v));   // a value, not a load the select could turn into one
+                ta = (k == x) ? v : ta;
+                tb = (k == y) ? v : tb;
+            }
+            uint32_t r2;
+            const uint64_t ee =
+                solve((uint32_t)sv ^ local_column<C>(ta) ^ local_column<C>(tb), r2) ^ (1ull << ta) ^ (1ull << tb);
+            const int32_t c = cost(ee);
+            if (c < best) {
+                best = c;
+                e = ee;
+            }
+        }
+    return e;
 }
 
 // Phase 1 as a work queue over (shot, vertex) items: a lane runs the local BP
@@ -599,8 +686,9 @@ __device__ __forceinline__ void partial_sums(const ST &st, const float (&lam)[C:
     });
 }
 
-// Local post-processing of the views listed by the queue kernel: OSD-0 on
-// the view (osd0 above); where it reaches the local syndrome the view counts
+// Local post-processing of the views listed by the queue kernel: OSD of
+// order a.osd_order on the view (osd_local above, costs from the view's
+// channel priors); where it reaches the local syndrome the view counts
 // as converged, is flagged as resolved by OSD-0, and the confidence boost
 // (p <- max(p, 1/2) on its errors, i.e. L <- min(L, 0)) is applied to its
 // stored posteriors.  Lanes stride over the list.
@@ -618,8 +706,18 @@ __device__ __forceinline__ void local_osd_body(const DecodeArgs &a, const LocalA
         float Lc[D2];
 #pragma unroll
         for (int j = 0; j < D2; ++j) Lc[j] = io[j];
+        int32_t q[D2];
+#pragma unroll
+        for (int j = 0; j < D2; ++j) q[j] = 0;
+        if (a.osd_order > 0) {
+            // the sweep's costs: the view's channel priors
+            const int64_t base = a.prior_mode == 2 ? shot * a.n : 0;   // LEAD_PRIOR_FULL
+#pragma unroll
+            for (int j = 0; j < D2; ++j)
+                q[j] = osd_weight(a.prior_mode == 0 ? a.prior[shot] : a.prior[base + a.view[v * D2 + j]]);
+        }
         bool ok;
-        const uint64_t e = osd0<C>(Lc, sv, ok);
+        const uint64_t e = osd_local<C>(Lc, q, sv, a.osd_order, ok);
         if (ok) {
             if (a.boost) {
 #pragma unroll
@@ -1109,9 +1207,7 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
         __shared__ unsigned long long best;
         const float *lp = a.lam_out + shot * a.n;
         for (int t = tid; t < NQ; t += WG) {
-            const float x = lp[(uint32_t)keys[t]];
-            const float wgt = fmaxf(x, 0.f) + log1p_nonneg(exp_hw(-fabsf(x)));
-            qw[t] = (int32_t)__builtin_rintf(64.f * wgt);
+            qw[t] = osd_weight(lp[(uint32_t)keys[t]]);
             acc[t] = 0;
         }
         for (int i = tid; i < (NQ + 31) / 32; i += WG) pbits[i] = 0u;

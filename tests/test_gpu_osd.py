@@ -60,3 +60,49 @@ def test_local_osd_forms_identical_and_limits():
         dec.decode(st, pr, plain=True)
     with pytest.raises(P.LeadError, match="UNSUPPORTED"):
         gpu_decoder(spec, local_post=1, stage=2)
+
+
+@pytest.mark.parametrize("name,t,p,T,order,mode", [("T", 0, 0.05, 32, 3, 0), ("M", 0, 0.05, 8, 3, 0),
+                                                  ("M", 0, 0.02, 50, 8, 0), ("T", 1, 0.05, 16, 3, 2)])
+def test_local_osd_cs_matches_oracle(name, t, p, T, order, mode):
+    """Local OSD with the combination sweep (costs from the view's channel
+    priors), per-shot and per-qubit priors, against the oracle."""
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=T, max_iter_global=T, local_post=1, osd_order=order)
+    e, s, lam = bitflip_inputs(oc, 160, p, seed=83, t=t)
+    s = _gpu_syndrome(dec, e)
+    prior = lam
+    if mode == 2:
+        rng = np.random.default_rng(5)
+        prior = np.log(1 / rng.uniform(0.02, 0.08, (160, oc.n)) - 1).astype(np.float32)
+    g = run_gpu(dec, s, prior, mode, lam=True)
+    orc = oracle_decode_conditioned(oc, s, prior.astype(np.float64), t=t, max_iter_local=T, max_iter_global=T,
+                                    local_osd=1, osd_order=order)
+    o0 = oracle_decode_conditioned(oc, s, prior.astype(np.float64), t=t, k=0, max_iter_local=T, max_iter_global=T,
+                                   local_osd=1)
+    res = compare(orc, g, oc.n)
+    well = ~orc["ill"]
+    assert np.array_equal(g["stats"][well, 7], orc["osd_views"][well])
+    changed = int((np.abs(o0["lam"] - orc["lam"]).max(axis=1) > 0).sum())
+    log(f"[osd-cs local] {name} t={t} p={p} T={T} order={order} mode={mode}: {res['bad']} differ, "
+        f"{res['tie']} ill-conditioned, {changed} shots whose lambda' the sweep changes")
+    assert not res["unexplained"], res["detail"]
+    assert well.mean() >= 0.3 and changed > 0
+
+
+def test_local_and_global_osd_cs_forms_identical():
+    """Local and global OSD with the sweep together: every kernel form gives
+    the same bits."""
+    spec, oc = code_pair("M")
+    code, dec = gpu_decoder(spec, max_iter_local=12, max_iter_global=12, local_post=1, global_post=1, osd_order=3,
+                            max_shots=1024)
+    e, _, _ = bitflip_inputs(oc, 300, 0.05, seed=13)
+    s = _gpu_syndrome(dec, e)
+    lam = np.full(300, 2.94, dtype=np.float32)
+    runs = {}
+    for form in (2, 1):
+        dec.set_schedule(specialized=form)
+        runs[form] = run_gpu(dec, s, lam, 0, lam=True)
+    for k in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(runs[1][k], runs[2][k]), k
+    assert (runs[2]["stats"][:, 0] == 2).any() and runs[2]["stats"][:, 7].sum() > 0
