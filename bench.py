@@ -403,7 +403,8 @@ def main():
         # OSD-0 on H_t after global BP: LEAD with it, and BP-OSD-0 on H_t alone
         for key, kw in (("global_osd0_A5_p005", {}), ("bp_osd0_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL}),
                         ("global_osd_cs3_A5_p005", {"osd_order": 3}),
-                        ("bp_osd_cs3_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL, "osd_order": 3})):
+                        ("bp_osd_cs3_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL, "osd_order": 3}),
+                        ("local_and_global_osd_cs3_A5_p005", {"local_post": 1, "osd_order": 3})):
             gd2 = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
                             ms_scale=0.75, alpha=1.0, global_post=1, **kw)
             go2 = gd2.alloc_outputs(shots)
