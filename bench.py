@@ -236,6 +236,9 @@ def main():
                     help="only the eager pass used for the roofline, with --schedule (for profilers)")
     ap.add_argument("--schedule", type=str, default=None,
                     help="JSON schedule of the headline instead of the autotuner's choice")
+    ap.add_argument("--code", choices=("M", "L"), default="M",
+                    help="with --roofline-only: M = the A5 headline (p = 0.05, 50 + 50 rounds), L = the PSL(2,7) "
+                         "code (p = 0.03, 64 + 64 rounds, 5*10^4 shots)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -253,14 +256,18 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
-    shots = args.shots
-    code, dec = make_decoder(P, "M", shots)
+    if args.code != "M" and not args.roofline_only:
+        raise SystemExit("--code selects the workload of --roofline-only")
+    cname = args.code
+    shots = args.shots if cname == "M" else min(args.shots, 50_000)
+    pflip = P_FLIP if cname == "M" else 0.03
+    code, dec = make_decoder(P, cname, shots)
     n, m = code.n, code.m()
     info = code.info
 
     pool_batches = 4
-    synd_pool = [syndromes(torch, dec, n, shots, P_FLIP, seed=1000 + b) for b in range(pool_batches)]
-    lam = torch.full((shots,), float(channel_llr(P_FLIP)), dtype=torch.float32, device="cuda")
+    synd_pool = [syndromes(torch, dec, n, shots, pflip, seed=1000 + b) for b in range(pool_batches)]
+    lam = torch.full((shots,), float(channel_llr(pflip)), dtype=torch.float32, device="cuda")
     out = dec.alloc_outputs(shots)
     torch.cuda.synchronize()
 
@@ -277,7 +284,7 @@ def main():
     #      fixed-point exit is off in this pass: a run it ends reports the cap
     #      as its iteration count, and the edge updates counted from the
     #      statistics must be ones the kernels execute
-    dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=1.0,
+    dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], ms_scale=0.75, alpha=1.0,
                    fixed_point_stop=0)
     dec.decode(synd_pool[0], lam, out=out)
     torch.cuda.synchronize()
@@ -292,7 +299,7 @@ def main():
         eu_global += b
     pt = dec.phase_times()
     dec.time_phases(False)
-    dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=1.0)
+    dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], ms_scale=0.75, alpha=1.0)
     if pt["global_launches"] == 0:
         raise SystemExit(f"the schedule {best} does not run the work-queue form, which the roofline pass times")
     d2 = info.delta ** 2
@@ -306,7 +313,8 @@ def main():
     g_bytes = global_kernel_bytes_per_shot(n, m, info.order, d2) * shots_per_launch
     hbm_gbs = g_bytes / (kern["global"]["ms_per_launch"] * 1e-3) / 1e9
     if args.roofline_only:
-        print(json.dumps({"roofline_pass": kern, "schedule": best}), flush=True)
+        print(json.dumps({"roofline_pass": kern, "schedule": best, "code": cname, "p": pflip, "shots": shots}),
+              flush=True)
         return
     gname = f"lead_spec_global_{best.get('specialized')}"
     traffic = None

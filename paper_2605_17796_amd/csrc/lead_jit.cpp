@@ -68,6 +68,25 @@ std::map<std::pair<int, std::string>, std::shared_ptr<const Kernels>> g_modules;
 
 int workgroup_for(int order) { return ((order + 63) / 64) * 64; }
 
+// Degree from which a check keeps the compressed state in the per-shot
+// min-sum kernel (0: none): for views above kTwoWaveMaxEdges edges, the
+// largest threshold that leaves at most kHybridExplicitEdges messages (those
+// of the lower-degree checks) in registers.
+int hybrid_degree(const TypeTables &tt) {
+    if (tt.eloc <= kTwoWaveMaxEdges) return 0;
+    int best = 1;   // every check compressed
+    for (int i = 0; i < tt.r; ++i) {
+        const int t = __builtin_popcountll(tt.mask[i]) + 1;
+        int ex = 0;
+        for (int k = 0; k < tt.r; ++k) {
+            const int d = __builtin_popcountll(tt.mask[k]);
+            if (d < t) ex += d;
+        }
+        if (ex <= kHybridExplicitEdges && t > best) best = t;
+    }
+    return best;
+}
+
 }  // namespace
 
 bool osd_fits(const Code &c, int t) {
@@ -93,6 +112,7 @@ std::string source(const Code &c, int t, bool sp) {
       << "struct LeadCode {\n"
       << "    static constexpr int D = " << D << ", R = " << tt.r << ", NFIX = " << nfix << ";\n"
       << "    static constexpr bool SPLIT = " << (tt.eloc > kTwoWaveMaxEdges ? "true" : "false") << ";\n"
+      << "    static constexpr int HYB = " << hybrid_degree(tt) << ";\n"
       << "    static constexpr uint64_t mask[" << tt.r << "] = {";
     for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";
     o << "};\n    static constexpr int sigma[" << D2 << "] = {";
@@ -126,7 +146,7 @@ std::string source(const Code &c, int t, bool sp) {
         // explicit forms: at least two waves per SIMD for the per-shot kernel
         // (its rounds wait on ds_bpermute, which a lone wave cannot hide)
         o << "extern \"C\" __global__ void __launch_bounds__(" << wg
-          << (form == kCompressed || tt.eloc > kTwoWaveMaxEdges ? "" : ", 2")
+          << (form == kCompressed ? "" : ", 2")
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";

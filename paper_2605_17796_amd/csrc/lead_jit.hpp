@@ -27,10 +27,13 @@ constexpr int kForms = 3;
 // sum-product form.
 constexpr int kExplicitMaxEdges = 160;
 constexpr int kSumProductMaxEdges = 128;
-// Up to this many edges the explicit forms' per-shot kernel is held to two
-// waves per SIMD (256 VGPRs); above it, one wave with the whole register
-// file.
+// Up to this many edges the explicit forms' per-shot kernel keeps one
+// register per message; above it, the min-sum per-shot kernel keeps the
+// compressed state on the checks of highest degree, leaving at most
+// kHybridExplicitEdges messages in registers.  Either way it is held to two
+// waves per SIMD (256 VGPRs).
 constexpr int kTwoWaveMaxEdges = 128;
+constexpr int kHybridExplicitEdges = 72;
 
 // The global OSD-0 kernel keeps ceil(m/256) rows of ceil(n/64) words per lane
 // in registers; it is compiled when that product is at most this.

@@ -73,6 +73,64 @@ __device__ __forceinline__ void for_edges(const F &f) {
 // Compressed check state (the precompiled kernels' form): per check
 // beta * n1, beta * n2, the position of the smallest and the sign bit of
 // every outgoing message; messages are rebuilt from it when needed.
+// Check update of check c in the compressed state (m1, m2, am, q of that
+// check) from the sums S of the previous iteration: mu_{j->c} = S_j - m_{c->j}
+// (not clamped per edge: the clamp goes to the two minima; clamping is
+// monotone, and where the unclamped and the clamped position of the smallest
+// differ, both minima clamp to the same value and the position does not
+// matter) and the new min-sum state.  sat &= [S_j < 0] satisfies the check;
+// diff gains the bits that differ between the old and the new state.
+template <class C, int c>
+__device__ __forceinline__ void compressed_update(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
+                                                  float keep, float &m1, float &m2, uint32_t &am, uint32_t &q,
+                                                  bool &sat, uint32_t &diff) {
+    float n1 = kBig, n2 = kBig;
+    uint32_t nam = 0u, sg = 0u, par = 0u, pend = 0u;
+    for_edges<C, c>([&](auto jj, auto kk) {
+        constexpr int j = decltype(jj)::value;
+        constexpr uint32_t k = decltype(kk)::value;
+        // sign parity of S, two edges per three-input XOR
+        if constexpr ((k & 1) == 0) {
+            pend = __float_as_uint(S[j]);
+            if constexpr (k + 1 == (uint32_t)C::deg[c]) par ^= pend;
+        } else {
+            par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
+        }
+        const float mu = __builtin_fmaf(-msg_of(m1, m2, am, q, k), keep, S[j]);
+        const float ab = fabsf(mu);
+        sg |= signbit_of(mu) << k;
+        n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
+        const bool lt = ab < n1;
+        nam = lt ? k : nam;
+        n1 = lt ? ab : n1;
+    });
+    const uint32_t sc = (uint32_t)(sv >> c) & 1u;
+    sat = sat && ((par >> 31) == sc);
+    const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
+    constexpr uint32_t all = (uint32_t)((1ull << C::deg[c]) - 1ull);
+    uint32_t nq = flip ? (sg ^ all) : sg;
+    uint32_t b1u = __float_as_uint(beta * fminf(n1, clampv)), b2u = __float_as_uint(beta * fminf(n2, clampv));
+    // every outgoing message unchanged (the position of the smallest
+    // matters only when the two magnitudes differ)
+    const uint32_t dterm = (nq ^ q) | (b1u ^ __float_as_uint(m1)) | (b2u ^ __float_as_uint(m2)) |
+                           (b1u == b2u ? 0u : nam ^ am);
+    diff |= dterm;
+    // the new state is written from operands that depend on the
+    // comparison: the old values are then dead when the new ones are
+    // written and can share their registers (no copies at the loop
+    // back-edge)
+    asm("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam) : "v"(dterm));
+    q = nq;
+    m1 = __uint_as_float(b1u);
+    m2 = __uint_as_float(b2u);
+    am = nam;
+    asm volatile("" : "+v"(diff));
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Compressed check state (the precompiled kernels' form): per check
+// beta * n1, beta * n2, the position of the smallest and the sign bit of
+// every outgoing message; messages are rebuilt from it when needed.
 template <class C>
 struct Compressed {
     static constexpr int R = C::R;
@@ -83,9 +141,8 @@ struct Compressed {
         for (int c = 0; c < R; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
     }
     // Check update of every check of the view from the sums S of the
-    // previous iteration: mu_{j->c} = clamp(S_j - m_{c->j}) and the new
-    // min-sum state.  Returns whether [S_j < 0] satisfies every check; `same`
-    // tells whether every outgoing message is unchanged bit for bit.
+    // previous iteration.  Returns whether [S_j < 0] satisfies every check;
+    // `same` tells whether every outgoing message is unchanged bit for bit.
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
         bool sat = true;
@@ -96,52 +153,7 @@ struct Compressed {
         uint32_t diff = 0u;
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            // mu is not clamped per edge: the clamp goes to the two minima
-            // (clamping is monotone; where the unclamped and the clamped
-            // position of the smallest differ, both minima clamp to the same
-            // value and the position does not matter)
-            float n1 = kBig, n2 = kBig;
-            uint32_t nam = 0u, sg = 0u, par = 0u, pend = 0u;
-            for_edges<C, c>([&](auto jj, auto kk) {
-                constexpr int j = decltype(jj)::value;
-                constexpr uint32_t k = decltype(kk)::value;
-                // sign parity of S, two edges per three-input XOR
-                if constexpr ((k & 1) == 0) {
-                    pend = __float_as_uint(S[j]);
-                    if constexpr (k + 1 == (uint32_t)C::deg[c]) par ^= pend;
-                } else {
-                    par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
-                }
-                const float mu = __builtin_fmaf(-msg_of(m1[c], m2[c], am[c], q[c], k), keep, S[j]);
-                const float ab = fabsf(mu);
-                sg |= signbit_of(mu) << k;
-                n2 = __builtin_amdgcn_fmed3f(n1, n2, ab);
-                const bool lt = ab < n1;
-                nam = lt ? k : nam;
-                n1 = lt ? ab : n1;
-            });
-            const uint32_t sc = (uint32_t)(sv >> c) & 1u;
-            sat = sat && ((par >> 31) == sc);
-            const uint32_t flip = ((uint32_t)__popc(sg) & 1u) ^ sc;
-            constexpr uint32_t all = (uint32_t)((1ull << C::deg[c]) - 1ull);
-            uint32_t nq = flip ? (sg ^ all) : sg;
-            uint32_t b1u = __float_as_uint(beta * fminf(n1, clampv)), b2u = __float_as_uint(beta * fminf(n2, clampv));
-            // every outgoing message unchanged (the position of the smallest
-            // matters only when the two magnitudes differ)
-            const uint32_t dterm = (nq ^ q[c]) | (b1u ^ __float_as_uint(m1[c])) | (b2u ^ __float_as_uint(m2[c])) |
-                                   (b1u == b2u ? 0u : nam ^ am[c]);
-            diff |= dterm;
-            // the new state is written from operands that depend on the
-            // comparison: the old values are then dead when the new ones are
-            // written and can share their registers (no copies at the loop
-            // back-edge)
-            asm("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam) : "v"(dterm));
-            q[c] = nq;
-            m1[c] = __uint_as_float(b1u);
-            m2[c] = __uint_as_float(b2u);
-            am[c] = nam;
-            asm volatile("" : "+v"(diff));
-            __builtin_amdgcn_sched_barrier(0);
+            compressed_update<C, c>(S, sv, beta, clampv, keep, m1[c], m2[c], am[c], q[c], sat, diff);
         });
         same = diff == 0u;
         return sat;
@@ -161,6 +173,77 @@ struct Compressed {
     }
 };
 
+// Check update of check c with one register per message: the messages of
+// its edges are m[b], m[b + 1], ... (b fixed by the caller's layout).
+template <class C, int c, int b, int E>
+__device__ __forceinline__ void explicit_update(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
+                                                float keep, float (&m)[E], bool &sat, uint32_t &diff) {
+    constexpr int D2 = C::D * C::D;
+    for_edges<C, c>([&m](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
+    // The clamp of mu is applied to the two minima instead of to
+    // every edge: clamping is monotone, so the minimum and second
+    // minimum of the clamped magnitudes are the clamped minima, and
+    // where |mu_k| == n1 and the clamped comparison differ, both
+    // minima clamp to the same value.  Messages are bit for bit those
+    // of clamping each mu.
+    // With C::SPLIT the two smallest are tracked over the first and
+    // the second half of the edges separately and then merged
+    // (shorter dependency chains for kernels that run one wave per
+    // SIMD); min and max are exact, so n1 and n2 are the same values.
+    constexpr int h = C::SPLIT ? C::deg[c] / 2 : C::deg[c];
+    float n1 = kBig, n2 = kBig, n1b = kBig, n2b = kBig, mu[D2];
+    uint32_t par = 0u, ps = 0u, pend = 0u;
+    for_edges<C, c>([&](auto jj, auto kk) {
+        constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+        mu[j] = __builtin_fmaf(-m[b + k], keep, S[j]);
+        // sign parities of S and mu, two edges per three-input XOR
+        if constexpr ((k & 1) == 0) {
+            pend = __float_as_uint(S[j]);
+            if constexpr (k + 1 == C::deg[c]) par ^= pend;
+        } else {
+            par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
+        }
+        if constexpr (k < h) {
+            n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[j]));
+            n1 = fminf(n1, fabsf(mu[j]));
+        } else {
+            n2b = __builtin_amdgcn_fmed3f(n1b, n2b, fabsf(mu[j]));
+            n1b = fminf(n1b, fabsf(mu[j]));
+        }
+    });
+    if constexpr (h < C::deg[c]) {
+        n2 = fminf(fmaxf(n1, n1b), fminf(n2, n2b));
+        n1 = fminf(n1, n1b);
+    }
+    for_edges<C, c>([&](auto jj, auto kk) {
+        constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+        if constexpr ((k & 1) == 0) {
+            pend = __float_as_uint(mu[j]);
+            if constexpr (k + 1 == C::deg[c]) ps ^= pend;
+        } else {
+            ps = __builtin_amdgcn_bitop3_b32(ps, pend, __float_as_uint(mu[j]), 0x96);
+        }
+    });
+    const uint32_t sc = (uint32_t)(sv >> c) & 1u;
+    sat = sat && ((par >> 31) == sc);
+    // the two candidate messages with the sign of the whole product
+    // (check syndrome included); each edge then flips the sign by its
+    // own mu's, which takes its mu out of the product
+    const uint32_t px = (ps ^ (sc << 31)) & kSign;
+    uint32_t b1 = __float_as_uint(beta * fminf(n1, clampv)) ^ px,
+             b2 = __float_as_uint(beta * fminf(n2, clampv)) ^ px;
+    asm("" : "+v"(b1), "+v"(b2));   // keep the two products (not a product per edge)
+    for_edges<C, c>([&](auto jj, auto kk) {
+        constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+        const uint32_t sel = fabsf(mu[j]) == n1 ? b2 : b1;
+        const uint32_t nm = __builtin_amdgcn_bitop3_b32(sel, __float_as_uint(mu[j]), kSign, 0x78);   // sel ^ (mu & sign)
+        diff = __builtin_amdgcn_bitop3_b32(diff, nm, __float_as_uint(m[b + k]), 0xf6);   // diff | (nm ^ old)
+        m[b + k] = __uint_as_float(nm);
+    });
+    asm volatile("" : "+v"(diff));
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // Explicit messages: every m_{c->j} of the view in a register (edges
 // numbered check by check, positions ascending within a check).  The
 // messages are the compressed form's, bit for bit: magnitude beta * n2 on the
@@ -178,75 +261,11 @@ struct Explicit {
     }
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
-        constexpr int D2 = C::D * C::D;
         bool sat = true;
         uint32_t diff = 0u;   // see Compressed::check
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            constexpr int b = C::base[c];
-            for_edges<C, c>([&](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
-            // The clamp of mu is applied to the two minima instead of to
-            // every edge: clamping is monotone, so the minimum and second
-            // minimum of the clamped magnitudes are the clamped minima, and
-            // where |mu_k| == n1 and the clamped comparison differ, both
-            // minima clamp to the same value.  Messages are bit for bit those
-            // of clamping each mu.
-            // With C::SPLIT the two smallest are tracked over the first and
-            // the second half of the edges separately and then merged
-            // (shorter dependency chains for kernels that run one wave per
-            // SIMD); min and max are exact, so n1 and n2 are the same values.
-            constexpr int h = C::SPLIT ? C::deg[c] / 2 : C::deg[c];
-            float n1 = kBig, n2 = kBig, n1b = kBig, n2b = kBig, mu[D2];
-            uint32_t par = 0u, ps = 0u, pend = 0u;
-            for_edges<C, c>([&](auto jj, auto kk) {
-                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                mu[j] = __builtin_fmaf(-m[b + k], keep, S[j]);
-                // sign parities of S and mu, two edges per three-input XOR
-                if constexpr ((k & 1) == 0) {
-                    pend = __float_as_uint(S[j]);
-                    if constexpr (k + 1 == C::deg[c]) par ^= pend;
-                } else {
-                    par = __builtin_amdgcn_bitop3_b32(par, pend, __float_as_uint(S[j]), 0x96);
-                }
-                if constexpr (k < h) {
-                    n2 = __builtin_amdgcn_fmed3f(n1, n2, fabsf(mu[j]));
-                    n1 = fminf(n1, fabsf(mu[j]));
-                } else {
-                    n2b = __builtin_amdgcn_fmed3f(n1b, n2b, fabsf(mu[j]));
-                    n1b = fminf(n1b, fabsf(mu[j]));
-                }
-            });
-            if constexpr (h < C::deg[c]) {
-                n2 = fminf(fmaxf(n1, n1b), fminf(n2, n2b));
-                n1 = fminf(n1, n1b);
-            }
-            for_edges<C, c>([&](auto jj, auto kk) {
-                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                if constexpr ((k & 1) == 0) {
-                    pend = __float_as_uint(mu[j]);
-                    if constexpr (k + 1 == C::deg[c]) ps ^= pend;
-                } else {
-                    ps = __builtin_amdgcn_bitop3_b32(ps, pend, __float_as_uint(mu[j]), 0x96);
-                }
-            });
-            const uint32_t sc = (uint32_t)(sv >> c) & 1u;
-            sat = sat && ((par >> 31) == sc);
-            // the two candidate messages with the sign of the whole product
-            // (check syndrome included); each edge then flips the sign by its
-            // own mu's, which takes its mu out of the product
-            const uint32_t px = (ps ^ (sc << 31)) & kSign;
-            uint32_t b1 = __float_as_uint(beta * fminf(n1, clampv)) ^ px,
-                     b2 = __float_as_uint(beta * fminf(n2, clampv)) ^ px;
-            asm("" : "+v"(b1), "+v"(b2));   // keep the two products (not a product per edge)
-            for_edges<C, c>([&](auto jj, auto kk) {
-                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
-                const uint32_t sel = fabsf(mu[j]) == n1 ? b2 : b1;
-                const uint32_t nm = __builtin_amdgcn_bitop3_b32(sel, __float_as_uint(mu[j]), kSign, 0x78);   // sel ^ (mu & sign)
-                diff = __builtin_amdgcn_bitop3_b32(diff, nm, __float_as_uint(m[b + k]), 0xf6);   // diff | (nm ^ old)
-                m[b + k] = __uint_as_float(nm);
-            });
-            asm volatile("" : "+v"(diff));
-            __builtin_amdgcn_sched_barrier(0);
+            explicit_update<C, c, C::base[c], E>(S, sv, beta, clampv, keep, m, sat, diff);
         });
         same = diff == 0u;
         return sat;
@@ -258,6 +277,75 @@ struct Explicit {
             constexpr int c = decltype(cc)::value;
             for_edges<C, c>([&](auto jj, auto kk) {
                 S[decltype(jj)::value] = __builtin_fmaf(m[C::base[c] + decltype(kk)::value], keep, S[decltype(jj)::value]);
+            });
+        });
+    }
+};
+
+// Mixed storage for views with many edges: the checks of degree at least
+// C::HYB keep the compressed state, the others one register per message
+// (C::HYB = 0: none compressed).  Each check is updated exactly as in its own
+// form, so the messages are bit for bit those of either; the mix keeps a
+// view's state small enough for two waves per SIMD.
+template <class C>
+constexpr bool hyb_compressed(int c) { return C::HYB > 0 && C::deg[c] >= C::HYB; }
+template <class C>
+constexpr int hyb_index(int c) {   // compressed checks before check c
+    int n = 0;
+    for (int i = 0; i < c; ++i) n += hyb_compressed<C>(i) ? 1 : 0;
+    return n;
+}
+template <class C>
+constexpr int hyb_base(int c) {    // explicit edges before check c
+    int n = 0;
+    for (int i = 0; i < c; ++i) n += hyb_compressed<C>(i) ? 0 : C::deg[i];
+    return n;
+}
+
+template <class C>
+struct Hybrid {
+    static constexpr int R = C::R;
+    static constexpr int NC = hyb_index<C>(R) > 0 ? hyb_index<C>(R) : 1, EX = hyb_base<C>(R) > 0 ? hyb_base<C>(R) : 1;
+    float m[EX];
+    float m1[NC], m2[NC];
+    uint32_t am[NC], q[NC];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int e = 0; e < EX; ++e) m[e] = 0.f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
+    }
+    __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
+                                          bool &same, float keep = 1.f) {
+        bool sat = true;
+        uint32_t diff = 0u;   // see Compressed::check
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if constexpr (hyb_compressed<C>(c)) {
+                constexpr int i = hyb_index<C>(c);
+                compressed_update<C, c>(S, sv, beta, clampv, keep, m1[i], m2[i], am[i], q[i], sat, diff);
+            } else {
+                explicit_update<C, c, hyb_base<C>(c), EX>(S, sv, beta, clampv, keep, m, sat, diff);
+            }
+        });
+        same = diff == 0u;
+        return sat;
+    }
+    template <int c, int k>
+    __device__ __forceinline__ float msg() const {
+        if constexpr (hyb_compressed<C>(c)) {
+            constexpr int i = hyb_index<C>(c);
+            return msg_of(m1[i], m2[i], am[i], q[i], (uint32_t)k);
+        } else {
+            return m[hyb_base<C>(c) + k];
+        }
+    }
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                S[decltype(jj)::value] =
+                    __builtin_fmaf(this->template msg<c, decltype(kk)::value>(), keep, S[decltype(jj)::value]);
             });
         });
     }
@@ -358,6 +446,20 @@ struct Pick<C, 3> {
 };
 template <class C, int FORM>
 using CheckState = typename Pick<C, FORM>::type;
+
+// The Phases 2-3 kernel keeps the mixed storage where C::HYB is set (views
+// whose one-register-per-message state would take more than half the
+// register file); the Phase 1 queue kernel keeps the explicit form.
+template <class C, int FORM, bool H = (FORM == 2 && C::HYB > 0)>
+struct PickGlobal {
+    using type = CheckState<C, FORM>;
+};
+template <class C, int FORM>
+struct PickGlobal<C, FORM, true> {
+    using type = Hybrid<C>;
+};
+template <class C, int FORM>
+using GlobalState = typename PickGlobal<C, FORM>::type;
 
 // Whether [S_j < 0] satisfies every check of the view.
 template <class C>
@@ -733,20 +835,23 @@ __device__ __forceinline__ void local_osd_body(const DecodeArgs &a, const LocalA
 enum { SF_FLAG0 = 0, SF_FLAG1 = 1, SF_FINAL = 2, SF_ITSUM = 3, SF_ITMAX = 4, SF_NCONV = 5, SF_CHG = 6, SF_NFIX = 7,
        SF_NOSD = 8, SF_STRIDE = 9 };
 
-// Partner addresses: for local position j, the byte address of the lane
-// that holds the other occurrence of the qubit (lane * 4).  Within one wave
-// (BPERM) they fit in 8 bits, four per register; across waves in 16 bits.
-template <bool BPERM>
+// Partner addresses: for local position j, the lane that holds the other
+// occurrence of the qubit.  Within one wave (BPERM) its byte address
+// (lane * 4, 8 bits); across the waves of a workgroup of at most 256 lanes
+// the lane itself (8 bits); four per register.  Larger workgroups: the byte
+// address in 16 bits, two per register.
+template <bool BPERM, int WG>
 struct PartnerAddr {
-    static constexpr int PER = BPERM ? 4 : 2, BITS = 32 / PER;
-    static constexpr uint32_t MASK = BPERM ? 0xffu : 0xffffu;
+    static constexpr int PER = (BPERM || WG <= 256) ? 4 : 2, BITS = 32 / PER;
+    static constexpr uint32_t MASK = PER == 4 ? 0xffu : 0xffffu;
+    static constexpr uint32_t SCALE = (BPERM || PER == 2) ? 4u : 1u;   // stored value = lane * SCALE
     template <int D2>
     static constexpr int words() { return (D2 + PER - 1) / PER; }
 };
 
-template <bool BPERM, int J, int NW>
+template <bool BPERM, int WG, int J, int NW>
 __device__ __forceinline__ uint32_t partner_addr(const uint32_t (&pa)[NW]) {
-    using A = PartnerAddr<BPERM>;
+    using A = PartnerAddr<BPERM, WG>;
     return (pa[J / A::PER] >> ((J % A::PER) * A::BITS)) & A::MASK;
 }
 
@@ -758,6 +863,7 @@ template <class C, int WG, bool BPERM, int J>
 __device__ __forceinline__ float partner(const float (&X)[C::D * C::D], const float *buf, uint32_t addr) {
     if (BPERM)
         return __int_as_float(__builtin_amdgcn_ds_bpermute((int)addr, __float_as_int(X[C::sigma[J]])));
+    if (PartnerAddr<BPERM, WG>::SCALE == 1u) return buf[C::sigma[J] * WG + addr];
     return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(buf) + C::sigma[J] * WG * 4 + addr);
 }
 
@@ -765,7 +871,7 @@ template <class C, int WG, bool BPERM, int NW, int J = 0>
 __device__ __forceinline__ void partner_all(const float (&X)[C::D * C::D], float (&Y)[C::D * C::D],
                                             const float *buf, const uint32_t (&pa)[NW]) {
     if constexpr (J < C::D * C::D) {
-        Y[J] = partner<C, WG, BPERM, J>(X, buf, partner_addr<BPERM, J>(pa));
+        Y[J] = partner<C, WG, BPERM, J>(X, buf, partner_addr<BPERM, WG, J>(pa));
         partner_all<C, WG, BPERM, NW, J + 1>(X, Y, buf, pa);
     }
 }
@@ -790,7 +896,7 @@ template <class C, int WG, bool BPERM, int FORM>
 __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x) {
     constexpr int D2 = C::D * C::D;
     constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
-    constexpr int NW = PartnerAddr<BPERM>::template words<D2>();  // words of the packed addresses
+    constexpr int NW = PartnerAddr<BPERM, WG>::template words<D2>();  // words of the packed addresses
     extern __shared__ float lds[];
     float *buf = lds;
     int *shf = reinterpret_cast<int *>(lds + (BPERM ? 0 : D2 * WG));
@@ -826,21 +932,22 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             osd_v = (int)((f >> 18) & 1u);
         }
         const uint32_t base = (uint32_t)(sl * a.N);
-        using A = PartnerAddr<BPERM>;
+        using A = PartnerAddr<BPERM, WG>;
 #pragma unroll
         for (int k = 0; k < NW; ++k) pa[k] = 0u;
 #pragma unroll
         for (int j = 0; j < D2; ++j) {
             const uint32_t vp = (x.pv[v * NP + j / 2] >> (16 * (j & 1))) & 0xffffu;
-            pa[j / A::PER] |= ((base + vp) * 4u) << ((j % A::PER) * A::BITS);
+            pa[j / A::PER] |= ((base + vp) * A::SCALE) << ((j % A::PER) * A::BITS);
         }
         if (C::NFIX) fown = x.fown[v];
     } else {
 #pragma unroll
         for (int j = 0; j < D2; ++j) S[j] = 0.f;
-        using A = PartnerAddr<BPERM>;
+        using A = PartnerAddr<BPERM, WG>;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) pa[k] = BPERM ? (uint32_t)tid * 4u * 0x01010101u : (uint32_t)tid * 4u * 0x10001u;
+        for (int k = 0; k < NW; ++k)
+            pa[k] = (uint32_t)tid * A::SCALE * (A::PER == 4 ? 0x01010101u : 0x10001u);
     }
     __syncthreads();
     if (live) {
@@ -900,7 +1007,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     };
 #pragma unroll
     for (int j = 0; j < D2; ++j) S[j] = lam[j];
-    CheckState<C, FORM> st;
+    GlobalState<C, FORM> st;
     st.clear();
     if (!BPERM) __syncthreads();
     bool done = !live;
@@ -928,18 +1035,20 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             shot_sat = shf[(t & 1)] == 0;
             shot_same = shf[SF_CHG] != t;
         }
+        // (one shot per workgroup, !BPERM: the loop ends right here for
+        // every lane, and the outputs are written after it, from the same S)
         if (!done && t > 1) {
             if (shot_sat && a.early_exit) {
                 done = true;
                 gconv = 1;
                 itg = t - 1;
-                emit();
+                if constexpr (BPERM) emit();
             } else if (a.fixed_stop && shot_same) {
                 done = true;
                 gconv = shot_sat ? 1 : 0;
                 itg = a.Tg;
                 gfix = t;
-                emit();
+                if constexpr (BPERM) emit();
             }
         }
         if constexpr (BPERM) {
@@ -961,7 +1070,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             float Q[D2];
             static_for<0, D2>([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
-                if constexpr (C::sigma[j] >= j) Q[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, j>(pa));
+                if constexpr (C::sigma[j] >= j) Q[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, WG, j>(pa));
             });
             static_for<0, D2>([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
@@ -969,14 +1078,29 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             });
             static_for<0, D2>([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
-                if constexpr (C::sigma[j] < j) S[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, j>(pa));
+                if constexpr (C::sigma[j] < j) S[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, WG, j>(pa));
             });
         } else {
-            float Q[D2];
-            store_all<C, WG, BPERM>(S, buf);
-            partner_all<C, WG, BPERM, NW>(S, Q, buf, pa);
+            // through LDS, sixteen positions at a time (all 64 partner
+            // values in flight at once would need 64 more registers); the
+            // addresses are unpacked here each round, not kept unpacked
+            // across the loop
 #pragma unroll
-            for (int j = 0; j < D2; ++j) S[j] += Q[j];
+            for (int k = 0; k < NW; ++k) asm volatile("" : "+v"(pa[k]));
+            store_all<C, WG, BPERM>(S, buf);
+            static_for<0, (D2 + 15) / 16>([&](auto qq) {
+                constexpr int j0 = 16 * decltype(qq)::value;
+                float Q[16];
+                static_for<0, 16>([&](auto ii) {
+                    constexpr int j = j0 + decltype(ii)::value;
+                    if constexpr (j < D2) Q[j - j0] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, WG, j>(pa));
+                });
+                static_for<0, 16>([&](auto ii) {
+                    constexpr int j = j0 + decltype(ii)::value;
+                    if constexpr (j < D2) S[j] += Q[j - j0];
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            });
         }
         }
     const bool ran_out = !done;
@@ -992,7 +1116,10 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     if (ran_out) {
         gconv = shot_final ? 1 : 0;
         itg = a.Tg;
-        emit();
+        if constexpr (BPERM) emit();
+    }
+    if constexpr (!BPERM) {
+        if (live) emit();
     }
     __syncthreads();
     if (live) {
