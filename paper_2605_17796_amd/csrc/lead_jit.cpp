@@ -267,6 +267,12 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
     k->wg = workgroup_for(c.order);
     k->spw = k->wg / c.order;
     k->bperm = k->wg == 64;
+    if (!k->bperm && hybrid_degree(c.t[t]) > 0) {
+        // the per-shot kernel of form 2 keeps lambda' of the positions with
+        // sigma[j] >= j in LDS (lead_spec::lam_in_lds)
+        const int D2 = c.delta * c.delta;
+        for (int j = 0; j < D2; ++j) k->lam_slots += c.t[t].sigma[j] >= j ? 1 : 0;
+    }
     std::lock_guard<std::mutex> lk(g_mu);
     auto ins = g_modules.emplace(std::make_pair(device, src), k);
     return ins.first->second;   // another thread may have loaded it first

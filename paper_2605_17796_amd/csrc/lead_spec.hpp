@@ -885,6 +885,23 @@ __device__ __forceinline__ void store_all(const float (&X)[C::D * C::D], float *
     }
 }
 
+// Positions j with sigma[j] >= j (those a view may own) and the rank of j
+// among them.
+template <class C>
+constexpr int owner_slots() {
+    int n = 0;
+    for (int j = 0; j < C::D * C::D; ++j) n += C::sigma[j] >= j ? 1 : 0;
+    return n;
+}
+template <class C>
+constexpr int owner_slot(int j) {
+    int n = 0;
+    for (int i = 0; i < j; ++i) n += C::sigma[i] >= i ? 1 : 0;
+    return n;
+}
+template <class C, bool BPERM, int FORM>
+constexpr bool lam_in_lds() { return !BPERM && FORM == 2 && C::HYB > 0; }
+
 // Phases 2-3 of `spw` shots per workgroup after the Phase 1 queue kernel;
 // lane (slot, v) holds vertex v of shot blockIdx.x * spw + slot.  The same
 // computation as the precompiled split kernel: lambda' of every qubit from
@@ -897,9 +914,14 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     constexpr int D2 = C::D * C::D;
     constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
     constexpr int NW = PartnerAddr<BPERM, WG>::template words<D2>();  // words of the packed addresses
+    // with the mixed check state across waves, lambda' of the positions a
+    // view may own (sigma[j] >= j) waits in LDS between rounds, not in VGPRs
+    constexpr bool LAML = lam_in_lds<C, BPERM, FORM>();
+    constexpr int NO = LAML ? owner_slots<C>() : 0;
     extern __shared__ float lds[];
     float *buf = lds;
-    int *shf = reinterpret_cast<int *>(lds + (BPERM ? 0 : D2 * WG));
+    float *laml = lds + (BPERM ? 0 : D2 * WG);
+    int *shf = reinterpret_cast<int *>(lds + (BPERM ? 0 : D2 * WG) + NO * WG);
     const int ew32 = (a.n + 31) >> 5;
     uint32_t *ebits = reinterpret_cast<uint32_t *>(shf + a.spw * SF_STRIDE);
     const int tid = threadIdx.x;
@@ -979,6 +1001,12 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
 #pragma unroll
         for (int j = 0; j < D2; ++j)
             if (owned(j)) a.lam_out[shot * a.n + a.view[v * D2 + j]] = lam[j];
+    }
+    if constexpr (LAML) {
+        static_for<0, D2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            if constexpr (C::sigma[j] >= j) laml[owner_slot<C>(j) * WG + tid] = lam[j];
+        });
     }
     if (a.stage == 1) {
         __syncthreads();
@@ -1060,7 +1088,16 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             if (tid == 0) shf[((t + 1) & 1)] = 0;
         }
         // partial sums of this view, then S_j = P_j + P of the other occurrence
-        partial_sums<C>(st, lam, fown, S);
+        if constexpr (LAML) {
+            float lr[D2];
+            static_for<0, D2>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                lr[j] = C::sigma[j] >= j ? laml[owner_slot<C>(j) * WG + tid] : 0.f;
+            });
+            partial_sums<C>(st, lr, fown, S);
+        } else {
+            partial_sums<C>(st, lam, fown, S);
+        }
         if constexpr (BPERM) {
             // the owner of a qubit adds its partner's P (fixed points of
             // sigma: both occurrences, as ownership is known only at run
