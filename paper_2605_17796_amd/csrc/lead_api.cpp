@@ -175,7 +175,8 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
     a.spw = k.spw;
     lead::SpecArgs x{d->d_pv, d->d_fown};
     const int D2 = d->D * d->D, ew32 = (d->n + 31) / 32;
-    const size_t lam_lds = f + 1 == lead::jit::kExplicit ? sizeof(float) * (size_t)k.lam_slots * k.wg : 0;
+    const bool lam_in_lds = f + 1 == lead::jit::kCompressed || (f + 1 == lead::jit::kExplicit && k.hybrid);
+    const size_t lam_lds = lam_in_lds ? sizeof(float) * (size_t)k.lam_slots * k.wg : 0;
     const size_t lds = (k.bperm ? 0 : sizeof(float) * (size_t)D2 * k.wg) + lam_lds + sizeof(int) * (size_t)k.spw * 9 +
                        sizeof(uint32_t) * (size_t)k.spw * ew32;   // 9: the kernel's per-shot flag stride
     const int64_t grid = (a.shots + k.spw - 1) / k.spw;

@@ -68,6 +68,16 @@ std::map<std::pair<int, std::string>, std::shared_ptr<const Kernels>> g_modules;
 
 int workgroup_for(int order) { return ((order + 63) / 64) * 64; }
 
+// Whether the per-shot kernel's LDS (partner-exchange buffer D2 x wg and
+// lambda' of the positions with sigma[j] >= j, wg each, f32) stays within
+// 128 KB, leaving room for the per-shot flags and e_hat bitmaps.
+bool lam_lds_fits(const Code &c, int t) {
+    const int D2 = c.delta * c.delta, wg = workgroup_for(c.order);
+    int no = 0;
+    for (int j = 0; j < D2 && j < (int)c.t[t].sigma.size(); ++j) no += c.t[t].sigma[j] >= j ? 1 : 0;
+    return (size_t)(D2 + no) * wg * sizeof(float) <= 128u * 1024u;
+}
+
 // Degree from which a check keeps the compressed state in the per-shot
 // min-sum kernel (0: none): for views above kTwoWaveMaxEdges edges, the
 // largest threshold that leaves at most kHybridExplicitEdges messages (those
@@ -113,6 +123,7 @@ std::string source(const Code &c, int t, bool sp) {
       << "    static constexpr int D = " << D << ", R = " << tt.r << ", NFIX = " << nfix << ";\n"
       << "    static constexpr bool SPLIT = " << (tt.eloc > kTwoWaveMaxEdges ? "true" : "false") << ";\n"
       << "    static constexpr int HYB = " << hybrid_degree(tt) << ";\n"
+      << "    static constexpr bool LAM_LDS = " << (lam_lds_fits(c, t) ? "true" : "false") << ";\n"
       << "    static constexpr uint64_t mask[" << tt.r << "] = {";
     for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";
     o << "};\n    static constexpr int sigma[" << D2 << "] = {";
@@ -143,10 +154,11 @@ std::string source(const Code &c, int t, bool sp) {
               << ") lead_spec_local_" << form << pm
               << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << form
               << ">(a, w); }\n";
-        // explicit forms: at least two waves per SIMD for the per-shot kernel
-        // (its rounds wait on ds_bpermute, which a lone wave cannot hide)
+        // at least two waves per SIMD for the per-shot kernel (its rounds
+        // wait on the partner exchange, which a lone wave cannot hide); the
+        // compressed form within one wave keeps the whole register file
         o << "extern \"C\" __global__ void __launch_bounds__(" << wg
-          << (form == kCompressed ? "" : ", 2")
+          << (form == kCompressed && wg == 64 ? "" : ", 2")
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
@@ -267,9 +279,11 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
     k->wg = workgroup_for(c.order);
     k->spw = k->wg / c.order;
     k->bperm = k->wg == 64;
-    if (!k->bperm && hybrid_degree(c.t[t]) > 0) {
-        // the per-shot kernel of form 2 keeps lambda' of the positions with
-        // sigma[j] >= j in LDS (lead_spec::lam_in_lds)
+    k->hybrid = hybrid_degree(c.t[t]) > 0;
+    if (!k->bperm && lam_lds_fits(c, t)) {
+        // across waves the per-shot kernels of form 1 (and of form 2 with
+        // the mixed state) keep lambda' of the positions with sigma[j] >= j
+        // in LDS (lead_spec::lam_in_lds)
         const int D2 = c.delta * c.delta;
         for (int j = 0; j < D2; ++j) k->lam_slots += c.t[t].sigma[j] >= j ? 1 : 0;
     }

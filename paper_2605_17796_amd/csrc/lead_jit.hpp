@@ -56,8 +56,9 @@ struct Kernels {
     int wg = 0;                          // workgroup size of `global`
     int spw = 0;                         // shots per workgroup of `global`
     bool bperm = false;                  // partner values exchanged within the wave
-    int lam_slots = 0;                   // form 2 across waves with the mixed check
-                                         // state: lambda' slots per lane in LDS
+    int lam_slots = 0;                   // across waves: lambda' slots per lane in LDS
+                                         // (form 1, and form 2 with the mixed state)
+    bool hybrid = false;                 // form 2 keeps the mixed check state
     int local_waves_per_cu[kForms][2] = {{4, 4}, {4, 4}, {4, 4}};
     int best_form() const { return has[2] ? kSumProduct : has[1] ? kExplicit : kCompressed; }
 };

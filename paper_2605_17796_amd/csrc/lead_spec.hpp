@@ -12,7 +12,12 @@
 //   C::E, C::deg[R], C::base[R]
 //                   the local edges (numbered check by check, positions
 //                   ascending within a check): their count, and per check
-//                   the degree and the number of its first edge.
+//                   the degree and the number of its first edge,
+//   C::SPLIT        track the two smallest |mu| in two chains per check,
+//   C::HYB          degree from which the per-shot kernel keeps a check's
+//                   compressed state in form 2 (0: none),
+//   C::LAM_LDS      the per-shot kernel's LDS has room for lambda' when a
+//                   shot spans several waves.
 // Every loop below runs over compile-time bounds and indexes arrays with
 // loop-constant subscripts only (through tables, not constexpr functions
 // with loops of their own), so that each index folds to an immediate once
@@ -900,7 +905,7 @@ constexpr int owner_slot(int j) {
     return n;
 }
 template <class C, bool BPERM, int FORM>
-constexpr bool lam_in_lds() { return !BPERM && FORM == 2 && C::HYB > 0; }
+constexpr bool lam_in_lds() { return !BPERM && C::LAM_LDS && (FORM == 1 || (FORM == 2 && C::HYB > 0)); }
 
 // Phases 2-3 of `spw` shots per workgroup after the Phase 1 queue kernel;
 // lane (slot, v) holds vertex v of shot blockIdx.x * spw + slot.  The same
@@ -914,8 +919,9 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     constexpr int D2 = C::D * C::D;
     constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
     constexpr int NW = PartnerAddr<BPERM, WG>::template words<D2>();  // words of the packed addresses
-    // with the mixed check state across waves, lambda' of the positions a
-    // view may own (sigma[j] >= j) waits in LDS between rounds, not in VGPRs
+    // across waves, with the compressed or the mixed check state, lambda' of
+    // the positions a view may own (sigma[j] >= j) waits in LDS between
+    // rounds, not in VGPRs (two waves per SIMD)
     constexpr bool LAML = lam_in_lds<C, BPERM, FORM>();
     constexpr int NO = LAML ? owner_slots<C>() : 0;
     extern __shared__ float lds[];
