@@ -88,3 +88,38 @@ def test_specialised_kernels_compile(name):
     code = P.Code.from_spec(spec)
     for t in (0, 1):
         code.specialize(t)
+
+
+_DUMP_SCRIPT = """
+import sys
+sys.path.insert(0, {root!r})
+import paper_2605_17796_amd as P
+from lead_inputs import standard
+P.Code.from_spec(standard({name!r})).specialize(0)
+"""
+
+
+@pytest.mark.parametrize("name", ["M", "L"])
+def test_per_shot_kernel_register_budget(name, tmp_path):
+    """The Phases 2-3 kernel of form 2 fits 256 VGPRs (two waves per SIMD)
+    without scratch memory: with one register per message for the A5 views,
+    with the mixed check state and lambda' in LDS for the PSL(2,7) views."""
+    import os, re, subprocess, sys
+    readelf = "/opt/rocm/llvm/bin/llvm-readelf"
+    if not os.path.exists(readelf):
+        pytest.skip("llvm-readelf not installed")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, LEAD_JIT_DUMP=str(tmp_path))
+    subprocess.run([sys.executable, "-c", _DUMP_SCRIPT.format(root=root, name=name)], env=env, check=True,
+                   timeout=600)
+    found = {}
+    for co in tmp_path.glob("*.co"):
+        notes = subprocess.run([readelf, "--notes", str(co)], capture_output=True, text=True, check=True).stdout
+        for block in notes.split("- .agpr_count")[1:]:
+            kname = re.search(r"\.name:\s+(\S+)", block)
+            if kname and kname.group(1) == "lead_spec_global_2":
+                found["vgpr"] = int(re.search(r"\.vgpr_count:\s+(\d+)", block).group(1))
+                found["spill"] = int(re.search(r"\.vgpr_spill_count:\s+(\d+)", block).group(1))
+                found["scratch"] = int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1))
+    assert found, "lead_spec_global_2 not found in the compiled objects"
+    assert found["vgpr"] <= 256 and found["spill"] == 0 and found["scratch"] == 0, found
