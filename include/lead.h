@@ -261,7 +261,7 @@ typedef struct {
                                      lead_code_specialize; they pick their own
                                      workgroup shape): 1 with the compressed
                                      min-sum check state, 2 with one register
-                                     per message (views of at most 160 edges;
+                                     per message (views of at most 192 edges;
                                      above 128 edges the Phases 2-3 kernel
                                      keeps the compressed state on the
                                      highest-degree checks, same outputs);

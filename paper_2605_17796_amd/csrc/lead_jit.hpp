@@ -25,7 +25,7 @@ constexpr int kForms = 3;
 // Views with at most this many local edges also get the explicit-message
 // min-sum form (one VGPR per message), and at most kSumProductMaxEdges the
 // sum-product form.
-constexpr int kExplicitMaxEdges = 160;
+constexpr int kExplicitMaxEdges = 192;
 constexpr int kSumProductMaxEdges = 128;
 // Up to this many edges the explicit forms' per-shot kernel keeps one
 // register per message; above it, the min-sum per-shot kernel keeps the

@@ -33,12 +33,13 @@ def _priors(mode, ps, n, seed):
 
 def _forms(dec, synd, prior, mode, eloc):
     """Outputs under every kernel form: specialised with one register per
-    message (views of at most 160 edges), specialised with the compressed
-    check state, precompiled split, precompiled fused."""
+    message (views of at most 192 edges; the per-shot kernel keeps the
+    compressed state on the highest-degree checks above 128), specialised with
+    the compressed check state, precompiled split, precompiled fused."""
     runs = {}
     for form in (2, 1, 0):
         dec.set_schedule(specialized=form)
-        want = form if form != 2 or eloc <= 160 else 1
+        want = form if form != 2 or eloc <= 192 else 1
         assert dec.get_schedule()["specialized"] == want
         runs[form] = run_gpu(dec, synd, prior, mode, lam=True)
     dec.set_schedule(fused=1)
