@@ -123,3 +123,8 @@ def test_per_shot_kernel_register_budget(name, tmp_path):
                 found["scratch"] = int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1))
     assert found, "lead_spec_global_2 not found in the compiled objects"
     assert found["vgpr"] <= 256 and found["spill"] == 0 and found["scratch"] == 0, found
+    # the checks kept compressed in form 2: none for the 56-edge A5 views; for
+    # the 156-edge PSL(2,7) Z-check views those of degree >= 11 (90 edges),
+    # leaving 66 messages in registers
+    src = "".join(p.read_text() for p in tmp_path.glob("*.hip"))
+    assert ("HYB = 0;" if name == "M" else "HYB = 11;") in src
