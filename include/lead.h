@@ -107,7 +107,10 @@ lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_
 /* Compiles, for gfx950 and without touching a GPU, the decoding kernels
  * specialised to the local check structure of type t (its check masks and
  * the local position map of the two occurrences of a qubit, Sec. II-B), and
- * caches the code objects for the rest of the process (the min-sum forms,
+ * caches the code objects for the rest of the process and on disk (the
+ * directory $LEAD_JIT_CACHE, "off" to disable, else _build/jit beside the
+ * library; a later process with the same compiler, library headers and code
+ * loads them instead of compiling) (the min-sum forms,
  * and the sum-product form where views have at most 128 local edges);
  * lead_decoder_create does the same on first use and then loads them.  LEAD_E_UNSUPPORTED (with the
  * reason in lead_last_error) when the code has no position map or the

@@ -1,10 +1,16 @@
-// Run-time compilation of the specialised kernels (see lead_jit.hpp).
+// Run-time compilation of the specialised kernels (see lead_jit.hpp), with a
+// cache of code objects on disk.
 #include "lead_jit.hpp"
 
 #include <dlfcn.h>
 #include <hip/hiprtc.h>
 
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <functional>
 #include <map>
@@ -36,6 +42,7 @@ struct Rtc {
     hiprtcResult (*code_size)(hiprtcProgram, size_t *) = nullptr;
     hiprtcResult (*code)(hiprtcProgram, char *) = nullptr;
     hiprtcResult (*destroy)(hiprtcProgram *) = nullptr;
+    hiprtcResult (*version)(int *, int *) = nullptr;   // optional
 };
 
 const Rtc &rtc() {
@@ -58,6 +65,7 @@ const Rtc &rtc() {
                sym(r.code_size, "hiprtcGetCodeSize") && sym(r.code, "hiprtcGetCode") &&
                sym(r.destroy, "hiprtcDestroyProgram");
         if (!r.ok) r.err = "hipRTC lacks an entry point";
+        sym(r.version, "hiprtcVersion");
     });
     return r;
 }
@@ -95,6 +103,102 @@ int hybrid_degree(const TypeTables &tt) {
         if (ex <= kHybridExplicitEdges && t > best) best = t;
     }
     return best;
+}
+
+// ---- code objects on disk --------------------------------------------------
+// A compiled code object is kept in a file named by a 128-bit hash of its key
+// (compiler options, hipRTC version, the embedded headers and the generated
+// source, which holds the code's check masks and position map).  The file
+// stores the key itself, and a hit requires it to match byte for byte, so a
+// hash collision can only cost a recompilation.  Directory: $LEAD_JIT_CACHE
+// ("off" disables the cache), else _build/jit beside liblead.so.  Files are
+// written to a temporary name and renamed, so concurrent processes never see
+// a partial object.
+
+const char *const kCompileOpts[] = {"--gpu-architecture=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+                                    "-Xclang", "-packed-fp32-ops"};
+constexpr int kNumCompileOpts = (int)(sizeof(kCompileOpts) / sizeof(kCompileOpts[0]));
+constexpr char kCacheMagic[8] = {'L', 'E', 'A', 'D', 'C', 'O', '0', '1'};
+
+std::string cache_key(const std::string &src) {
+    std::string k;
+    for (int i = 0; i < kNumCompileOpts; ++i) (k += kCompileOpts[i]) += '\n';
+    int ma = 0, mi = 0;
+    const Rtc &r = rtc();
+    if (r.ok && r.version) r.version(&ma, &mi);
+    k += "hiprtc " + std::to_string(ma) + "." + std::to_string(mi) + "\n";
+    for (int i = 0; i < kNumHeaders; ++i) {
+        k += kHeaderNames[i];
+        k += '\0';
+        k += kHeaderTexts[i];
+        k += '\0';
+    }
+    return k + src;
+}
+
+// FNV-1a, 64 bits, from two offset bases: a 128-bit file name.
+std::string key_hash(const std::string &key) {
+    uint64_t h[2] = {0xcbf29ce484222325ull, 0x6c62272e07bb0142ull};
+    for (unsigned char ch : key)
+        for (uint64_t &x : h) x = (x ^ ch) * 0x100000001b3ull;
+    char buf[40];
+    std::snprintf(buf, sizeof buf, "%016llx%016llx", (unsigned long long)h[0], (unsigned long long)h[1]);
+    return buf;
+}
+
+const std::string &cache_dir() {
+    static const std::string dir = [] {
+        if (const char *e = std::getenv("LEAD_JIT_CACHE")) return std::string(std::strcmp(e, "off") ? e : "");
+        Dl_info info{};
+        if (!dladdr(reinterpret_cast<void *>(&cache_key), &info) || !info.dli_fname) return std::string();
+        std::string lib = info.dli_fname;
+        const size_t slash = lib.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/_build/jit";
+    }();
+    return dir;
+}
+
+bool cache_read(const std::string &key, std::vector<char> &obj) {
+    const std::string &dir = cache_dir();
+    if (dir.empty()) return false;
+    std::ifstream f(dir + "/lead_spec_" + key_hash(key) + ".co", std::ios::binary);
+    if (!f) return false;
+    char magic[8];
+    uint64_t klen = 0, olen = 0;
+    if (!f.read(magic, 8) || std::memcmp(magic, kCacheMagic, 8) || !f.read(reinterpret_cast<char *>(&klen), 8) ||
+        klen != key.size())
+        return false;
+    std::string stored(klen, '\0');
+    if (!f.read(&stored[0], (std::streamsize)klen) || stored != key) return false;
+    if (!f.read(reinterpret_cast<char *>(&olen), 8) || olen == 0 || olen > (1ull << 30)) return false;
+    obj.assign(olen, 0);
+    return (bool)f.read(obj.data(), (std::streamsize)olen);
+}
+
+void cache_write(const std::string &key, const std::vector<char> &obj) {
+    const std::string &dir = cache_dir();
+    if (dir.empty()) return;
+    // create the directory and its parent (_build) if missing
+    const size_t slash = dir.rfind('/');
+    if (slash != std::string::npos && slash > 0) mkdir(dir.substr(0, slash).c_str(), 0755);
+    mkdir(dir.c_str(), 0755);
+    const std::string path = dir + "/lead_spec_" + key_hash(key) + ".co";
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        const uint64_t klen = key.size(), olen = obj.size();
+        f.write(kCacheMagic, 8);
+        f.write(reinterpret_cast<const char *>(&klen), 8);
+        f.write(key.data(), (std::streamsize)klen);
+        f.write(reinterpret_cast<const char *>(&olen), 8);
+        f.write(obj.data(), (std::streamsize)olen);
+        if (!f) {
+            f.close();
+            std::remove(tmp.c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
 }
 
 }  // namespace
@@ -190,6 +294,12 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
             return true;
         }
     }
+    const std::string key = cache_key(src);
+    if (cache_read(key, obj)) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_objects.emplace(src, obj);
+        return true;
+    }
     const Rtc &r = rtc();
     if (!r.ok) {
         err = r.err;
@@ -201,9 +311,7 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
         err = "hiprtcCreateProgram failed";
         return false;
     }
-    const char *opts[] = {"--gpu-architecture=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature",
-                          "-Xclang", "-packed-fp32-ops"};
-    const hiprtcResult cr = r.compile(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    const hiprtcResult cr = r.compile(prog, kNumCompileOpts, kCompileOpts);
     bool ok = cr == HIPRTC_SUCCESS;
     if (!ok) {
         size_t n = 0;
@@ -227,6 +335,7 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
             std::ofstream(name.str(), std::ios::binary).write(obj.data(), (std::streamsize)obj.size());
             std::ofstream(name.str() + ".hip") << src;
         }
+        cache_write(key, obj);
         std::lock_guard<std::mutex> lk(g_mu);
         g_objects.emplace(src, obj);
     }

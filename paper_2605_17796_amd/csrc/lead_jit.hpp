@@ -2,8 +2,9 @@
 //
 // The check masks and the local position map of a code become compile-time
 // constants of lead_spec.hpp's kernels (hipRTC, gfx950).  Code objects are
-// cached per process by source text, modules per device; neither is ever
-// unloaded.
+// cached per process by source text and on disk (keyed by compiler, headers
+// and source; $LEAD_JIT_CACHE, else _build/jit beside the library), modules
+// per device; neither is ever unloaded.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -69,7 +70,8 @@ struct Kernels {
 // has more than kSumProductMaxEdges edges.
 std::string source(const Code &c, int t, bool sp = false);
 
-// Code object of `src` for gfx950 (compiled once per process).  Needs no GPU.
+// Code object of `src` for gfx950 (compiled once per process, or read from
+// the disk cache).  Needs no GPU.
 bool compile(const std::string &src, std::vector<char> &obj, std::string &err);
 
 // Kernels of check type t of code c on the current device (device index
