@@ -201,6 +201,17 @@ void cache_write(const std::string &key, const std::vector<char> &obj) {
     if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
 }
 
+// LEAD_JIT_DUMP=<dir>: keep a copy of every code object this process
+// compiles or reads from the cache, with its source (for inspection).
+void dump(const std::string &src, const std::vector<char> &obj) {
+    const char *dir = std::getenv("LEAD_JIT_DUMP");
+    if (!dir) return;
+    std::ostringstream name;
+    name << dir << "/lead_spec_" << std::hex << std::hash<std::string>{}(src) << ".co";
+    std::ofstream(name.str(), std::ios::binary).write(obj.data(), (std::streamsize)obj.size());
+    std::ofstream(name.str() + ".hip") << src;
+}
+
 }  // namespace
 
 bool osd_fits(const Code &c, int t) {
@@ -296,6 +307,7 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
     }
     const std::string key = cache_key(src);
     if (cache_read(key, obj)) {
+        dump(src, obj);
         std::lock_guard<std::mutex> lk(g_mu);
         g_objects.emplace(src, obj);
         return true;
@@ -328,13 +340,7 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err) {
     }
     r.destroy(&prog);
     if (ok) {
-        // LEAD_JIT_DUMP=<dir>: keep a copy of every code object (for inspection)
-        if (const char *dir = std::getenv("LEAD_JIT_DUMP")) {
-            std::ostringstream name;
-            name << dir << "/lead_spec_" << std::hex << std::hash<std::string>{}(src) << ".co";
-            std::ofstream(name.str(), std::ios::binary).write(obj.data(), (std::streamsize)obj.size());
-            std::ofstream(name.str() + ".hip") << src;
-        }
+        dump(src, obj);
         cache_write(key, obj);
         std::lock_guard<std::mutex> lk(g_mu);
         g_objects.emplace(src, obj);

@@ -70,12 +70,14 @@ def test_library_rejects_invalid_descriptions(lead):
         with pytest.raises(lead.LeadError) as ei:
             lead.Code(*args)
         assert lead.STATUS_NAMES[ei.value.status] == status
+        if status == "LEAD_E_TNC":
+            # the message names the offending elements
+            assert "TNC fails: a*g == g*b for a=" in str(ei.value)
     bad = np.array(g, copy=True)
     bad[1, 1] = 3
     with pytest.raises(lead.LeadError) as ei:
         lead.Code(bad, 2, [1, 4], [2, 3], [0b11], [0b11])
     assert lead.STATUS_NAMES[ei.value.status] == "LEAD_E_GROUP"
-    assert "TNC" in lead.lib().lead_last_error().decode() or True
 
 
 @pytest.mark.parametrize("name", ["T", "M", "L", "appendix"])
@@ -95,36 +97,63 @@ import sys
 sys.path.insert(0, {root!r})
 import paper_2605_17796_amd as P
 from lead_inputs import standard
-P.Code.from_spec(standard({name!r})).specialize(0)
+P.Code.from_spec(standard({name!r})).specialize({t})
 """
 
 
-@pytest.mark.parametrize("name", ["M", "L"])
-def test_per_shot_kernel_register_budget(name, tmp_path):
+def _kernel_notes(readelf, co):
+    """{kernel name: (vgpr, spill, scratch bytes)} of a code object."""
+    import re, subprocess
+    notes = subprocess.run([readelf, "--notes", str(co)], capture_output=True, text=True, check=True).stdout
+    out = {}
+    for block in notes.split("- .agpr_count")[1:]:
+        kname = re.search(r"\.name:\s+(\S+)", block)
+        if kname:
+            out[kname.group(1)] = (int(re.search(r"\.vgpr_count:\s+(\d+)", block).group(1)),
+                                   int(re.search(r"\.vgpr_spill_count:\s+(\d+)", block).group(1)),
+                                   int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)))
+    return out
+
+
+_SPILLS = pytest.mark.xfail(strict=True, reason="the per-shot kernel of form 2 spills to scratch memory on these "
+                            "views (A5 X checks: 77 edges; PSL(2,7) X checks: 182 edges)")
+
+
+@pytest.mark.parametrize("name,t", [("M", 0), pytest.param("M", 1, marks=_SPILLS), ("L", 0),
+                                    pytest.param("L", 1, marks=_SPILLS)])
+def test_per_shot_kernel_register_budget(name, t, tmp_path):
     """The Phases 2-3 kernel of form 2 fits 256 VGPRs (two waves per SIMD)
-    without scratch memory: with one register per message for the A5 views,
-    with the mixed check state and lambda' in LDS for the PSL(2,7) views."""
-    import os, re, subprocess, sys
+    without spills: with one register per message for the 56-edge A5 Z-check
+    views, with the mixed check state and lambda' in LDS for the PSL(2,7)
+    views (156 edges on the Z checks, 182 on the X checks).  The Phase 1 queue
+    kernels of form 2 (one register per message) use no scratch memory:
+    within 256 VGPRs for A5, within the 512 registers of one wave per SIMD
+    for PSL(2,7) (what does not fit the VGPRs goes to accumulation
+    registers)."""
+    import os, subprocess, sys
     readelf = "/opt/rocm/llvm/bin/llvm-readelf"
     if not os.path.exists(readelf):
         pytest.skip("llvm-readelf not installed")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, LEAD_JIT_DUMP=str(tmp_path))
-    subprocess.run([sys.executable, "-c", _DUMP_SCRIPT.format(root=root, name=name)], env=env, check=True,
+    subprocess.run([sys.executable, "-c", _DUMP_SCRIPT.format(root=root, name=name, t=t)], env=env, check=True,
                    timeout=600)
     found = {}
     for co in tmp_path.glob("*.co"):
-        notes = subprocess.run([readelf, "--notes", str(co)], capture_output=True, text=True, check=True).stdout
-        for block in notes.split("- .agpr_count")[1:]:
-            kname = re.search(r"\.name:\s+(\S+)", block)
-            if kname and kname.group(1) == "lead_spec_global_2":
-                found["vgpr"] = int(re.search(r"\.vgpr_count:\s+(\d+)", block).group(1))
-                found["spill"] = int(re.search(r"\.vgpr_spill_count:\s+(\d+)", block).group(1))
-                found["scratch"] = int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1))
-    assert found, "lead_spec_global_2 not found in the compiled objects"
-    assert found["vgpr"] <= 256 and found["spill"] == 0 and found["scratch"] == 0, found
-    # the checks kept compressed in form 2: none for the 56-edge A5 views; for
-    # the 156-edge PSL(2,7) Z-check views those of degree >= 11 (90 edges),
-    # leaving 66 messages in registers
+        found.update(_kernel_notes(readelf, co))
+    assert "lead_spec_global_2" in found, "lead_spec_global_2 not found in the compiled objects"
+    vgpr, spill, scratch = found["lead_spec_global_2"]
+    assert vgpr <= 256 and spill == 0 and scratch == 0, found["lead_spec_global_2"]
+    for k in ("lead_spec_local_20", "lead_spec_local_21"):
+        vgpr, spill, scratch = found[k]
+        print(f"{name} t={t} {k}: {vgpr} VGPRs, {spill} moved to accumulation registers, {scratch} B scratch")
+        assert scratch == 0 and vgpr <= (256 if name == "M" else 512), (k, found[k])
+        if name == "M":
+            assert spill == 0, (k, found[k])
+    # the checks kept compressed in form 2: none for the 56- and 36-edge A5
+    # views; for the 156-edge PSL(2,7) Z-check views those of degree >= 11
+    # (90 edges), leaving 66 messages in registers; for the 182-edge X-check
+    # views, whose degree-9 checks alone hold 81 edges, every check
     src = "".join(p.read_text() for p in tmp_path.glob("*.hip"))
-    assert ("HYB = 0;" if name == "M" else "HYB = 11;") in src
+    hyb = {("M", 0): 0, ("M", 1): 0, ("L", 0): 11, ("L", 1): 1}[(name, t)]
+    assert f"HYB = {hyb};" in src
