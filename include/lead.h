@@ -234,6 +234,34 @@ lead_status lead_decode(lead_decoder *dec, int64_t shots, const uint64_t *d_synd
                         const float *d_prior, lead_prior_mode mode, uint64_t *d_ehat, int64_t ehat_words,
                         float *d_post, float *d_prior_llr, lead_shot_stats *d_stats, void *stream);
 
+/* The same decode for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): outputs
+ * are bit-identical to lead_decode's, from the same kernels and launches,
+ * but every buffer the kernels need beyond the caller's inputs and outputs
+ * (local posteriors, view flags, queue counters, the local OSD list and,
+ * with global_post, the global OSD's buffers for outputs passed as NULL) is
+ * taken from a static device array of LEAD_NOALLOC_SCRATCH_BYTES bytes that
+ * each GPU holds until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree, event or stream creation) and records no phase
+ * timing; the device's array address is looked up once, on its first call
+ * on that device, which must be the decoder's device (LEAD_E_ARG
+ * otherwise).  Shots are decoded in one pass through the scratch, so a call
+ * takes at most (LEAD_NOALLOC_SCRATCH_BYTES - 2048) / b shots, b = 4 *
+ * order * delta^2 + 8 * order bytes per shot (plus 4n, 32 and 4n with
+ * global_post for the post, stats and, with osd_order > 0, lambda' outputs
+ * passed as NULL): about 7 300 A5 shots or 1 500 PSL(2,7) shots.  Larger
+ * batches return LEAD_E_CAPACITY with the limit in lead_last_error and
+ * enqueue nothing.  Every call on one GPU uses that GPU's one array, which
+ * keeps the last call's contents (the queue counters are cleared by a fill
+ * kernel at the start of each call): calls whose device work overlaps on one
+ * GPU (other host threads, or other streams not ordered with this one) race
+ * and give undefined results.  Arguments and the other errors are as for
+ * lead_decode. */
+#define LEAD_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+lead_status lead_decode_noalloc(lead_decoder *dec, int64_t shots, const uint64_t *d_synd, int64_t synd_words,
+                                const float *d_prior, lead_prior_mode mode, uint64_t *d_ehat, int64_t ehat_words,
+                                float *d_post, float *d_prior_llr, lead_shot_stats *d_stats, void *stream);
+
 /* The same decode as a plain sequence of launches: one launch for Phases 1-2
  * (lambda' written to HBM), then one launch per global BP round with the
  * message state in HBM, and a host-visible convergence count after every

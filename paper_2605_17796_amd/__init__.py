@@ -84,7 +84,7 @@ STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max
 
 SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_get_H", "lead_code_get_views",
            "lead_code_specialize", "lead_code_destroy", "lead_decoder_create", "lead_decoder_set_params", "lead_decoder_destroy",
-           "lead_decode", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
+           "lead_decode", "lead_decode_noalloc", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
            "lead_decoder_get_schedule", "lead_decoder_time_phases", "lead_decoder_phase_times",
            "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
            "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_server_create", "lead_server_submit",
@@ -124,6 +124,7 @@ def lib():
         L.lead_decoder_destroy.restype = None
         dec_args = [P, I64, P, I64, P, I32, P, I64, P, P, P, P]
         L.lead_decode.argtypes = dec_args
+        L.lead_decode_noalloc.argtypes = dec_args
         L.lead_decode_plain.argtypes = dec_args
         L.lead_syndrome.argtypes = [P, I64, P, I64, P, I64, P]
         L.lead_decoder_autotune.argtypes = [P, I64, P, I64, P, I32, P, C.POINTER(lead_schedule)]
@@ -240,6 +241,11 @@ def lead_decoder_destroy(dec):
 def lead_decode(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream):
     _check(lib().lead_decode(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats,
                              stream))
+
+
+def lead_decode_noalloc(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream):
+    _check(lib().lead_decode_noalloc(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam,
+                                     stats, stream))
 
 
 def lead_decode_plain(dec, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream):
@@ -405,10 +411,12 @@ class Decoder:
         return out
 
     def decode(self, synd, prior, mode=LEAD_PRIOR_PER_SHOT, out=None, post=True, lam=False, stream=None,
-               plain=False):
+               plain=False, noalloc=False):
         """synd: int64 tensor [S, W] of packed syndromes on the GPU; prior:
         float32 LLRs ([S] PER_SHOT, [n] SHARED, [S, n] FULL).  Returns the
-        dict of output tensors (ehat packed int64, post, lam, stats [S, 8])."""
+        dict of output tensors (ehat packed int64, post, lam, stats [S, 8]).
+        plain: lead_decode_plain; noalloc: lead_decode_noalloc (the library's
+        static scratch; pass `out` to allocate nothing on this side either)."""
         shots = int(synd.shape[0])
         _need(synd, "synd", (shots, None), "int64")
         if synd.shape[1] < self.synd_words:
@@ -423,7 +431,7 @@ class Decoder:
         _need(out["post"], "post", (shots, self.n), "float32", optional=True)
         _need(out["lam"], "lam", (shots, self.n), "float32", optional=True)
         _need(out["stats"], "stats", (shots, 8), "int32", optional=True)
-        fn = lead_decode_plain if plain else lead_decode
+        fn = lead_decode_plain if plain else lead_decode_noalloc if noalloc else lead_decode
         fn(self._h, shots, _ptr(synd), int(synd.shape[1]), _ptr(prior), mode, _ptr(out["ehat"]),
            self.ehat_words if out["ehat"] is not None else 0, _ptr(out["post"]), _ptr(out["lam"]),
            _ptr(out["stats"]), _stream(stream))

@@ -15,6 +15,7 @@
 #include "lead_internal.hpp"
 #include "lead_jit.hpp"
 #include "lead_kernels.hpp"
+#include "lead_scratch.hpp"
 
 static_assert(sizeof(lead::ShotStats) == sizeof(lead_shot_stats), "ShotStats layout");
 static_assert(offsetof(lead::ShotStats, global_fixed_iter) == offsetof(lead_shot_stats, global_fixed_iter),
@@ -79,6 +80,20 @@ lead_status fail(lead_status s, const std::string &msg) {
 lead_status hip_fail(hipError_t e, const char *what) {
     return fail(LEAD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+// Device buffers a decode launch works in beyond its inputs and outputs:
+// the work-queue form's local posteriors, flags, queue counters and local
+// OSD list, and the global OSD's posterior / statistics / prior buffers for
+// calls that pass none; `shots` is how many shots they hold.
+struct Workspace {
+    float *Lv = nullptr;
+    uint32_t *vflag = nullptr;
+    int64_t *counter = nullptr;
+    uint32_t *osd_list = nullptr;
+    float *gpost = nullptr, *glam = nullptr;
+    lead_shot_stats *gstats = nullptr;
+    int64_t shots = 0;
+};
 
 lead_status check_params(const lead_params *p) {
     if (!p) return fail(LEAD_E_ARG, "params is NULL");
@@ -187,12 +202,25 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
     return e;
 }
 
-lead::LocalArgs local_args(const lead_decoder *d, int64_t shots, lead_prior_mode mode) {
+Workspace decoder_workspace(const lead_decoder *d) {
+    Workspace ws;
+    ws.Lv = d->d_Lv;
+    ws.vflag = d->d_vflag;
+    ws.counter = d->d_counter;
+    ws.osd_list = d->d_osd_list;
+    ws.gpost = d->d_gpost;
+    ws.glam = d->d_glam;
+    ws.gstats = d->d_gstats;
+    ws.shots = d->ws_shots;
+    return ws;
+}
+
+lead::LocalArgs local_args(const lead_decoder *d, const Workspace &ws, int64_t shots, lead_prior_mode mode) {
     lead::LocalArgs w{};
-    w.Lv = d->d_Lv;
-    w.vflag = d->d_vflag;
-    w.counter = d->d_counter;
-    w.osd_list = d->d_osd_list;
+    w.Lv = ws.Lv;
+    w.vflag = ws.vflag;
+    w.counter = ws.counter;
+    w.osd_list = ws.osd_list;
     w.items = shots * d->N;
     w.chunk = d->sched.local_chunk;
     const int pm = mode == LEAD_PRIOR_PER_SHOT ? 0 : 1;
@@ -296,7 +324,8 @@ hipError_t drain_timing(lead_decoder *d) {
 // split path) on stream s.
 hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
                          const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post,
-                         float *lam, lead_shot_stats *stats, int stage, hipStream_t s) {
+                         float *lam, lead_shot_stats *stats, int stage, hipStream_t s, const Workspace &ws,
+                         bool allow_timing = true) {
     // global BP alone: the per-shot kernel alone (there is no Phase 1); the
     // precompiled form runs it fused
     const bool gonly = d->params.stage == LEAD_STAGE_GLOBAL;
@@ -304,7 +333,7 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
     // global OSD-0 after global BP (its buffers hold ws_shots shots)
     const bool gpost = d->params.global_post && stage != LEAD_STAGE_LOCAL;
     // equal chunks of at most the schedule's chunk (no small tail launch)
-    const int64_t chunk = d->sched.chunk_shots > 0 ? std::min<int64_t>(d->sched.chunk_shots, d->ws_shots) : d->ws_shots;
+    const int64_t chunk = d->sched.chunk_shots > 0 ? std::min<int64_t>(d->sched.chunk_shots, ws.shots) : ws.shots;
     const int64_t nchunks = split || gpost ? (shots + chunk - 1) / chunk : 1;
     const int64_t step = (shots + nchunks - 1) / nchunks;
     for (int64_t off = 0; off < shots; off += step) {
@@ -322,12 +351,12 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         a.shots = cnt;
         a.stage = stage == LEAD_STAGE_LOCAL ? LEAD_STAGE_LOCAL : LEAD_STAGE_FULL;
         a.global_only = gonly ? 1 : 0;
-        const lead::LocalArgs w = local_args(d, cnt, mode);
-        std::array<hipEvent_t, 3> *ev = split ? timing_events(d, s) : nullptr;
+        const lead::LocalArgs w = local_args(d, ws, cnt, mode);
+        std::array<hipEvent_t, 3> *ev = split && allow_timing ? timing_events(d, s) : nullptr;
         if (gpost) {
-            if (!a.post) a.post = d->d_gpost;
-            if (!a.stats) a.stats = d->d_gstats;
-            if (!a.lam_out && d->params.osd_order > 0) a.lam_out = d->d_glam;   // the sweep's costs
+            if (!a.post) a.post = ws.gpost;
+            if (!a.stats) a.stats = ws.gstats;
+            if (!a.lam_out && d->params.osd_order > 0) a.lam_out = ws.glam;   // the sweep's costs
         }
         hipError_t e = split && use_spec(d) ? launch_spec(d, a, w, s, ev)
                                    : lead::launch_decode(d->D, d->r, a, w, split, s, ev ? ev->data() : nullptr);
@@ -397,7 +426,7 @@ lead_status enqueue_batch(const lead_batch_item *items, int32_t n, hipStream_t s
         if (it.shots == 0) continue;
         e = decode_chunks(it.decoder, it.shots, it.d_synd, it.synd_words, it.d_prior, it.mode, it.d_ehat,
                           it.ehat_words, it.d_post, it.d_prior_llr, it.d_stats, it.decoder->params.stage,
-                          streams[group[i]]);
+                          streams[group[i]], decoder_workspace(it.decoder));
         if (e != hipSuccess) return hip_fail(e, "batch launch");
     }
     for (int g = 0; g < ngroups; ++g) {
@@ -765,7 +794,63 @@ lead_status lead_decode(lead_decoder *d, int64_t shots, const uint64_t *synd, in
     if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, d->spw), d->spw, d->n) > 65536)
         return fail(LEAD_E_UNSUPPORTED, "workgroup needs more than 64 KiB of LDS");
     hipError_t e = decode_chunks(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats,
-                                 d->params.stage, (hipStream_t)stream);
+                                 d->params.stage, (hipStream_t)stream, decoder_workspace(d));
+    if (e != hipSuccess) return hip_fail(e, "decode launch");
+    return LEAD_OK;
+}
+
+lead_status lead_decode_noalloc(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
+                                const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words,
+                                float *post, float *lam, lead_shot_stats *stats, void *stream) {
+    lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
+    if (st != LEAD_OK || shots == 0) return st;
+    if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, d->spw), d->spw, d->n) > 65536)
+        return fail(LEAD_E_UNSUPPORTED, "workgroup needs more than 64 KiB of LDS");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != d->device)
+        return fail(LEAD_E_ARG, "lead_decode_noalloc: the current device is not the decoder's device");
+    // scratch layout: queue counters (256 B), then per shot the local
+    // posteriors, view flags and local OSD list, then (global_post) the
+    // global OSD's buffers for outputs the caller does not pass
+    const bool gpost = d->params.global_post && d->params.stage != LEAD_STAGE_LOCAL;
+    const size_t lv = sizeof(float) * (size_t)d->N * d->D * d->D, vf = sizeof(uint32_t) * (size_t)d->N;
+    const size_t gp = gpost && !post ? sizeof(float) * (size_t)d->n : 0;
+    const size_t gs = gpost && !stats ? sizeof(lead_shot_stats) : 0;
+    const size_t gl = gpost && !lam && d->params.osd_order > 0 ? sizeof(float) * (size_t)d->n : 0;
+    const size_t per_shot = lv + 2 * vf + gp + gs + gl;
+    const size_t head = 256, slack = 7 * 256;   // counters, alignment of the seven arrays
+    const int64_t capacity = (int64_t)((lead::kScratchBytes - head - slack) / per_shot);
+    if (shots > capacity)
+        return fail(LEAD_E_CAPACITY, "lead_decode_noalloc: " + std::to_string(shots) + " shots need " +
+                                         std::to_string(per_shot * (size_t)shots + head) +
+                                         " bytes of scratch; the static scratch holds " +
+                                         std::to_string(lead::kScratchBytes) + " bytes (at most " +
+                                         std::to_string(capacity) + " shots of this decoder per call)");
+    void *base = nullptr;
+    if ((e = lead::scratch_address(d->device, &base)) != hipSuccess) return hip_fail(e, "scratch address");
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        char *q = bytes ? p + off : nullptr;
+        off = (off + bytes + 255) & ~size_t(255);
+        return q;
+    };
+    Workspace ws;
+    ws.counter = reinterpret_cast<int64_t *>(carve(head));
+    ws.Lv = reinterpret_cast<float *>(carve(lv * (size_t)shots));
+    ws.vflag = reinterpret_cast<uint32_t *>(carve(vf * (size_t)shots));
+    ws.osd_list = reinterpret_cast<uint32_t *>(carve(vf * (size_t)shots));
+    ws.gpost = reinterpret_cast<float *>(carve(gp * (size_t)shots));
+    ws.gstats = reinterpret_cast<lead_shot_stats *>(carve(gs * (size_t)shots));
+    ws.glam = reinterpret_cast<float *>(carve(gl * (size_t)shots));
+    ws.shots = shots;
+    if (off > lead::kScratchBytes) return fail(LEAD_E_CAPACITY, "lead_decode_noalloc: scratch layout overflow");
+    // every launch is enqueued without timing events (no event objects are
+    // created); the queue counters are cleared by a fill kernel
+    e = decode_chunks(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, d->params.stage,
+                      (hipStream_t)stream, ws, false);
     if (e != hipSuccess) return hip_fail(e, "decode launch");
     return LEAD_OK;
 }
@@ -798,7 +883,7 @@ lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *sy
     // Phases 1-2: lambda' to HBM (and to the caller's buffer if given)
     float *lam_hbm = lam ? lam : d->d_lamp;
     e = decode_chunks(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam_hbm, stats,
-                      LEAD_STAGE_LOCAL, s);
+                      LEAD_STAGE_LOCAL, s, decoder_workspace(d));
     if (e != hipSuccess) return hip_fail(e, "local-stage launch");
     lead::DecodeArgs a = base_args(d);
     a.synd = synd;
@@ -959,7 +1044,8 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
                 e = hipEventRecord(e0, s);
                 if (e == hipSuccess)
                     e = decode_chunks(d, n, synd, synd_words, prior, mode, ehat, ew, post,
-                                      d->params.stage == LEAD_STAGE_LOCAL ? lam : nullptr, stats, d->params.stage, s);
+                                      d->params.stage == LEAD_STAGE_LOCAL ? lam : nullptr, stats, d->params.stage, s,
+                                      decoder_workspace(d));
                 if (e == hipSuccess) e = hipEventRecord(e1, s);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 float ms = 0.f;
