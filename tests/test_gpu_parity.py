@@ -215,7 +215,7 @@ def _wilson(k, n, z=1.96):
     return c - h, c + h
 
 
-@pytest.mark.parametrize("name,shots,p,T", [("T", 4000, 0.05, 32), ("M", 600, 0.02, 50)])
+@pytest.mark.parametrize("name,shots,p,T", [("T", 4000, 0.05, 32)])
 def test_logical_error_rate_in_oracle_ci(name, shots, p, T):
     """c-14: over all shots, ill-conditioned ones included, the GPU's logical
     error rate (failure = not converged, or residual a non-trivial logical)
