@@ -20,8 +20,17 @@
  *                  syndromes never converge, boost is a no-op for BP, local
  *                  slices against computation trees, equivariance under the
  *                  centre of D_6
- *   oracle_global_bp  the same BP routine as oracle_bp, and oracle_osd0;
- *                  no separate pin
+ *   oracle_global_bp  the same BP routine as oracle_bp; its first iteration
+ *                  against the scaled single-check min-cost closed form on
+ *                  the global graph, its zero-syndrome closed form
+ *   oracle_osd     OSD-0 is the information-set solution (brute force on
+ *                  small matrices), unreachable syndromes reported; the
+ *                  combination sweep returns the cheapest of its candidates
+ *                  (enumerated independently), the cost unit against its
+ *                  closed form; local and global OSD inside LEAD rebuilt
+ *                  step by step from the oracle's own intermediate outputs
+ *   stored outcomes  tests/golden/outcomes_*.json: 10^4-shot outcomes,
+ *                  re-decoded on a sample by the current oracle
  *   margin output  diagnostic only: parity unpinned
  */
 #ifndef LEAD_ORACLE_H
@@ -71,6 +80,12 @@ typedef struct {
      * channel priors locally; lambda' in LEAD's global stage, the channel
      * prior in global BP alone); see oracle_osd. */
     int    osd_order;
+    /* 1: both OSDs rank by the exact FP64 posterior (ties in position
+     * order) and price candidates with exact FP64 weights ln(1 + e^lambda),
+     * instead of round(64 L) keys and round(64 ln(1 + e^lambda)) integer
+     * weights.  0 (the reading shared with the GPU) is the default; 1
+     * exists to measure what the rounding to 1/64 changes. */
+    int    osd_exact;
 } oracle_params;
 
 /* info[] layout for oracle_info */
@@ -111,6 +126,10 @@ int  oracle_osd0(int rows, int cols, const uint8_t *H, const uint8_t *s, const d
  * costs from the prior LLRs `prior` (unused at order 0; see lead_oracle.c). */
 int  oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L,
                 const double *prior, int order, uint8_t *e);
+/* The same with exact FP64 ranking and costs when exact = 1 (see
+ * oracle_params.osd_exact). */
+int  oracle_osd_ex(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L,
+                   const double *prior, int order, int exact, uint8_t *e);
 /* Cost of setting a bit whose prior LLR is lambda: round(64 ln(1 + e^lambda)). */
 long oracle_osd_weight(double lambda);
 
