@@ -617,8 +617,19 @@ long oracle_osd_weight(double lambda) {
  *   sum over set bits of oracle_osd_weight(prior[j]).
  * Returns 0, or -1 when s is not in the column space of H (e is then all
  * zero). */
+static double osd_weight_exact(double lambda) {
+    return (lambda > 0.0 ? lambda : 0.0) + log1p(exp(-fabs(lambda)));
+}
+
 int oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L,
                const double *prior, int order, uint8_t *e) {
+    return oracle_osd_ex(rows, cols, H, s, L, prior, order, 0, e);
+}
+
+/* exact = 1: keys are L itself and candidate costs sums of
+ * osd_weight_exact (FP64), otherwise as described above. */
+int oracle_osd_ex(int rows, int cols, const uint8_t *H, const uint8_t *s, const double *L,
+                  const double *prior, int order, int exact, uint8_t *e) {
     const int words = cols / 64 + 1;          /* bit `cols` holds s */
     int *ord = (int *)malloc(sizeof(int) * (size_t)cols);
     int *pivcol = (int *)malloc(sizeof(int) * (size_t)(rows > 0 ? rows : 1));
@@ -627,7 +638,7 @@ int oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const dou
     uint64_t *M = (uint64_t *)calloc((size_t)rows * words, sizeof(uint64_t));
     for (int j = 0; j < cols; j++) {
         ord[j] = j;
-        key[j] = nearbyint(L[j] * 64.0);       /* round half to even */
+        key[j] = exact ? L[j] : nearbyint(L[j] * 64.0);   /* round half to even */
     }
     for (int a = 1; a < cols; a++) {          /* stable insertion sort */
         int x = ord[a], b = a;
@@ -674,18 +685,21 @@ int oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const dou
             /* T in rank order */
             int nt = 0;
             int *T = (int *)malloc(sizeof(int) * (size_t)cols);
-            long *q = (long *)malloc(sizeof(long) * (size_t)cols);
+            double *q = (double *)malloc(sizeof(double) * (size_t)cols);
             for (int t = 0; t < cols; t++)
                 if (!ispiv[ord[t]]) T[nt++] = ord[t];
-            for (int j = 0; j < cols; j++) q[j] = oracle_osd_weight(prior[j]);
+            /* integer weights are exact in a double (|w| < 2^53), so the
+             * sums below are the integer sums */
+            for (int j = 0; j < cols; j++)
+                q[j] = exact ? osd_weight_exact(prior[j]) : (double)oracle_osd_weight(prior[j]);
             /* cost of the candidate with e_T = {a} or {a, b} (b < 0: none) */
-            long best = 0;
+            double best = 0;
             int ba = -1, bb = -1;
             for (int k = 0; k < rank; k++)
                 if (OSD_BIT(k, cols)) best += q[pivcol[k]];
             for (int x = 0; x < nt; x++) {
                 const int a = T[x];
-                long c = q[a];
+                double c = q[a];
                 for (int k = 0; k < rank; k++)
                     if (OSD_BIT(k, cols) ^ OSD_BIT(k, a)) c += q[pivcol[k]];
                 if (c < best) { best = c; ba = a; bb = -1; }
@@ -694,7 +708,7 @@ int oracle_osd(int rows, int cols, const uint8_t *H, const uint8_t *s, const dou
             for (int x = 0; x < lam; x++)
                 for (int y = x + 1; y < lam; y++) {
                     const int a = T[x], b = T[y];
-                    long c = q[a] + q[b];
+                    double c = q[a] + q[b];
                     for (int k = 0; k < rank; k++)
                         if (OSD_BIT(k, cols) ^ OSD_BIT(k, a) ^ OSD_BIT(k, b)) c += q[pivcol[k]];
                     if (c < best) { best = c; ba = a; bb = b; }
@@ -790,7 +804,7 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             /* local post-processing: OSD (order osd_order, costs from the
              * view's channel priors) where BP left the local syndrome
              * unsatisfied; its estimate replaces BP's decisions */
-            if (p->local_osd && !conv_v && oracle_osd(r, D2, c->hloc[type], sv, Lv, lamv, p->osd_order, ev) == 0) {
+            if (p->local_osd && !conv_v && oracle_osd_ex(r, D2, c->hloc[type], sv, Lv, lamv, p->osd_order, p->osd_exact, ev) == 0) {
                 conv_v = 1;
                 nosd++;
             }
@@ -820,7 +834,7 @@ int oracle_decode(const oracle_code *c, int type, const oracle_params *p, int sh
             /* global post-processing: OSD-0 on H_t with the global posteriors
              * where global BP left the syndrome unsatisfied (when s is not
              * in the column space of H_t, BP's estimate stays) */
-            if (p->global_osd && !conv && oracle_osd(m, n, c->H[type], s, Lg, lamp, p->osd_order, eo) == 0) {
+            if (p->global_osd && !conv && oracle_osd_ex(m, n, c->H[type], s, Lg, lamp, p->osd_order, p->osd_exact, eo) == 0) {
                 memcpy(eg, eo, (size_t)n);
                 conv = 2;
             }
@@ -862,7 +876,7 @@ int oracle_global_bp(const oracle_code *c, int type, const oracle_params *p, int
         int it = bp_run(glob, s, prior + (size_t)shot * n, p, p->max_iter_global, Lg, eg, &conv, NULL, &wg);
         /* BP followed by OSD-0 where BP misses the syndrome */
         if (p->global_osd && !conv &&
-            oracle_osd(m, n, c->H[type], s, Lg, prior + (size_t)shot * n, p->osd_order, eo) == 0) {
+            oracle_osd_ex(m, n, c->H[type], s, Lg, prior + (size_t)shot * n, p->osd_order, p->osd_exact, eo) == 0) {
             memcpy(eg, eo, (size_t)n);
             conv = 2;
         }

@@ -25,14 +25,16 @@ class Params(C.Structure):
                 ("max_iter_local", C.c_int), ("max_iter_global", C.c_int),
                 ("llr_clamp", C.c_double), ("early_exit", C.c_int), ("stage", C.c_int),
                 ("boost", C.c_int), ("perturb", C.c_double), ("perturb_seed", C.c_uint64),
-                ("local_osd", C.c_int), ("global_osd", C.c_int), ("osd_order", C.c_int)]
+                ("local_osd", C.c_int), ("global_osd", C.c_int), ("osd_order", C.c_int),
+                ("osd_exact", C.c_int)]
 
 
 def params(alpha=1.0, bp=MINSUM, ms_scale=0.75, max_iter_local=32, max_iter_global=32,
            llr_clamp=30.0, early_exit=1, stage=FULL, boost=1, perturb=0.0, perturb_seed=0,
-           local_osd=0, global_osd=0, osd_order=0) -> Params:
+           local_osd=0, global_osd=0, osd_order=0, osd_exact=0) -> Params:
     return Params(alpha, bp, ms_scale, max_iter_local, max_iter_global, llr_clamp,
-                  early_exit, stage, boost, perturb, perturb_seed, local_osd, global_osd, osd_order)
+                  early_exit, stage, boost, perturb, perturb_seed, local_osd, global_osd, osd_order,
+                  osd_exact)
 
 
 _lib = None
@@ -69,6 +71,8 @@ def lib():
         L.oracle_osd0.argtypes = [C.c_int, C.c_int, P, P, P, P]
         L.oracle_osd.restype = C.c_int
         L.oracle_osd.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, P]
+        L.oracle_osd_ex.restype = C.c_int
+        L.oracle_osd_ex.argtypes = [C.c_int, C.c_int, P, P, P, P, C.c_int, C.c_int, P]
         L.oracle_osd_weight.restype = C.c_long
         L.oracle_osd_weight.argtypes = [C.c_double]
         L.oracle_global_bp.argtypes = [C.c_void_p, C.c_int, C.POINTER(Params), C.c_int, P,
@@ -277,16 +281,17 @@ def osd0(H: np.ndarray, s: np.ndarray, L: np.ndarray):
     return e, rc == 0
 
 
-def osd(H: np.ndarray, s: np.ndarray, L: np.ndarray, prior=None, order: int = 0):
+def osd(H: np.ndarray, s: np.ndarray, L: np.ndarray, prior=None, order: int = 0, exact: bool = False):
     """OSD of H e = s: ranking by round(64 L) as osd0; order >= 1 adds the
-    combination sweep with costs from the prior LLRs.  Returns (e, ok)."""
+    combination sweep with costs from the prior LLRs.  exact: rank by L and
+    price in FP64 instead.  Returns (e, ok)."""
     H = np.ascontiguousarray(H, dtype=np.uint8)
     s = np.ascontiguousarray(s, dtype=np.uint8)
     L = np.ascontiguousarray(L, dtype=np.float64)
     rows, cols = H.shape
     pr = np.ascontiguousarray(np.zeros(cols) if prior is None else prior, dtype=np.float64)
     e = np.zeros(cols, dtype=np.uint8)
-    rc = lib().oracle_osd(rows, cols, _p(H), _p(s), _p(L), _p(pr), int(order), _p(e))
+    rc = lib().oracle_osd_ex(rows, cols, _p(H), _p(s), _p(L), _p(pr), int(order), int(exact), _p(e))
     return e, rc == 0
 
 
