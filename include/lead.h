@@ -162,9 +162,9 @@ typedef struct {
                                  and its estimate is the OSD-0 solution.  A
                                  syndrome outside the column space of H_t
                                  keeps BP's estimate and report.  Stages FULL
-                                 and GLOBAL, kernels compiled for the code,
-                                 codes with ceil(m/256) * ceil(n/64) <= 64
-                                 (LEAD_E_UNSUPPORTED otherwise, and from
+                                 and GLOBAL, kernels compiled for the code
+                                 (lead_schedule.global_osd_form picks the
+                                 kernel; LEAD_E_UNSUPPORTED from
                                  lead_decode_plain).  0: none                  */
     int32_t osd_order;        /* order lambda of the OSDs of local_post and
                                  global_post, 0..8 (needs one of them).
@@ -249,7 +249,9 @@ lead_status lead_decode(lead_decoder *dec, int64_t shots, const uint64_t *d_synd
  * takes at most (LEAD_NOALLOC_SCRATCH_BYTES - 2048) / b shots, b = 4 *
  * order * delta^2 + 8 * order bytes per shot (plus 4n, 32 and 4n with
  * global_post for the post, stats and, with osd_order > 0, lambda' outputs
- * passed as NULL): about 7 300 A5 shots or 1 500 PSL(2,7) shots.  Larger
+ * passed as NULL; the global OSD with the matrix in device memory also
+ * takes its matrix slots from the scratch, as many as fit beside the batch,
+ * at least one): about 7 300 A5 shots or 1 500 PSL(2,7) shots.  Larger
  * batches return LEAD_E_CAPACITY with the limit in lead_last_error and
  * enqueue nothing.  Every call on one GPU uses that GPU's one array, which
  * keeps the last call's contents (the queue counters are cleared by a fill
@@ -303,6 +305,16 @@ typedef struct {
     int32_t chunk_shots;          /* shots per launch of the work-queue form
                                      (at most the workspace); 0: the workspace.
                                      Larger launches leave fewer kernel tails. */
+    int32_t global_osd_form;      /* kernel of the global OSD (global_post):
+                                     1: the rows of [H_t | s] in registers
+                                     (codes with ceil(m/256) * ceil(n/64) <= 64);
+                                     2: the matrix in device memory, one slot
+                                     of (ceil(n/64) + 1) * m words per
+                                     workgroup (any code up to 32768 checks and
+                                     65535 qubits; the decoder allocates a slot
+                                     per compute unit); 0: 1 where it fits, else
+                                     2.  Same outputs.  Reads back as the form
+                                     in use (2 where 1 does not fit). */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);

@@ -57,7 +57,10 @@ struct lead_decoder {
     int waves_per_cu[2] = {4, 4};
     float *d_Lv = nullptr;
     uint32_t *d_vflag = nullptr;
-    int64_t *d_counter = nullptr;          // [0] queue head, [1] local OSD list length
+    int64_t *d_counter = nullptr;          // [0] queue head, [1] local OSD list length,
+                                           // [2] global OSD shot queue (matrix in HBM)
+    uint64_t *d_osd_mat = nullptr;         // global OSD matrix slots (matrix in HBM)
+    int osd_slots = 0;
     uint32_t *d_osd_list = nullptr;        // views pending local OSD-0 (ws_shots * N)
     // phase timing: event triples (before Phase 1, between, after Phases 2-3)
     bool timing = false;
@@ -92,6 +95,8 @@ struct Workspace {
     uint32_t *osd_list = nullptr;
     float *gpost = nullptr, *glam = nullptr;
     lead_shot_stats *gstats = nullptr;
+    uint64_t *osd_mat = nullptr;   // global OSD matrix slots (matrix in HBM)
+    int osd_slots = 0;
     int64_t shots = 0;
 };
 
@@ -133,22 +138,52 @@ bool sum_product(const lead_decoder *d) { return d->params.bp == LEAD_BP_SUMPROD
 // Sum-product and OSD-0 run only on the kernels compiled for the code.
 bool needs_spec(const lead_decoder *d) { return sum_product(d) || d->params.local_post != 0; }
 
-bool osd_ready(const lead_decoder *d) { return d->spec && d->spec->osd && d->spec->osd_cs && d->d_rptr; }
+bool osd_kernels(const lead::jit::Kernels *k) {
+    return k && ((k->osd && k->osd_cs) || (k->osd_big && k->osd_big_cs));
+}
+
+bool osd_ready(const lead_decoder *d) { return osd_kernels(d->spec.get()) && d->d_rptr; }
+
+// The global OSD kernel in use keeps [H_t | s] in device memory (asked for,
+// or the rows do not fit in registers).
+bool osd_big(const lead_decoder *d) {
+    const lead::jit::Kernels *k = d->spec.get();
+    if (!k || !k->osd_big) return false;
+    return d->sched.global_osd_form == 2 || !(k->osd && k->osd_cs);
+}
 
 // Posterior and statistics buffers of the global OSD-0 for calls that pass
-// none (allocated once, when global_post is first set).
+// none, and the matrix slots of the kernel with the matrix in device memory
+// (one per compute unit: the kernel's LDS admits one workgroup per CU);
+// allocated when global_post is first set or that kernel is first chosen.
 hipError_t ensure_osd_workspace(lead_decoder *d) {
     hipError_t e = hipSuccess;
     if (!d->d_gpost) e = hipMalloc(&d->d_gpost, sizeof(float) * (size_t)d->ws_shots * d->n);
     if (e == hipSuccess && !d->d_gstats) e = hipMalloc(&d->d_gstats, sizeof(lead_shot_stats) * (size_t)d->ws_shots);
     if (e == hipSuccess && !d->d_glam) e = hipMalloc(&d->d_glam, sizeof(float) * (size_t)d->ws_shots * d->n);
+    if (e == hipSuccess && osd_big(d) && !d->d_osd_mat) {
+        const int slots = std::max(1, d->cus);
+        e = hipMalloc(&d->d_osd_mat, lead::jit::osd_big_slot_bytes(*d->code, d->type) * (size_t)slots);
+        if (e == hipSuccess) d->osd_slots = slots;
+    }
     return e;
 }
 
-// OSD on H_t for the shots of `a` that global BP left unresolved: one
-// workgroup per shot (the others exit at once).
-hipError_t launch_osd(const lead_decoder *d, lead::DecodeArgs a, hipStream_t s) {
+// OSD on H_t for the shots of `a` that global BP left unresolved: with the
+// rows in registers, one workgroup per shot (the others exit at once); with
+// the matrix in device memory, one persistent workgroup per matrix slot
+// taking unresolved shots from a queue.
+hipError_t launch_osd(const lead_decoder *d, lead::DecodeArgs a, const Workspace &ws, hipStream_t s) {
     lead::OsdArgs o{d->d_rptr, d->d_ridx};
+    if (osd_big(d)) {
+        lead::OsdBigArgs b{ws.osd_mat, ws.counter + 2};
+        hipError_t e = lead::launch_clear_i64(b.queue, 1, s);
+        if (e != hipSuccess) return e;
+        const int64_t grid = std::min<int64_t>(ws.osd_slots, a.shots);
+        void *args[] = {&a, &o, &b};
+        return hipModuleLaunchKernel(a.osd_order > 0 ? d->spec->osd_big_cs : d->spec->osd_big, (unsigned)grid, 1, 1,
+                                     (unsigned)d->spec->osd_big_wg, 1, 1, 0, s, args, nullptr);
+    }
     void *args[] = {&a, &o};
     return hipModuleLaunchKernel(a.osd_order > 0 ? d->spec->osd_cs : d->spec->osd, (unsigned)a.shots, 1, 1,
                                  (unsigned)d->spec->osd_wg, 1, 1, 0, s, args, nullptr);
@@ -211,6 +246,8 @@ Workspace decoder_workspace(const lead_decoder *d) {
     ws.gpost = d->d_gpost;
     ws.glam = d->d_glam;
     ws.gstats = d->d_gstats;
+    ws.osd_mat = d->d_osd_mat;
+    ws.osd_slots = d->osd_slots;
     ws.shots = d->ws_shots;
     return ws;
 }
@@ -360,7 +397,7 @@ hipError_t decode_chunks(lead_decoder *d, int64_t shots, const uint64_t *synd, i
         }
         hipError_t e = split && use_spec(d) ? launch_spec(d, a, w, s, ev)
                                    : lead::launch_decode(d->D, d->r, a, w, split, s, ev ? ev->data() : nullptr);
-        if (e == hipSuccess && gpost) e = launch_osd(d, a, s);
+        if (e == hipSuccess && gpost) e = launch_osd(d, a, ws, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -583,7 +620,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
     if (e == hipSuccess) e = hipMemcpy(d->d_own, own.data(), sizeof(uint32_t) * own.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d->d_Lv, sizeof(float) * (size_t)d->ws_shots * d->N * D2);
     if (e == hipSuccess) e = hipMalloc(&d->d_vflag, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
-    if (e == hipSuccess) e = hipMalloc(&d->d_counter, 2 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&d->d_counter, 4 * sizeof(int64_t));
     if (e == hipSuccess) e = hipMalloc(&d->d_osd_list, sizeof(uint32_t) * (size_t)d->ws_shots * d->N);
     // kernels for this code's check structure (the precompiled ones serve
     // when they cannot be built)
@@ -600,7 +637,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
             if (e == hipSuccess) e = hipMemcpy(d->d_pv, pv.data(), sizeof(uint32_t) * pv.size(), hipMemcpyHostToDevice);
             if (e == hipSuccess)
                 e = hipMemcpy(d->d_fown, fown.data(), sizeof(uint64_t) * fown.size(), hipMemcpyHostToDevice);
-            if (e == hipSuccess && d->spec->osd) {
+            if (e == hipSuccess && (d->spec->osd || d->spec->osd_big)) {
                 e = hipMalloc(&d->d_rptr, sizeof(int32_t) * tt.csr_ptr.size());
                 if (e == hipSuccess) e = hipMalloc(&d->d_ridx, sizeof(int32_t) * std::max<size_t>(tt.csr_idx.size(), 1));
                 if (e == hipSuccess)
@@ -612,7 +649,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
         }
         if (e == hipSuccess && d->params.global_post) {
             if (!osd_ready(d.get())) {
-                jerr = d->spec ? "the code is too large for the global OSD-0 kernel" : jerr;
+                jerr = d->spec ? "the code is too large for the global OSD kernels" : jerr;
                 e = hipErrorNotSupported;
             } else {
                 e = ensure_osd_workspace(d.get());
@@ -647,6 +684,7 @@ lead_status create_decoder(std::shared_ptr<lead::Code> code, int t, const lead_p
         (void)hipFree(d->d_gpost);
         (void)hipFree(d->d_glam);
         (void)hipFree(d->d_gstats);
+        (void)hipFree(d->d_osd_mat);
         return hip_fail(e, "device allocation");
     }
     *out = d.release();
@@ -704,9 +742,13 @@ lead_status lead_decoder_set_params(lead_decoder *d, const lead_params *params) 
         auto k = lead::jit::load(*d->code, d->type, d->device, params->bp == LEAD_BP_SUMPRODUCT, jerr);
         if (!k && params->bp == LEAD_BP_SUMPRODUCT) return fail(LEAD_E_UNSUPPORTED, "sum-product: " + jerr);
         if (k && !d->d_pv) return fail(LEAD_E_UNSUPPORTED, "no partner tables");
-        if (params->global_post && !(k && k->osd && k->osd_cs)) return fail(LEAD_E_UNSUPPORTED, "no global OSD kernel");
+        if (params->global_post && !osd_kernels(k.get())) return fail(LEAD_E_UNSUPPORTED, "no global OSD kernel");
         d->spec = k;
         d->params = *params;
+        if (params->global_post) {
+            hipError_t e = ensure_osd_workspace(d);
+            if (e != hipSuccess) return hip_fail(e, "OSD workspace allocation");
+        }
         d->sched.specialized = spec_form(d, lead::jit::kExplicit);
         if (needs_spec(d)) d->sched.fused = 0;
         return LEAD_OK;
@@ -724,6 +766,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
     if (sc->shots_per_workgroup < 0 || sc->local_chunk < 0 || sc->local_waves < 0 || sc->chunk_shots < 0)
         return fail(LEAD_E_ARG, "negative schedule field");
+    if (sc->global_osd_form < 0 || sc->global_osd_form > 2) return fail(LEAD_E_ARG, "bad global_osd_form");
     const int spw = sc->shots_per_workgroup ? sc->shots_per_workgroup : default_spw(d->N);
     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup)
         return fail(LEAD_E_UNSUPPORTED, "shots_per_workgroup too large for the workgroup limit");
@@ -735,10 +778,15 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.local_chunk = sc->local_chunk ? sc->local_chunk : 256;
     d->sched.local_waves = sc->local_waves;
     d->sched.chunk_shots = sc->chunk_shots;
+    d->sched.global_osd_form = sc->global_osd_form;
     d->sched.specialized = spec_form(d, sc->specialized);
     if (needs_spec(d)) {   // sum-product and OSD-0 run the kernels compiled for the code only
         d->sched.fused = 0;
         if (!d->sched.specialized) d->sched.specialized = spec_form(d, lead::jit::kExplicit);
+    }
+    if (d->params.global_post && osd_ready(d)) {
+        hipError_t e = ensure_osd_workspace(d);
+        if (e != hipSuccess) return hip_fail(e, "OSD workspace allocation");
     }
     return LEAD_OK;
 }
@@ -746,6 +794,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
 lead_status lead_decoder_get_schedule(const lead_decoder *d, lead_schedule *sc) {
     if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
     *sc = d->sched;
+    if (d->spec) sc->global_osd_form = osd_big(d) ? 2 : (d->spec->osd ? 1 : 0);
     return LEAD_OK;
 }
 
@@ -781,6 +830,7 @@ void lead_decoder_destroy(lead_decoder *d) {
     (void)hipFree(d->d_gpost);
     (void)hipFree(d->d_glam);
     (void)hipFree(d->d_gstats);
+    (void)hipFree(d->d_osd_mat);
     (void)drain_timing(d);
     free_plain(d);
     delete d;
@@ -820,8 +870,15 @@ lead_status lead_decode_noalloc(lead_decoder *d, int64_t shots, const uint64_t *
     const size_t gs = gpost && !stats ? sizeof(lead_shot_stats) : 0;
     const size_t gl = gpost && !lam && d->params.osd_order > 0 ? sizeof(float) * (size_t)d->n : 0;
     const size_t per_shot = lv + 2 * vf + gp + gs + gl;
-    const size_t head = 256, slack = 7 * 256;   // counters, alignment of the seven arrays
-    const int64_t capacity = (int64_t)((lead::kScratchBytes - head - slack) / per_shot);
+    const size_t head = 256, slack = 8 * 256;   // counters, alignment of the eight arrays
+    // the global OSD with the matrix in device memory works in matrix slots
+    // (one per workgroup): as many as fit beside the batch, at most one per CU
+    const size_t slot = gpost && osd_big(d) ? lead::jit::osd_big_slot_bytes(*d->code, d->type) : 0;
+    const size_t slot_room = slot ? slot * (size_t)std::min<int64_t>(std::max(1, d->cus), shots) : 0;
+    if (slot && lead::kScratchBytes < head + slack + slot)
+        return fail(LEAD_E_CAPACITY, "lead_decode_noalloc: one global OSD matrix slot (" + std::to_string(slot) +
+                                         " bytes) does not fit the static scratch");
+    const int64_t capacity = (int64_t)((lead::kScratchBytes - head - slack - slot) / per_shot);
     if (shots > capacity)
         return fail(LEAD_E_CAPACITY, "lead_decode_noalloc: " + std::to_string(shots) + " shots need " +
                                          std::to_string(per_shot * (size_t)shots + head) +
@@ -845,6 +902,11 @@ lead_status lead_decode_noalloc(lead_decoder *d, int64_t shots, const uint64_t *
     ws.gpost = reinterpret_cast<float *>(carve(gp * (size_t)shots));
     ws.gstats = reinterpret_cast<lead_shot_stats *>(carve(gs * (size_t)shots));
     ws.glam = reinterpret_cast<float *>(carve(gl * (size_t)shots));
+    if (slot) {
+        const size_t room = lead::kScratchBytes - std::min(lead::kScratchBytes, off);
+        ws.osd_slots = (int)std::min<size_t>(room / slot, std::min(slot_room / slot, (size_t)std::max(1, d->cus)));
+        ws.osd_mat = reinterpret_cast<uint64_t *>(carve(slot * (size_t)ws.osd_slots));
+    }
     ws.shots = shots;
     if (off > lead::kScratchBytes) return fail(LEAD_E_CAPACITY, "lead_decode_noalloc: scratch layout overflow");
     // every launch is enqueued without timing events (no event objects are
@@ -1030,13 +1092,13 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
                     if (fused && chunk != 256) continue;
                     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup) continue;
                     if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, spw), spw, d->n) > 65536) continue;
-                    cand.push_back(lead_schedule{spw, fused, chunk, 0, 0});
+                    cand.push_back(lead_schedule{spw, fused, chunk, 0, 0, 0, saved.global_osd_form});
                 }
         // the specialised split kernels fix their own workgroup shape
         for (int form : {lead::jit::kCompressed, lead::jit::kExplicit, lead::jit::kSumProduct})
             if (d->spec && d->spec->has[form - 1])
                 for (int chunk : {64, 256, 1024})
-                    cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, form});
+                    cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, form, 0, saved.global_osd_form});
         for (const lead_schedule &c : cand) {
             if (lead_decoder_set_schedule(d, &c) != LEAD_OK) continue;
             float ms_best = 1e30f;

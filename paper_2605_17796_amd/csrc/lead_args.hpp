@@ -75,4 +75,14 @@ struct OsdArgs {
     const int32_t *ridx;
 };
 
+// Workspace of the global OSD kernel that keeps [H_t | s] in device memory
+// (codes whose rows do not fit in registers): one matrix slot per
+// workgroup, (ceil(n/64) + 1) x m words, word-major (word k of row r at
+// k * m + r; the last word column holds s in bit 0), and the queue of
+// shots the workgroups take one at a time.
+struct OsdBigArgs {
+    uint64_t *mat;
+    int64_t *queue;            // [0] next shot (cleared before each launch)
+};
+
 }  // namespace lead

@@ -8,6 +8,7 @@
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -224,6 +225,21 @@ int osd_workgroup(const Code &c, int t) {
     return 64 * ((m + 64 * RPL - 1) / (64 * RPL));
 }
 
+bool osd_big_fits(const Code &c, int t) {
+    const int m = c.order * c.t[t].r;
+    return m > 0 && c.n > 0 && m <= kOsdBigMaxRows && c.n <= 65535;
+}
+
+int osd_big_workgroup(const Code &c, int t) {
+    const int m = c.order * c.t[t].r;
+    return std::min(512, 64 * ((m + 63) / 64));
+}
+
+size_t osd_big_slot_bytes(const Code &c, int t) {
+    const size_t m = (size_t)c.order * c.t[t].r;
+    return sizeof(uint64_t) * ((size_t)(c.n + 63) / 64 + 1) * m;
+}
+
 std::string source(const Code &c, int t, bool sp) {
     const TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
@@ -292,6 +308,21 @@ std::string source(const Code &c, int t, bool sp) {
           << ") lead_spec_osd(lead::DecodeArgs a, lead::OsdArgs o) { lead_spec::osd_global_body<LeadGlobal, false>(a, o); }\n"
           << "extern \"C\" __global__ void __launch_bounds__(" << owg
           << ") lead_spec_osd_cs(lead::DecodeArgs a, lead::OsdArgs o) { lead_spec::osd_global_body<LeadGlobal, true>(a, o); }\n";
+    }
+    if (osd_big_fits(c, t)) {
+        const int m = c.order * tt.r, bwg = osd_big_workgroup(c, t);
+        int sortn = 1;
+        while (sortn < c.n) sortn <<= 1;
+        const int kc = std::max(1, std::min(4, sortn / 2048));
+        o << "struct LeadGlobalBig {\n    static constexpr int M = " << m << ", NQ = " << c.n << ", W = " << (c.n + 63) / 64
+          << ", RPL = " << (m + bwg - 1) / bwg << ", WG = " << bwg << ", RANK = " << tt.rank << ", SORTN = " << sortn
+          << ", KC = " << kc << ";\n};\n"
+          << "extern \"C\" __global__ void __launch_bounds__(" << bwg
+          << ") lead_spec_osd_big(lead::DecodeArgs a, lead::OsdArgs o, lead::OsdBigArgs b) "
+             "{ lead_spec::osd_big_body<LeadGlobalBig, false>(a, o, b); }\n"
+          << "extern \"C\" __global__ void __launch_bounds__(" << bwg
+          << ") lead_spec_osd_big_cs(lead::DecodeArgs a, lead::OsdArgs o, lead::OsdBigArgs b) "
+             "{ lead_spec::osd_big_body<LeadGlobalBig, true>(a, o, b); }\n";
     }
     return o.str();
 }
@@ -385,6 +416,11 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
         e = hipModuleGetFunction(&k->osd, k->module, "lead_spec_osd");
         if (e == hipSuccess) e = hipModuleGetFunction(&k->osd_cs, k->module, "lead_spec_osd_cs");
         k->osd_wg = osd_workgroup(c, t);
+    }
+    if (e == hipSuccess && osd_big_fits(c, t)) {
+        e = hipModuleGetFunction(&k->osd_big, k->module, "lead_spec_osd_big");
+        if (e == hipSuccess) e = hipModuleGetFunction(&k->osd_big_cs, k->module, "lead_spec_osd_big_cs");
+        k->osd_big_wg = osd_big_workgroup(c, t);
     }
     if (e != hipSuccess) {
         err = std::string("module load: ") + hipGetErrorString(e);

@@ -44,6 +44,17 @@ bool osd_fits(const Code &c, int t);
 // at ceil(m/256) rows per lane.
 int osd_workgroup(const Code &c, int t);
 
+// The global OSD kernel with [H_t | s] in device memory (any code with at
+// most kOsdBigMaxRows rows and 65535 qubits): its workgroup size (the fewest
+// whole waves, at most 512 lanes so that 256 VGPRs are available, holding
+// the rows at ceil(m/512) rows per lane; its LDS admits one workgroup per CU
+// for PSL(2,7) anyway) and the bytes of one matrix slot ((ceil(n/64) + 1) * m
+// words).
+constexpr int kOsdBigMaxRows = 32 * 512;
+bool osd_big_fits(const Code &c, int t);
+int osd_big_workgroup(const Code &c, int t);
+size_t osd_big_slot_bytes(const Code &c, int t);
+
 struct Kernels {
     hipModule_t module = nullptr;
     // [form - 1][prior mode]: Phase 1 queue kernel for per-shot / per-qubit priors
@@ -53,6 +64,9 @@ struct Kernels {
     hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
     hipFunction_t osd_cs = nullptr;      // the same with the combination sweep
     int osd_wg = 0;                      // its workgroup size
+    hipFunction_t osd_big = nullptr;     // global OSD-0 with [H_t | s] in device memory
+    hipFunction_t osd_big_cs = nullptr;  // the same with the combination sweep
+    int osd_big_wg = 0;                  // their workgroup size
     bool has[kForms] = {};               // [form - 1]: compiled
     int wg = 0;                          // workgroup size of `global`
     int spw = 0;                         // shots per workgroup of `global`

@@ -300,6 +300,10 @@ __global__ void __launch_bounds__(64) local_kernel(DecodeArgs a, LocalArgs w) {
 
 // Work queue reset before a local_kernel launch (a kernel rather than a
 // memset, so that the launch sequence can be captured in a graph).
+__global__ void clear_i64_kernel(int64_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 __global__ void reset_counter_kernel(int64_t *counter) {
     counter[0] = 0;   // work-queue head
     counter[1] = 0;   // local OSD-0 list
@@ -829,6 +833,11 @@ hipError_t launch_round(int D, int, const RoundArgs &ra, hipStream_t s) {
         case 8: return launch_round_d<8, 16>(wg, ra, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_clear_i64(int64_t *p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(clear_i64_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_reset_counter(int64_t *counter, hipStream_t s) {

@@ -42,6 +42,8 @@ hipError_t launch_decode(int D, int rmax_needed, const DecodeArgs &a, const Loca
                          hipStream_t s, hipEvent_t *ev = nullptr);
 hipError_t launch_round(int D, int rmax_needed, const RoundArgs &a, hipStream_t s);
 hipError_t launch_reset_counter(int64_t *counter, hipStream_t s);
+// Clears n int64 words with a fill kernel (no memset node under capture).
+hipError_t launch_clear_i64(int64_t *p, int n, hipStream_t s);
 hipError_t launch_syndrome(const SyndArgs &a, hipStream_t s);
 bool kernel_supported(int D, int r);
 int local_waves_per_cu(int D, int pm);

@@ -1504,4 +1504,390 @@ __device__ __forceinline__ void osd_global_body(const DecodeArgs &a, const lead:
     if (tid == 0) stp->converged = 2;
 }
 
+// ---------------------------------------------------------------------------
+// Global OSD with [H | s] in device memory, for codes whose rows do not fit
+// in registers (PSL(2,7): 2688 x 5376 bits, 1.8 MB per shot).  The method and
+// the result are those of osd_global_body (same ranking, same information
+// set, same candidates and costs); the organisation differs:
+//  * workgroups are persistent: each takes the next shot that global BP left
+//    unresolved from a queue and works in its own matrix slot;
+//  * the slot is word-major (word k of row r at k*M + r; word column W holds
+//    s in bit 0), so a wave's accesses to one word of consecutive rows
+//    coalesce;
+//  * Gauss-Jordan runs panel by panel, a panel being the 64 ranked columns
+//    of one word.  The panel word of every row is held in registers (rows
+//    tid + WG i) and reduced pivot by pivot as in osd_global_body, while each
+//    row records in a 64-bit mask which of the panel's pivot rows (as they
+//    were when the panel started) it has absorbed.  The other words are then
+//    updated in one pass, KC words at a time: each row XORs the combination
+//    of pivot rows its mask names, read from eight 256-entry tables of the
+//    XOR combinations of eight pivot rows each, built in LDS for those words.
+//    One pass per panel over the rest of the matrix replaces one pass per
+//    pivot;
+//  * in the combination sweep, the cost term sum_k u_k A_k[t] of flipping
+//    non-pivot column t is accumulated in a register of the lane owning t (a
+//    wave per 64-column word), from each row's word read once and spread to
+//    the lanes with readlane, instead of LDS atomics per set bit.
+// G: M, NQ, W = ceil(NQ/64), WG, RPL = ceil(M/WG) (rows per lane), RANK (of
+// H), SORTN (power of two >= NQ), KC (words per update chunk).
+template <class G, bool CS>
+__device__ __forceinline__ void osd_big_body(const DecodeArgs &a, const lead::OsdArgs &o,
+                                             const lead::OsdBigArgs &b) {
+    constexpr int WG = G::WG, NWAVE = WG / 64, W = G::W, M = G::M, NQ = G::NQ, RPL = G::RPL,
+                  SORTN = G::SORTN, KC = G::KC;
+    constexpr int WS = W + 1;                                   // word columns, the last holds s
+    constexpr int R0 = SORTN > 2048 * KC ? SORTN : 2048 * KC;   // words of region 0
+    constexpr int NPAIR = lead::kMaxOsdOrder * (lead::kMaxOsdOrder - 1) / 2;
+    static_assert(RPL <= 32 && NQ <= SORTN && NQ <= 65535 && WG % 64 == 0 && WG * RPL >= M && KC >= 1,
+                  "OSD sizes");
+    __shared__ uint64_t r0[R0];            // sort keys, then the XOR tables [8][256][KC]
+    __shared__ int32_t r1[NQ];             // qubit -> rank position, then weights by rank position
+    __shared__ unsigned short order[NQ];   // rank position -> qubit
+    __shared__ int32_t uarr[M];            // sweep: u of pivot row r (0 for the other rows)
+    __shared__ uint64_t P[64][KC];         // the panel's pivot rows, one word chunk
+    __shared__ int32_t prl[64];            // the panel's pivot rows
+    __shared__ uint64_t pw[2];             // pivot broadcast: panel word, absorbed mask
+    __shared__ uint64_t cmw[2][NWAVE];
+    __shared__ int32_t wmin[2][NWAVE];
+    __shared__ int32_t misc[4];            // shot, syndrome unreachable, C0, listed non-pivot columns
+    __shared__ uint32_t pbits[(NQ + 31) / 32];
+    __shared__ uint32_t ebits[(NQ + 31) / 32];
+    __shared__ int32_t tl[lead::kMaxOsdOrder], pairsum[NPAIR];
+    __shared__ unsigned long long best;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t *mat = b.mat + (size_t)blockIdx.x * WS * M;
+    lead::ShotStats *stats = reinterpret_cast<lead::ShotStats *>(a.stats);
+    for (;;) {
+        // ---- the next shot global BP left unresolved (every wave sees the
+        // same value and leaves together when the queue is empty)
+        if (tid == 0) {
+            int64_t sh;
+            do {
+                sh = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(b.queue), 1ull);
+            } while (sh < a.shots && stats[sh].converged != 0);
+            misc[0] = sh < a.shots ? (int32_t)sh : -1;
+            misc[1] = 0;
+        }
+        __syncthreads();
+        if (misc[0] < 0) return;
+        const int64_t shot = misc[0];
+        const float *Lp = a.post + shot * a.n;
+
+        // ---- ranking: rint(64 L) as an order-preserving word, then the index
+        for (int i = tid; i < SORTN; i += WG) {
+            uint64_t k = ~0ull;
+            if (i < NQ) {
+                const float q = __builtin_rintf(Lp[i] * 64.f) + 0.f;
+                uint32_t u = __float_as_uint(q);
+                u = (u >> 31) ? ~u : (u | 0x80000000u);
+                k = ((uint64_t)u << 32) | (uint32_t)i;
+            }
+            r0[i] = k;
+        }
+        __syncthreads();
+        for (int size = 2; size <= SORTN; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = tid; i < SORTN / 2; i += WG) {
+                    const int lo = 2 * i - (i & (stride - 1)), hi = lo + stride;
+                    const uint64_t x = r0[lo], y = r0[hi];
+                    if ((x > y) == ((lo & size) == 0)) {
+                        r0[lo] = y;
+                        r0[hi] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        for (int t = tid; t < NQ; t += WG) {
+            const int q = (int)(uint32_t)r0[t];
+            order[t] = (unsigned short)q;
+            r1[q] = t;
+        }
+        for (int i = tid; i < (NQ + 31) / 32; i += WG) {
+            ebits[i] = 0u;
+            pbits[i] = 0u;
+        }
+        __syncthreads();
+
+        // ---- this lane's rows of [H | s], columns in rank order (each row is
+        // written only by the lane that owns it)
+        const uint64_t *srow = a.synd + shot * a.synd_words;
+        uint32_t piv = 0u;
+        int pcol[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            pcol[i] = 0;
+            const int r = tid + WG * i;
+            if (r < M) {
+                for (int k = 0; k < W; ++k) mat[(size_t)k * M + r] = 0ull;
+                mat[(size_t)W * M + r] = (srow[r >> 6] >> (r & 63)) & 1ull;
+                for (int x = o.rptr[r]; x < o.rptr[r + 1]; ++x) {
+                    const int t = r1[o.ridx[x]];
+                    mat[(size_t)(t >> 6) * M + r] |= 1ull << (t & 63);
+                }
+            }
+        }
+
+        // ---- Gauss-Jordan, panel by panel
+        int rank = 0, par = 0;
+        for (int w = 0; w < W && rank < G::RANK; ++w) {
+            uint64_t cw[RPL], tr[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int r = tid + WG * i;
+                cw[i] = r < M ? mat[(size_t)w * M + r] : 0ull;
+                tr[i] = 0ull;
+            }
+            // columns of this word that some non-pivot row has (the others
+            // can take no pivot in it)
+            uint64_t any = 0ull;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) any |= ((piv >> i) & 1u) ? 0ull : cw[i];
+#pragma unroll
+            for (int sh = 1; sh < 64; sh <<= 1) {
+                const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)any, sh);
+                const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(any >> 32), sh);
+                any |= ((uint64_t)hi << 32) | lo;
+            }
+            if (NWAVE > 1) {
+                if (lane == 0) cmw[w & 1][wave] = any;
+                __syncthreads();
+#pragma unroll
+                for (int x = 0; x < NWAVE; ++x) any |= cmw[w & 1][x];
+            }
+            int np = 0;   // pivots found in this panel
+            for (uint64_t todo = any; todo && rank < G::RANK; todo &= todo - 1ull, par ^= 1) {
+                const int bb = __builtin_ctzll(todo);
+                // lowest-numbered non-pivot row with the bit (row tid + WG i)
+                int cand = 0x7fffffff;
+#pragma unroll
+                for (int i = RPL - 1; i >= 0; --i) {
+                    const uint64_t bal = __ballot(!((piv >> i) & 1u) && ((cw[i] >> bb) & 1ull));
+                    if (bal) cand = WG * i + 64 * wave + __builtin_ctzll(bal);
+                }
+                if (NWAVE > 1) {
+                    if (lane == 0) wmin[par][wave] = cand;
+                    __syncthreads();
+                }
+                int p = cand;
+                if (NWAVE > 1) {
+                    p = wmin[par][0];
+#pragma unroll
+                    for (int x = 1; x < NWAVE; ++x) p = min(p, wmin[par][x]);
+                }
+                if (p == 0x7fffffff) continue;   // the column depends on the ones before it
+                const int pi = p / WG;
+                if (tid == p - WG * pi) {
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i)
+                        if (i == pi) {
+                            pw[0] = cw[i];
+                            pw[1] = tr[i];
+                            pcol[i] = 64 * w + bb;
+                        }
+                    piv |= 1u << pi;
+                    prl[np] = p;
+                }
+                __syncthreads();
+                const uint64_t pcw = pw[0], ptr = pw[1] ^ (1ull << np);
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+                    if (tid + WG * i != p && ((cw[i] >> bb) & 1ull)) {
+                        cw[i] ^= pcw;
+                        tr[i] ^= ptr;
+                    }
+                ++np;
+                ++rank;
+            }
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int r = tid + WG * i;
+                if (r < M) mat[(size_t)w * M + r] = cw[i];
+            }
+            if (np == 0) continue;
+            // the other words (from w + 1 on; every word for the sweep),
+            // KC at a time
+            const int ng = (np + 7) / 8;
+            for (int k0 = CS ? 0 : w + 1; k0 < WS; k0 += KC) {
+                __syncthreads();   // the previous chunk's table reads are done
+                for (int x = tid; x < 64 * KC; x += WG) {
+                    const int j = x / KC, kk = x % KC, k = k0 + kk;
+                    P[j][kk] = (j < np && k < WS && k != w) ? mat[(size_t)k * M + prl[j]] : 0ull;
+                }
+                __syncthreads();
+                for (int x = tid; x < ng * 256 * KC; x += WG) {
+                    const int g = x / (256 * KC), c = (x / KC) & 255, kk = x % KC;
+                    uint64_t v = 0ull;
+#pragma unroll
+                    for (int bit = 0; bit < 8; ++bit) v ^= ((c >> bit) & 1) ? P[8 * g + bit][kk] : 0ull;
+                    r0[(g * 256 + c) * KC + kk] = v;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < RPL; ++i) {
+                    const int r = tid + WG * i;
+                    const uint64_t t = tr[i];
+                    if (r < M && t != 0ull)
+#pragma unroll
+                        for (int kk = 0; kk < KC; ++kk) {
+                            const int k = k0 + kk;
+                            if (k < WS && k != w) {
+                                uint64_t v = mat[(size_t)k * M + r];
+                                for (int g = 0; g < ng; ++g) v ^= r0[(g * 256 + (int)((t >> (8 * g)) & 255u)) * KC + kk];
+                                mat[(size_t)k * M + r] = v;
+                            }
+                        }
+                }
+            }
+        }
+
+        // ---- the estimate, or BP's when the syndrome is not reached
+        uint32_t sb = 0u;
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = tid + WG * i;
+            if (r < M) {
+                const uint32_t bit = (uint32_t)(mat[(size_t)W * M + r] & 1ull);
+                sb |= bit << i;
+                if (!((piv >> i) & 1u) && bit) bad = true;
+            }
+        }
+        if (bad) misc[1] = 1;
+        int ca = -1, cb = -1;   // non-pivot columns (rank positions) set by the sweep's choice
+        if constexpr (CS) {
+            const float *lp = a.lam_out + shot * a.n;
+            __syncthreads();   // r1 (qubit -> rank position) is no longer read
+            for (int t = tid; t < NQ; t += WG) r1[t] = osd_weight(lp[order[t]]);
+            for (int r = tid; r < M; r += WG) uarr[r] = 0;
+            if (tid == 0) misc[2] = 0;
+            if (tid < NPAIR) pairsum[tid] = 0;
+            __syncthreads();
+            int c0p = 0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+                if ((piv >> i) & 1u) {
+                    const int pc = pcol[i];
+                    atomicOr(&pbits[pc >> 5], 1u << (pc & 31));
+                    const int32_t qv = r1[pc];
+                    uarr[tid + WG * i] = ((sb >> i) & 1u) ? -qv : qv;
+                    c0p += ((sb >> i) & 1u) ? qv : 0;
+                }
+            atomicAdd(&misc[2], c0p);
+            __syncthreads();
+            const int32_t C0 = misc[2];
+            if (tid == 0) {
+                best = (unsigned long long)(uint32_t)C0 << 32;   // OSD-0 is candidate 0
+                int nt = 0;
+                for (int t = 0; t < NQ && nt < a.osd_order; ++t)
+                    if (!((pbits[t >> 5] >> (t & 31)) & 1u)) tl[nt++] = t;
+                misc[3] = nt;
+            }
+            __syncthreads();
+            const int nt = misc[3];
+            // pairs among the first nt non-pivot columns, in lexicographic order
+            for (int x = 0, pi = 0; x < nt; ++x)
+                for (int y = x + 1; y < nt; ++y, ++pi) {
+                    const int ta = tl[x], tb = tl[y];
+                    int part = 0;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i)
+                        if ((piv >> i) & 1u) {
+                            const int r = tid + WG * i;
+                            const uint64_t wa = mat[(size_t)(ta >> 6) * M + r], wb = mat[(size_t)(tb >> 6) * M + r];
+                            if (((wa >> (ta & 63)) ^ (wb >> (tb & 63))) & 1ull) part += uarr[r];
+                        }
+                    if (part) atomicAdd(&pairsum[pi], part);
+                }
+            // single flips: lane l of the wave handling word k owns column
+            // 64 k + l; the rows' words are read 64 rows at a time (one row
+            // per lane) and handed to every lane with readlane
+            unsigned long long mine = ~0ull;
+            for (int k = wave; k < W; k += NWAVE) {
+                int32_t acc = 0;
+                for (int rb = 0; rb < M; rb += 64) {
+                    const int r = rb + lane;
+                    const int32_t u = r < M ? uarr[r] : 0;
+                    if (__ballot(u != 0) == 0ull) continue;
+                    const uint64_t wd = u != 0 ? mat[(size_t)k * M + r] : 0ull;
+                    const int lo = (int)(uint32_t)wd, hi = (int)(uint32_t)(wd >> 32);
+#pragma unroll 8
+                    for (int j = 0; j < 64; ++j) {
+                        const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane(lo, j);
+                        const uint32_t wh = (uint32_t)__builtin_amdgcn_readlane(hi, j);
+                        const int32_t uj = __builtin_amdgcn_readlane(u, j);
+                        acc += (((lane < 32 ? wl : wh) >> (lane & 31)) & 1u) ? uj : 0;
+                    }
+                }
+                const int t = 64 * k + lane;
+                if (t < NQ && !((pbits[t >> 5] >> (t & 31)) & 1u)) {
+                    const uint32_t cost = (uint32_t)(C0 + r1[t] + acc);
+                    const unsigned long long key = ((unsigned long long)cost << 32) | (uint32_t)(t + 1);
+                    mine = key < mine ? key : mine;
+                }
+            }
+            __syncthreads();   // pair sums complete
+            if (tid < nt * (nt - 1) / 2) {
+                int x = 0, rr = tid;
+                while (rr >= nt - 1 - x) {
+                    rr -= nt - 1 - x;
+                    ++x;
+                }
+                const int ta = tl[x], tb = tl[x + 1 + rr];
+                const uint32_t cost = (uint32_t)(C0 + r1[ta] + r1[tb] + pairsum[tid]);
+                const unsigned long long key = ((unsigned long long)cost << 32) | (uint32_t)(NQ + 1 + tid);
+                mine = key < mine ? key : mine;
+            }
+            atomicMin(&best, mine);
+            __syncthreads();
+            const uint32_t idx = (uint32_t)best;
+            if (idx >= 1 && idx <= (uint32_t)NQ) {
+                ca = (int)idx - 1;
+            } else if (idx > (uint32_t)NQ) {
+                int x = 0, rr = (int)idx - NQ - 1;
+                while (rr >= nt - 1 - x) {
+                    rr -= nt - 1 - x;
+                    ++x;
+                }
+                ca = tl[x];
+                cb = tl[x + 1 + rr];
+            }
+            if (tid == 0 && ca >= 0) {
+                const int qa = order[ca];
+                atomicOr(&ebits[qa >> 5], 1u << (qa & 31));
+                if (cb >= 0) {
+                    const int qb = order[cb];
+                    atomicOr(&ebits[qb >> 5], 1u << (qb & 31));
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i)
+            if ((piv >> i) & 1u) {
+                const int r = tid + WG * i;
+                uint32_t bit = (sb >> i) & 1u;
+                if (CS && ca >= 0) {
+                    bit ^= (uint32_t)((mat[(size_t)(ca >> 6) * M + r] >> (ca & 63)) & 1ull);
+                    if (cb >= 0) bit ^= (uint32_t)((mat[(size_t)(cb >> 6) * M + r] >> (cb & 63)) & 1ull);
+                }
+                if (bit) {
+                    const int q = order[pcol[i]];
+                    atomicOr(&ebits[q >> 5], 1u << (q & 31));
+                }
+            }
+        __syncthreads();
+        if (misc[1] == 0) {
+            if (a.ehat) {
+                constexpr int EW32 = (NQ + 31) / 32;
+                for (int wd = tid; wd < a.ehat_words; wd += WG) {
+                    const uint64_t lo = (2 * wd < EW32) ? ebits[2 * wd] : 0u;
+                    const uint64_t hi = (2 * wd + 1 < EW32) ? ebits[2 * wd + 1] : 0u;
+                    a.ehat[shot * a.ehat_words + wd] = lo | (hi << 32);
+                }
+            }
+            if (tid == 0) stats[shot].converged = 2;
+        }
+        __syncthreads();   // LDS and misc are reused by the next shot
+    }
+}
+
 }  // namespace lead_spec

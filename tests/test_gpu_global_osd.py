@@ -86,8 +86,9 @@ def test_global_osd_paths_identical_and_limits():
     lam = np.full(400, 2.75, dtype=np.float32)
     runs = {}
     for key, sched in (("f2", dict(specialized=2)), ("f1", dict(specialized=1)), ("pre", dict(specialized=0)),
-                       ("fused", dict(specialized=0, fused=1))):
+                       ("fused", dict(specialized=0, fused=1)), ("big", dict(specialized=2, global_osd_form=2))):
         dec.set_schedule(**sched)
+        assert dec.get_schedule()["global_osd_form"] == (2 if key == "big" else 1)
         runs[key] = run_gpu(dec, s, lam, 0, lam=True)
     ref = runs["f2"]
     assert (ref["stats"][:, 0] == 2).any()
@@ -134,8 +135,8 @@ def test_global_osd_paths_identical_and_limits():
         dec.decode(st, pr, plain=True)
     with pytest.raises(P.LeadError, match="UNSUPPORTED"):
         gpu_decoder(spec, global_post=1, stage=1)
-    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
-        gpu_decoder(standard("L"), global_post=1, max_shots=64)
+    with pytest.raises(P.LeadError, match="ARG"):
+        dec.set_schedule(global_osd_form=3)
 
 
 @pytest.mark.parametrize("name,t,p,T,order", [("T", 0, 0.08, 8, 3), ("T", 1, 0.06, 12, 3), ("M", 0, 0.06, 8, 3),
@@ -187,7 +188,7 @@ def test_global_osd_cs_forms_identical_and_limits():
     lam = np.full(300, 2.75, dtype=np.float32)
     runs = {}
     for key, sched in (("f2", dict(specialized=2)), ("f1", dict(specialized=1)), ("pre", dict(specialized=0)),
-                       ("fused", dict(specialized=0, fused=1))):
+                       ("fused", dict(specialized=0, fused=1)), ("big", dict(specialized=2, global_osd_form=2))):
         dec.set_schedule(**sched)
         runs[key] = run_gpu(dec, s, lam, 0, lam=key != "pre")
     for key, r in runs.items():
@@ -197,3 +198,55 @@ def test_global_osd_cs_forms_identical_and_limits():
         gpu_decoder(spec, global_post=1, osd_order=9)
     with pytest.raises(P.LeadError, match="ARG"):
         gpu_decoder(spec, osd_order=3)
+
+
+@pytest.mark.parametrize("name,t,order,stage", [("T", 0, 0, 0), ("T", 1, 3, 0), ("M", 0, 0, 0), ("M", 0, 3, 0),
+                                                ("M", 0, 3, GLOBAL), ("M", 1, 8, 0)])
+def test_global_osd_matrix_in_memory_identical(name, t, order, stage):
+    """The global OSD kernel with [H_t | s] in device memory (persistent
+    workgroups, panel elimination) gives the bits of the kernel with the
+    rows in registers, for OSD-0 and the combination sweep, in LEAD and after
+    global BP alone."""
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=10, max_iter_global=10, global_post=1, osd_order=order,
+                            stage=stage, max_shots=1024)
+    e, _, _ = bitflip_inputs(oc, 700, 0.06, seed=11, t=t)
+    s = _gpu_syndrome(dec, e)
+    lam = np.full(700, 2.75, dtype=np.float32)
+    dec.set_schedule(global_osd_form=1)
+    reg = run_gpu(dec, s, lam, 0, lam=True)
+    dec.set_schedule(global_osd_form=2)
+    big = run_gpu(dec, s, lam, 0, lam=True)
+    n2 = int((reg["stats"][:, 0] == 2).sum())
+    log(f"[global-osd-hbm] {name} t={t} order={order} stage={stage}: {n2} of 700 shots resolved by OSD")
+    assert n2 > 0
+    for k in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(reg[k], big[k]), k
+
+
+@pytest.mark.parametrize("t,order", [(0, 0), (1, 0), (0, 3), (1, 3)])
+def test_global_osd_psl27_matches_oracle(t, order):
+    """PSL(2,7) (m = 2688, n = 5376): global OSD-0 and OSD-CS of order 3 with
+    the matrix in device memory, against the oracle, with caps short enough
+    for the shots to stay well-conditioned (3 + 3 rounds, depolarising
+    p = 0.03 with the marginal prior 2p/3)."""
+    from lead_inputs import channel_llr, depolarizing_packed
+    spec, oc = code_pair("L")
+    shots, p, T = 24, 0.03, 3
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=T, max_iter_global=T, global_post=1, osd_order=order,
+                            max_shots=shots)
+    assert dec.get_schedule()["global_osd_form"] == 2
+    xs, zs = depolarizing_packed(shots, oc.n, p, seed=131)
+    e = xs if t == 0 else zs
+    s = _gpu_syndrome(dec, e)
+    assert np.array_equal(s, oc.syndrome(e, t))
+    lam = np.full(shots, float(channel_llr(2 * p / 3)), dtype=np.float32)
+    g = run_gpu(dec, s, lam, 0, lam=True)
+    orc = oracle_decode_conditioned(oc, s, lam, t=t, k=2, max_iter_local=T, max_iter_global=T, global_osd=1,
+                                    osd_order=order)
+    res = compare(orc, g, oc.n)
+    n_osd = _check_osd_shots(orc, g, oc.n, oc.H(t), s)
+    log(f"[global-osd] L t={t} order={order}: {res['bad']} differ, {res['tie']} ill-conditioned, OSD-resolved "
+        f"{int((orc['stats'][:, 0] == 2).sum())} ({n_osd} well-conditioned), worst ok |dLLR| {res['worst_ok']:.2e}")
+    assert not res["unexplained"], res["detail"]
+    assert n_osd >= shots // 2
