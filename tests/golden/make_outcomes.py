@@ -15,7 +15,14 @@ reached H e = s), logical failure (not converged, or the residual e + e_hat
 is a non-trivial logical), global iterations and the sum of local
 iterations.  Arrays are stored zlib-compressed and base64-encoded.
 
-Usage: python tests/golden/make_outcomes.py [--procs P] [--only NAME ...]
+With --perturbed the same shots are decoded once more by the oracle with
+every computed value multiplied by 1 + eps*xi (eps = 2.4e-7, a few FP32 ulps;
+xi uniform in [-1, 1) from the oracle's seeded stream, seed 1), and the
+outcomes are added to each part under "perturbed": a second correct
+implementation whose rounding differs, which calibrates how far two correct
+decoders drift apart shot by shot where min-sum is ill-conditioned.
+
+Usage: python tests/golden/make_outcomes.py [--procs P] [--only NAME ...] [--perturbed]
 """
 from __future__ import annotations
 
@@ -37,6 +44,8 @@ from lead_inputs import standard, bitflip_packed, depolarizing_packed, channel_l
 
 SHOTS = 10000
 SHARD = 250
+PERTURB = 2.4e-7
+PERTURB_SEED = 1
 
 # name -> (code, noise, p, rounds, seed)
 POINTS = {
@@ -67,7 +76,7 @@ def point_inputs(name, shots=SHOTS):
 
 
 def _shard(args):
-    name, t, s0, s1 = args
+    name, t, s0, s1, pert = args
     from oracle import oracle as O
     code, noise, p, T, seed = POINTS[name]
     # the draws are sequential per shot, so the first s1 shots of a smaller
@@ -76,8 +85,9 @@ def _shard(args):
     e = dict(parts)[t][s0:s1]
     oc = O.OracleCode.from_spec(spec)
     s = oc.syndrome(e, t)
+    kw = dict(perturb=PERTURB, perturb_seed=PERTURB_SEED) if pert else {}
     o = oc.decode(s, lam[s0:s1].astype(np.float64), t=t,
-                  p=O.params(max_iter_local=T, max_iter_global=T))
+                  p=O.params(max_iter_local=T, max_iter_global=T, **kw))
     conv = o["stats"][:, 0] != 0
     fail = ~conv | oc.logical_failure(o["ehat"] ^ e, t)
     return name, t, s0, conv, fail, o["stats"][:, 1].copy(), o["stats"][:, 2].copy()
@@ -101,17 +111,26 @@ def load(name):
     with open(path_of(name)) as f:
         d = json.load(f)
     for part in d["parts"]:
-        part["conv"] = dec(part["conv"], np.uint8).astype(bool)
-        part["fail"] = dec(part["fail"], np.uint8).astype(bool)
-        part["iters_g"] = dec(part["iters_g"], np.uint8).astype(np.int64)
-        part["iters_l_sum"] = dec(part["iters_l_sum"], np.uint16).astype(np.int64)
+        for x in [part] + ([part["perturbed"]] if "perturbed" in part else []):
+            x["conv"] = dec(x["conv"], np.uint8).astype(bool)
+            x["fail"] = dec(x["fail"], np.uint8).astype(bool)
+            x["iters_g"] = dec(x["iters_g"], np.uint8).astype(np.int64)
+            x["iters_l_sum"] = dec(x["iters_l_sum"], np.uint16).astype(np.int64)
     return d
+
+
+def _arrays(conv, fail, ig, il):
+    assert ig.max() <= 255 and il.max() < 65536
+    return dict(conv=enc(conv.astype(np.uint8)), fail=enc(fail.astype(np.uint8)), iters_g=enc(ig.astype(np.uint8)),
+                iters_l_sum=enc(il.astype(np.uint16)),
+                summary=dict(converged=float(conv.mean()), failure=float(fail.mean()), mean_iters_g=float(ig.mean())))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--procs", type=int, default=os.cpu_count() or 1)
     ap.add_argument("--only", nargs="*")
+    ap.add_argument("--perturbed", action="store_true")
     args = ap.parse_args()
     names = args.only or list(POINTS)
     jobs = []
@@ -119,7 +138,7 @@ def main():
         nparts = 1 if POINTS[name][1] == "bitflip" else 2
         for t in range(nparts):
             for s0 in range(0, SHOTS, SHARD):
-                jobs.append((name, t, s0, min(SHOTS, s0 + SHARD)))
+                jobs.append((name, t, s0, min(SHOTS, s0 + SHARD), args.perturbed))
     res = {}
     t0 = time.time()
     with ProcessPoolExecutor(args.procs) as ex:
@@ -130,16 +149,23 @@ def main():
     for name in names:
         code, noise, p, T, seed = POINTS[name]
         nparts = 1 if noise == "bitflip" else 2
+        if args.perturbed:
+            with open(path_of(name)) as f:
+                out = json.load(f)
+            for t in range(nparts):
+                cols = [res[(name, t, s0)] for s0 in range(0, SHOTS, SHARD)]
+                arr = _arrays(*(np.concatenate([c[i] for c in cols]) for i in range(4)))
+                arr.update(perturb=PERTURB, perturb_seed=PERTURB_SEED)
+                out["parts"][t]["perturbed"] = arr
+            with open(path_of(name), "w") as f:
+                json.dump(out, f, indent=1)
+            print(name, "perturbed", [pt["perturbed"]["summary"] for pt in out["parts"]], flush=True)
+            continue
         parts = []
         for t in range(nparts):
             cols = [res[(name, t, s0)] for s0 in range(0, SHOTS, SHARD)]
-            conv, fail, ig, il = (np.concatenate([c[i] for c in cols]) for i in range(4))
-            assert ig.max() <= 255 and il.max() < 65536
             parts.append(dict(check_type=t, errors="X" if t == 0 else "Z",
-                              conv=enc(conv.astype(np.uint8)), fail=enc(fail.astype(np.uint8)),
-                              iters_g=enc(ig.astype(np.uint8)), iters_l_sum=enc(il.astype(np.uint16)),
-                              summary=dict(converged=float(conv.mean()), failure=float(fail.mean()),
-                                           mean_iters_g=float(ig.mean()))))
+                              **_arrays(*(np.concatenate([c[i] for c in cols]) for i in range(4)))))
         out = dict(point=name, code=code, noise=noise, p=p, max_iter_local=T, max_iter_global=T, seed=seed,
                    shots=SHOTS, ms_scale=0.75, alpha=1.0, prior="ln((1-q)/q) in float32, q = p (bit flips) "
                    "or 2p/3 (depolarising)", writer="tests/golden/make_outcomes.py (oracle only)", parts=parts)

@@ -20,12 +20,14 @@ def test_stored_outcomes_consistent(point):
     assert (ref["code"], ref["noise"], ref["p"], ref["max_iter_global"], ref["seed"]) == (code, noise, p, T, seed)
     assert len(ref["parts"]) == (1 if noise == "bitflip" else 2)
     for part in ref["parts"]:
-        conv, fail, ig = part["conv"], part["fail"], part["iters_g"]
-        assert conv.size == fail.size == ig.size == part["iters_l_sum"].size == G.SHOTS
-        assert np.all(fail[~conv]), "a shot that does not converge is a failure"
-        assert np.all(ig[~conv] == T), "a run that does not converge reports the cap"
-        assert np.all((ig >= 1) & (ig <= T))
-        assert abs(part["summary"]["failure"] - fail.mean()) < 1e-12
+        assert part["perturbed"]["perturb"] == G.PERTURB
+        for x in (part, part["perturbed"]):
+            conv, fail, ig = x["conv"], x["fail"], x["iters_g"]
+            assert conv.size == fail.size == ig.size == x["iters_l_sum"].size == G.SHOTS
+            assert np.all(fail[~conv]), "a shot that does not converge is a failure"
+            assert np.all(ig[~conv] == T), "a run that does not converge reports the cap"
+            assert np.all((ig >= 1) & (ig <= T))
+            assert abs(x["summary"]["failure"] - fail.mean()) < 1e-12
 
 
 @pytest.mark.parametrize("point", list(G.POINTS))
