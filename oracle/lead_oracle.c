@@ -529,12 +529,16 @@ static int bp_run(const tanner *t, const uint8_t *s, const double *lam, const or
                     }
                     out = p->ms_scale * (neg ? -mn : mn);
                 } else {
-                    double prod = s[c] ? -1.0 : 1.0;
+                    /* in extended precision: near saturation the product is
+                     * 1 - O(e^-|mu|) (1 - 2e-13 at |mu| = 30), and in double
+                     * its distance from 1, which sets the message, would keep
+                     * only three or four digits (message errors up to 6e-4) */
+                    long double prod = s[c] ? -1.0L : 1.0L;
                     for (int y = t->row_ptr[c]; y < t->row_ptr[c + 1]; y++) {
                         if (y == x) continue;
-                        prod *= tanh(w->mu[y] / 2.0);
+                        prod *= tanhl((long double)w->mu[y] / 2.0L);
                     }
-                    out = 2.0 * atanh(prod);
+                    out = (double)(2.0L * atanhl(prod));
                 }
                 w->msg[x] = perturbed(out, p->perturb, &w->rng);
             }

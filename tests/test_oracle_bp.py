@@ -432,3 +432,26 @@ def test_global_bp_zero_syndrome_closed_form(name):
         assert np.array_equal(out["stats"], [[1, 1], [1, 1]])
         assert np.allclose(out["post"], lam * (1 + 0.75 * deg), rtol=1e-12)
         assert not out["ehat"].any()
+
+
+@pytest.mark.parametrize("mus", [(30.0, 30.0), (30.0, 25.0, 28.0), (12.0, 30.0, 30.0, 30.0, 29.5), (0.7, 30.0)])
+def test_sum_product_message_at_saturation(mus):
+    """One check: the sum-product message to a variable equals
+    phi(sum phi(|mu|)) over the other edges, phi(x) = log1p(2 / expm1(x)) (the
+    tanh rule's log-domain form, well-conditioned in double), to 1e-6 even
+    where every |mu| sits at the clamp and 1 - prod tanh(mu/2) ~ 1e-12 (the
+    oracle's extended-precision product resolves that distance to ~3e-7
+    relative; a double-precision product would miss the message by ~3e-4)."""
+    import math
+    from oracle import oracle as O
+
+    def phi(x):
+        return math.log1p(2.0 / math.expm1(x))
+
+    k = len(mus) + 1
+    H = np.ones((1, k), dtype=np.uint8)
+    lam = np.array([5.0] + list(mus))
+    L, e, conv, it = O.bp(H, np.zeros(1, np.uint8), lam, 1,
+                          O.params(bp=O.SUMPRODUCT, llr_clamp=1000.0, early_exit=0))
+    want = phi(sum(phi(abs(m)) for m in mus))
+    assert abs((L[0] - lam[0]) - want) <= 1e-6, (L[0] - lam[0], want)
