@@ -111,7 +111,7 @@ lead_status lead_code_get_views(const lead_code *code, lead_check_type t, int32_
  * directory $LEAD_JIT_CACHE, "off" to disable, else _build/jit beside the
  * library; a later process with the same compiler, library headers and code
  * loads them instead of compiling) (the min-sum forms,
- * and the sum-product form where views have at most 128 local edges);
+ * and the sum-product form where views have at most 192 local edges);
  * lead_decoder_create does the same on first use and then loads them.  LEAD_E_UNSUPPORTED (with the
  * reason in lead_last_error) when the code has no position map or the
  * run-time compiler is unavailable; decoders then use the precompiled
@@ -150,7 +150,7 @@ typedef struct {
                                  only (not plain, not stage GLOBAL).  0: none */
     int32_t bp;               /* lead_bp.  Sum-product runs on the kernels
                                  compiled for the code with one register per
-                                 message (views of at most 128 local edges),
+                                 message (views of at most 192 local edges),
                                  in lead_decode, batches and the server,
                                  stage GLOBAL included; lead_decode_plain is
                                  min-sum only (LEAD_E_UNSUPPORTED)            */

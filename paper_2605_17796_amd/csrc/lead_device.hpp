@@ -49,13 +49,26 @@ __device__ __forceinline__ float aggregate_llr(float La, float Lb, float alpha, 
     return clampf(l2 * 0.693147180559945309f, clampv) + 0.f;
 }
 
+// e^x to about two ulps: x log2(e) is formed as hi + lo (log2(e) split into
+// a float and its remainder, the product's rounding error recovered with an
+// fma), and 2^(hi + lo) = 2^hi (1 + lo ln 2) since |lo| < 2^-18.  exp_hw's
+// single rounding of x log2(e) costs up to |x| log2(e) 2^-24 of relative
+// error in e^x (about 20 ulps at x = 20).
+__device__ __forceinline__ float exp_acc(float x) {
+    constexpr float L1 = 1.44269502162933349609375f;      // log2(e) rounded to float
+    constexpr float L2 = 1.925963033500011079e-8f;         // log2(e) - L1
+    const float hi = x * L1;
+    const float lo = __builtin_fmaf(x, L1, -hi) + x * L2;
+    return __builtin_amdgcn_exp2f(hi) * __builtin_fmaf(lo, 0.693147180559945309f, 1.f);
+}
+
 // Sum-product in the log domain (Gallager's phi):
 //   phi(x) = ln((e^x + 1) / (e^x - 1)) = -ln tanh(x / 2) = log1p(2 / expm1(x)),  x >= 0,
 // its own inverse, with phi(0) = +inf and phi(+inf) = 0; the check message
 // 2 atanh(prod_j' tanh(mu_j' / 2)) has magnitude phi(sum_j' phi(|mu_j'|)).
 // expm1 and log1p take a short series where the plain form would cancel, so
 // phi keeps full relative precision at both ends (phi(30) ~ 1.9e-13 and
-// phi(1e-6) ~ 14.5).
+// phi(1e-6) ~ 14.5), and a correction of the rounding of 1 + y elsewhere.
 __device__ __forceinline__ float expm1_nonneg(float x) {
     // x (1 + x/2 (1 + x/3 (... (1 + x/8)))) below 1/2: truncation below 1e-8 relative
     float t = __builtin_fmaf(x, 0.125f, 1.f);
@@ -66,7 +79,7 @@ __device__ __forceinline__ float expm1_nonneg(float x) {
     t = __builtin_fmaf(x * (1.f / 3.f), t, 1.f);
     t = __builtin_fmaf(x * 0.5f, t, 1.f);
     const float series = x * t;
-    return x < 0.5f ? series : exp_hw(x) - 1.f;
+    return x < 0.5f ? series : exp_acc(x) - 1.f;
 }
 
 __device__ __forceinline__ float log1p_nonneg(float y) {
@@ -76,7 +89,12 @@ __device__ __forceinline__ float log1p_nonneg(float y) {
     t = __builtin_fmaf(y, t, -0.5f);
     t = __builtin_fmaf(y, t, 1.f);
     const float series = y * t;
-    return y < 0.03125f ? series : __builtin_amdgcn_logf(1.f + y) * 0.693147180559945309f;
+    // ln(u) for u = fl(1 + y), times y / (u - 1) to undo the rounding of
+    // 1 + y (u - 1 is exact below 2); above 1 that rounding is harmless
+    const float u = 1.f + y;
+    const float lg = __builtin_amdgcn_logf(u) * 0.693147180559945309f;
+    const float corr = y < 1.f ? y / (u - 1.f) : 1.f;
+    return y < 0.03125f ? series : lg * corr;
 }
 
 __device__ __forceinline__ float phi(float x) {

@@ -287,9 +287,12 @@ std::string source(const Code &c, int t, bool sp) {
               << ">(a, w); }\n";
         // at least two waves per SIMD for the per-shot kernel (its rounds
         // wait on the partner exchange, which a lone wave cannot hide); the
-        // compressed form within one wave keeps the whole register file
+        // compressed form within one wave keeps the whole register file, and
+        // so does sum-product on views above kTwoWaveMaxEdges edges (one
+        // register per message and no compressed alternative)
+        const bool whole_file = (form == kCompressed && wg == 64) || (form == kSumProduct && tt.eloc > kTwoWaveMaxEdges);
         o << "extern \"C\" __global__ void __launch_bounds__(" << wg
-          << (form == kCompressed && wg == 64 ? "" : ", 2")
+          << (whole_file ? "" : ", 2")
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";

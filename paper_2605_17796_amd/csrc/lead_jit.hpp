@@ -27,7 +27,7 @@ constexpr int kForms = 3;
 // min-sum form (one VGPR per message), and at most kSumProductMaxEdges the
 // sum-product form.
 constexpr int kExplicitMaxEdges = 192;
-constexpr int kSumProductMaxEdges = 128;
+constexpr int kSumProductMaxEdges = 192;
 // Up to this many edges the explicit forms' per-shot kernel keeps one
 // register per message; above it, the min-sum per-shot kernel keeps the
 // compressed state on the checks of highest degree, leaving at most
