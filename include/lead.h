@@ -264,11 +264,17 @@ lead_status lead_decode_noalloc(lead_decoder *dec, int64_t shots, const uint64_t
                                 const float *d_prior, lead_prior_mode mode, uint64_t *d_ehat, int64_t ehat_words,
                                 float *d_post, float *d_prior_llr, lead_shot_stats *d_stats, void *stream);
 
-/* The same decode as a plain sequence of launches: one launch for Phases 1-2
- * (lambda' written to HBM), then one launch per global BP round with the
- * message state in HBM, and a host-visible convergence count after every
- * round (the call synchronises `stream` once per round).  Outputs are
- * identical to lead_decode's. */
+/* The same decode as a plain sequence of launches: the Phase 1 launch, then
+ * one launch per global BP round (Phases 2-3 of that round, the per-view sums
+ * and check state kept in device memory between launches; the first round
+ * also forms lambda'), a host-visible count of shots still running after
+ * every round (the call synchronises `stream` once per round), and a last
+ * launch ending the shots that ran to the cap.  On the kernels compiled for
+ * the code (the default schedule) every parameter is supported, sum-product
+ * and OSD included; with the precompiled kernels (specialized = 0) min-sum
+ * without OSD only (LEAD_E_UNSUPPORTED otherwise).  The per-round state is
+ * allocated on first use (about 31 KB per A5 shot, for min(max_shots,
+ * workspace) shots).  Outputs are identical to lead_decode's. */
 lead_status lead_decode_plain(lead_decoder *dec, int64_t shots, const uint64_t *d_synd, int64_t synd_words,
                               const float *d_prior, lead_prior_mode mode, uint64_t *d_ehat,
                               int64_t ehat_words, float *d_post, float *d_prior_llr,

@@ -66,9 +66,15 @@ struct lead_decoder {
     bool timing = false;
     std::vector<std::array<hipEvent_t, 3>> tev;
     lead_phase_times tsum{};
-    // per-round state of lead_decode_plain (allocated on first use)
+    // per-round state of lead_decode_plain (allocated on first use): the
+    // precompiled round kernel's, and the compiled round kernels' (sums,
+    // check state, ended flags for plain_shots shots, running-shot count)
     float *d_S = nullptr, *d_cst = nullptr, *d_lamp = nullptr;
     int32_t *d_status = nullptr, *d_active = nullptr, *h_active = nullptr;
+    float *d_pS = nullptr, *d_pst = nullptr;
+    int32_t *d_pended = nullptr;
+    int64_t *d_pactive = nullptr;
+    int64_t plain_shots = 0;
 };
 
 namespace {
@@ -199,6 +205,16 @@ int spec_form(const lead_decoder *d, int want) {
     return d->spec->best_form();
 }
 
+// LDS bytes of the Phases 2-3 kernel compiled for the code (form f + 1).
+size_t spec_global_lds(const lead_decoder *d, int f) {
+    const lead::jit::Kernels &k = *d->spec;
+    const int D2 = d->D * d->D, ew32 = (d->n + 31) / 32;
+    const bool lam_in_lds = f + 1 == lead::jit::kCompressed || (f + 1 == lead::jit::kExplicit && k.hybrid);
+    const size_t lam_lds = lam_in_lds ? sizeof(float) * (size_t)k.lam_slots * k.wg : 0;
+    return (k.bperm ? 0 : sizeof(float) * (size_t)D2 * k.wg) + lam_lds + sizeof(int) * (size_t)k.spw * 9 +
+           sizeof(uint32_t) * (size_t)k.spw * ew32;   // 9: the kernel's per-shot flag stride
+}
+
 // Split-path launches with the kernels compiled for the decoder's code.
 hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArgs w, hipStream_t s,
                        std::array<hipEvent_t, 3> *ev) {
@@ -224,11 +240,7 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
     if (e != hipSuccess) return e;
     a.spw = k.spw;
     lead::SpecArgs x{d->d_pv, d->d_fown};
-    const int D2 = d->D * d->D, ew32 = (d->n + 31) / 32;
-    const bool lam_in_lds = f + 1 == lead::jit::kCompressed || (f + 1 == lead::jit::kExplicit && k.hybrid);
-    const size_t lam_lds = lam_in_lds ? sizeof(float) * (size_t)k.lam_slots * k.wg : 0;
-    const size_t lds = (k.bperm ? 0 : sizeof(float) * (size_t)D2 * k.wg) + lam_lds + sizeof(int) * (size_t)k.spw * 9 +
-                       sizeof(uint32_t) * (size_t)k.spw * ew32;   // 9: the kernel's per-shot flag stride
+    const size_t lds = spec_global_lds(d, f);
     const int64_t grid = (a.shots + k.spw - 1) / k.spw;
     void *gargs[] = {&a, &w, &x};
     e = hipModuleLaunchKernel(k.global[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
@@ -275,10 +287,17 @@ void free_plain(lead_decoder *d) {
     (void)hipFree(d->d_lamp);
     (void)hipFree(d->d_status);
     (void)hipFree(d->d_active);
+    (void)hipFree(d->d_pS);
+    (void)hipFree(d->d_pst);
+    (void)hipFree(d->d_pended);
+    (void)hipFree(d->d_pactive);
     if (d->h_active) (void)hipHostFree(d->h_active);
-    d->d_S = d->d_cst = d->d_lamp = nullptr;
-    d->d_status = d->d_active = d->h_active = nullptr;
+    d->d_S = d->d_cst = d->d_lamp = d->d_pS = d->d_pst = nullptr;
+    d->d_status = d->d_active = d->h_active = d->d_pended = nullptr;
+    d->d_pactive = nullptr;
+    d->plain_shots = 0;
 }
+
 
 lead::DecodeArgs base_args(const lead_decoder *d) {
     lead::DecodeArgs a{};
@@ -917,15 +936,120 @@ lead_status lead_decode_noalloc(lead_decoder *d, int64_t shots, const uint64_t *
     return LEAD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The plain form on the kernels compiled for the code: per chunk of the
+// workspace, Phase 1 exactly as in lead_decode, then one launch of the
+// compiled round kernel per global round (Phases 2-3 of that round, the
+// sums and check state restored from and saved to device memory), the count
+// of shots still running copied to pinned host memory and the stream
+// synchronised after every round, and a last launch ending the shots that
+// ran to the cap; then the global OSD if asked for.  Outputs are those of
+// lead_decode bit for bit (same arithmetic in the same order).
+hipError_t plain_spec(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words, const float *prior,
+                      lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words, float *post, float *lam,
+                      lead_shot_stats *stats, hipStream_t s) {
+    const lead::jit::Kernels &k = *d->spec;
+    const int f = d->sched.specialized - 1;
+    const int D2 = d->D * d->D;
+    hipError_t e = hipSuccess;
+    if (!d->d_pS) {
+        const int64_t ps = std::max<int64_t>(1, std::min<int64_t>(d->max_shots, d->ws_shots));
+        const size_t words = (size_t)lead::jit::plain_state_words(*d->code, d->type);
+        e = hipMalloc(&d->d_pS, sizeof(float) * (size_t)ps * D2 * d->N);
+        if (e == hipSuccess) e = hipMalloc(&d->d_pst, sizeof(float) * (size_t)ps * words * d->N);
+        if (e == hipSuccess) e = hipMalloc(&d->d_pended, sizeof(int32_t) * (size_t)ps);
+        if (e == hipSuccess) e = hipMalloc(&d->d_pactive, sizeof(int64_t));
+        if (e == hipSuccess && !d->h_active) e = hipHostMalloc(&d->h_active, sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        d->plain_shots = ps;
+    }
+    const bool gonly = d->params.stage == LEAD_STAGE_GLOBAL;
+    const bool gpost = d->params.global_post != 0;
+    const Workspace ws = decoder_workspace(d);
+    const int64_t cap = std::min<int64_t>(ws.shots, d->plain_shots);
+    const int64_t chunk = d->sched.chunk_shots > 0 ? std::min<int64_t>(d->sched.chunk_shots, cap) : cap;
+    const int64_t nchunks = (shots + chunk - 1) / chunk;
+    const int64_t step = (shots + nchunks - 1) / nchunks;
+    const size_t lds = spec_global_lds(d, f);
+    for (int64_t off = 0; off < shots; off += step) {
+        const int64_t cnt = std::min(step, shots - off);
+        lead::DecodeArgs a = base_args(d);
+        a.synd = synd + off * synd_words;
+        a.synd_words = synd_words;
+        a.prior = prior + (mode == LEAD_PRIOR_PER_SHOT ? off : mode == LEAD_PRIOR_FULL ? off * d->n : 0);
+        a.prior_mode = mode;
+        a.ehat = ehat ? ehat + off * ehat_words : nullptr;
+        a.ehat_words = ehat_words;
+        a.post = post ? post + off * d->n : nullptr;
+        a.lam_out = lam ? lam + off * d->n : nullptr;
+        a.stats = stats ? stats + off : nullptr;
+        a.shots = cnt;
+        a.stage = LEAD_STAGE_FULL;
+        a.global_only = gonly ? 1 : 0;
+        if (gpost) {
+            if (!a.post) a.post = ws.gpost;
+            if (!a.stats) a.stats = ws.gstats;
+            if (!a.lam_out && d->params.osd_order > 0) a.lam_out = ws.glam;   // the sweep's costs
+        }
+        lead::LocalArgs w = local_args(d, ws, cnt, mode);
+        if (!gonly) {
+            if ((e = lead::launch_reset_counter(w.counter, s)) != hipSuccess) return e;
+            void *largs[] = {&a, &w};
+            e = hipModuleLaunchKernel(k.local[f][mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1, 64, 1,
+                                      1, 0, s, largs, nullptr);
+            if (e == hipSuccess && a.local_osd)
+                e = hipModuleLaunchKernel(k.local_osd, (unsigned)(8 * d->cus), 1, 1, 64, 1, 1, 0, s, largs, nullptr);
+            if (e != hipSuccess) return e;
+        }
+        a.spw = k.spw;
+        lead::SpecArgs x{d->d_pv, d->d_fown};
+        lead::PlainArgs pl{d->d_pS, d->d_pst, d->d_pended, reinterpret_cast<int32_t *>(d->d_pactive), 0};
+        const int64_t grid = (cnt + k.spw - 1) / k.spw;
+        bool running = true;
+        for (int t = 1; t <= d->params.max_iter_global + 1 && running; ++t) {
+            if ((e = lead::launch_clear_i64(d->d_pactive, 1, s)) != hipSuccess) return e;
+            pl.round = t;
+            void *rargs[] = {&a, &w, &x, &pl};
+            e = hipModuleLaunchKernel(k.round[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, rargs,
+                                      nullptr);
+            if (e != hipSuccess) return e;
+            if (t <= d->params.max_iter_global) {
+                // the host-visible count of shots still running
+                e = hipMemcpyAsync(d->h_active, d->d_pactive, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return e;
+                running = *d->h_active != 0;
+            }
+        }
+        if (gpost && (e = launch_osd(d, a, ws, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
 lead_status lead_decode_plain(lead_decoder *d, int64_t shots, const uint64_t *synd, int64_t synd_words,
                               const float *prior, lead_prior_mode mode, uint64_t *ehat, int64_t ehat_words,
                               float *post, float *lam, lead_shot_stats *stats, void *stream) {
     lead_status st = check_decode_args(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, lam);
     if (st != LEAD_OK || shots == 0) return st;
-    if (needs_spec(d) || d->params.global_post)
-        return fail(LEAD_E_UNSUPPORTED, "the plain form runs min-sum without OSD-0 only");
     if (d->params.stage == LEAD_STAGE_LOCAL)
         return lead_decode(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats, stream);
+    if (use_spec(d) && d->spec->round[d->sched.specialized - 1]) {
+        hipError_t e = plain_spec(d, shots, synd, synd_words, prior, mode, ehat, ehat_words, post, lam, stats,
+                                  (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "plain-form launch");
+        return LEAD_OK;
+    }
+    // precompiled kernels (the schedule asks for them, or the code has none
+    // compiled): min-sum without OSD
+    if (needs_spec(d) || d->params.global_post)
+        return fail(LEAD_E_UNSUPPORTED, "the plain form on the precompiled kernels runs min-sum without OSD only");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     const int D2 = d->D * d->D;
@@ -1134,7 +1258,7 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
     }
     d->sched = win;
     d->spw = win.shots_per_workgroup;
-    if (best) *best = win;
+    if (best) (void)lead_decoder_get_schedule(d, best);   // as get_schedule reports it
     return LEAD_OK;
 }
 

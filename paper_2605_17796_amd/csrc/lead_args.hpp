@@ -75,6 +75,21 @@ struct OsdArgs {
     const int32_t *ridx;
 };
 
+// State of the plain per-round form of the Phases 2-3 kernel compiled for a
+// code: one launch per global round, the per-view sums and check state kept
+// in device memory between launches ([shot][word][view] floats, so a wave's
+// accesses coalesce), a per-shot flag set when the shot's run has ended, and
+// a count of the shots still running after the round (read by the host).
+// round = 1 .. Tg runs that round; round = Tg + 1 ends the shots that ran to
+// the cap.
+struct PlainArgs {
+    float *S;                  // [shot][D2][N] variable sums
+    float *st;                 // [shot][words][N] check state
+    int32_t *ended;            // [shot] 1 once the shot's outputs are written
+    int32_t *active;           // shots still running after this round
+    int32_t round;
+};
+
 // Workspace of the global OSD kernel that keeps [H_t | s] in device memory
 // (codes whose rows do not fit in registers): one matrix slot per
 // workgroup, (ceil(n/64) + 1) x m words, word-major (word k of row r at

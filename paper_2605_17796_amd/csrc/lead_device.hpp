@@ -58,7 +58,9 @@ __device__ __forceinline__ float exp_acc(float x) {
     constexpr float L1 = 1.44269502162933349609375f;      // log2(e) rounded to float
     constexpr float L2 = 1.925963033500011079e-8f;         // log2(e) - L1
     const float hi = x * L1;
-    const float lo = __builtin_fmaf(x, L1, -hi) + x * L2;
+    // beyond 128 e^x overflows anyway; there (x = +inf: phi(+inf) = 0 needs
+    // e^x = +inf) the correction would be inf - inf
+    const float lo = x < 128.f ? __builtin_fmaf(x, L1, -hi) + x * L2 : 0.f;
     return __builtin_amdgcn_exp2f(hi) * __builtin_fmaf(lo, 0.693147180559945309f, 1.f);
 }
 

@@ -296,6 +296,13 @@ std::string source(const Code &c, int t, bool sp) {
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
+        // the plain per-round form of the same kernel
+        o << "extern \"C\" __global__ void __launch_bounds__(" << wg
+          << (whole_file ? "" : ", 2")
+          << ") lead_spec_round_" << form
+          << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x, lead::PlainArgs pl) { "
+             "lead_spec::global_body<LeadCode, " << wg
+          << ", " << (wg == 64 ? "true" : "false") << ", " << form << ", true>(a, w, x, pl); }\n";
     }
     o << "extern \"C\" __global__ void __launch_bounds__(64) lead_spec_local_osd(lead::DecodeArgs a, lead::LocalArgs w) "
          "{ lead_spec::local_osd_body<LeadCode>(a, w); }\n";
@@ -406,6 +413,7 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
         for (int pm = 0; pm < 2 && e == hipSuccess; ++pm)
             e = hipModuleGetFunction(&k->local[form - 1][pm], k->module, ("lead_spec_local_" + f + std::to_string(pm)).c_str());
         if (e == hipSuccess) e = hipModuleGetFunction(&k->global[form - 1], k->module, ("lead_spec_global_" + f).c_str());
+        if (e == hipSuccess) e = hipModuleGetFunction(&k->round[form - 1], k->module, ("lead_spec_round_" + f).c_str());
         if (e == hipSuccess) k->has[form - 1] = true;
         for (int pm = 0; pm < 2 && e == hipSuccess; ++pm) {
             int nb = 0;
@@ -445,6 +453,8 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
     auto ins = g_modules.emplace(std::make_pair(device, src), k);
     return ins.first->second;   // another thread may have loaded it first
 }
+
+int plain_state_words(const Code &c, int t) { return c.t[t].eloc + 4 * c.t[t].r; }
 
 void partner_tables(const Code &c, int t, std::vector<uint32_t> &pv, std::vector<uint64_t> &fown) {
     const TypeTables &tt = c.t[t];

@@ -60,6 +60,7 @@ struct Kernels {
     // [form - 1][prior mode]: Phase 1 queue kernel for per-shot / per-qubit priors
     hipFunction_t local[kForms][2] = {};
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
+    hipFunction_t round[kForms] = {};    // [form - 1]: one global round (plain form)
     hipFunction_t local_osd = nullptr;   // OSD-0 on the views listed by the queue kernel
     hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
     hipFunction_t osd_cs = nullptr;      // the same with the combination sweep
@@ -91,6 +92,10 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err);
 // Kernels of check type t of code c on the current device (device index
 // `device`), compiled and loaded on first use.
 std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, std::string &err);
+
+// Words of check state per view the plain per-round kernels save between
+// launches, at most (an upper bound over the forms): E + 4 r.
+int plain_state_words(const Code &c, int t);
 
 // Partner tables of lead::SpecArgs for check type t: pv (order * ceil(D2/2)
 // words) and fown (order words).

@@ -163,6 +163,26 @@ struct Compressed {
         same = diff == 0u;
         return sat;
     }
+    // The state as WORDS 32-bit words at p[i * stride] (plain per-round form).
+    static constexpr int WORDS = 4 * R;
+    __device__ __forceinline__ void save(float *p, int stride) const {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            p[(4 * c) * stride] = m1[c];
+            p[(4 * c + 1) * stride] = m2[c];
+            p[(4 * c + 2) * stride] = __uint_as_float(am[c]);
+            p[(4 * c + 3) * stride] = __uint_as_float(q[c]);
+        }
+    }
+    __device__ __forceinline__ void load(const float *p, int stride) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            m1[c] = p[(4 * c) * stride];
+            m2[c] = p[(4 * c + 1) * stride];
+            am[c] = __float_as_uint(p[(4 * c + 2) * stride]);
+            q[c] = __float_as_uint(p[(4 * c + 3) * stride]);
+        }
+    }
     // The message of check c to its k-th edge.
     template <int c, int k>
     __device__ __forceinline__ float msg() const { return msg_of(m1[c], m2[c], am[c], q[c], (uint32_t)k); }
@@ -277,6 +297,15 @@ struct Explicit {
     }
     template <int c, int k>
     __device__ __forceinline__ float msg() const { return m[C::base[c] + k]; }
+    static constexpr int WORDS = E;
+    __device__ __forceinline__ void save(float *p, int stride) const {
+#pragma unroll
+        for (int e = 0; e < E; ++e) p[e * stride] = m[e];
+    }
+    __device__ __forceinline__ void load(const float *p, int stride) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) m[e] = p[e * stride];
+    }
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -335,6 +364,29 @@ struct Hybrid {
         });
         same = diff == 0u;
         return sat;
+    }
+    static constexpr int WORDS = EX + 4 * NC;
+    __device__ __forceinline__ void save(float *p, int stride) const {
+#pragma unroll
+        for (int e = 0; e < EX; ++e) p[e * stride] = m[e];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            p[(EX + 4 * c) * stride] = m1[c];
+            p[(EX + 4 * c + 1) * stride] = m2[c];
+            p[(EX + 4 * c + 2) * stride] = __uint_as_float(am[c]);
+            p[(EX + 4 * c + 3) * stride] = __uint_as_float(q[c]);
+        }
+    }
+    __device__ __forceinline__ void load(const float *p, int stride) {
+#pragma unroll
+        for (int e = 0; e < EX; ++e) m[e] = p[e * stride];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            m1[c] = p[(EX + 4 * c) * stride];
+            m2[c] = p[(EX + 4 * c + 1) * stride];
+            am[c] = __float_as_uint(p[(EX + 4 * c + 2) * stride]);
+            q[c] = __float_as_uint(p[(EX + 4 * c + 3) * stride]);
+        }
     }
     template <int c, int k>
     __device__ __forceinline__ float msg() const {
@@ -421,6 +473,15 @@ struct ExplicitSP {
     }
     template <int c, int k>
     __device__ __forceinline__ float msg() const { return m[C::base[c] + k]; }
+    static constexpr int WORDS = E;
+    __device__ __forceinline__ void save(float *p, int stride) const {
+#pragma unroll
+        for (int e = 0; e < E; ++e) p[e * stride] = m[e];
+    }
+    __device__ __forceinline__ void load(const float *p, int stride) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) m[e] = p[e * stride];
+    }
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -914,8 +975,14 @@ constexpr bool lam_in_lds() { return !BPERM && C::LAM_LDS && (FORM == 1 || (FORM
 // view forms its partial sum P_j (lambda' on owned positions, then its
 // checks' messages in check order) and S_j = P_j + P_j' of the other
 // occurrence.
-template <class C, int WG, bool BPERM, int FORM>
-__device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x) {
+// PLAIN (the plain per-round form): one launch per round pl.round, the sums
+// S and the check state restored from and saved to device memory between
+// launches, the same arithmetic in the same order (outputs identical bit for
+// bit); a shot writes its outputs in the launch where its run ends, and the
+// launch of round Tg + 1 ends the shots that ran to the cap.
+template <class C, int WG, bool BPERM, int FORM, bool PLAIN = false>
+__device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x,
+                                            const lead::PlainArgs &pl = lead::PlainArgs{}) {
     constexpr int D2 = C::D * C::D;
     constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
     constexpr int NW = PartnerAddr<BPERM, WG>::template words<D2>();  // words of the packed addresses
@@ -934,7 +1001,18 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     const int sl = tid / a.N, v = tid - sl * a.N;
     const bool lane_ok = sl < a.spw;
     const int64_t shot = (int64_t)blockIdx.x * a.spw + sl;
-    const bool live = lane_ok && shot < a.shots;
+    bool live = lane_ok && shot < a.shots;
+    if constexpr (PLAIN) {
+        // a shot whose run ended in an earlier launch is left alone (with
+        // one shot per workgroup the whole workgroup leaves)
+        if (pl.round > 1) {
+            if constexpr (!BPERM) {
+                const int64_t ws = (int64_t)blockIdx.x * a.spw;
+                if (ws >= a.shots || pl.ended[ws] != 0) return;
+            }
+            if (live && pl.ended[shot] != 0) live = false;
+        }
+    }
     for (int i = tid; i < a.spw * SF_STRIDE; i += WG) shf[i] = 0;
     for (int i = tid; i < a.spw * ew32; i += WG) ebits[i] = 0u;
 
@@ -1003,7 +1081,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
 #pragma unroll
         for (int j = 0; j < D2; ++j) lam[j] = aggregate_llr(clampf(S[j], a.clampv), clampf(Lp[j], a.clampv), a.alpha, a.clampv);
     }
-    if (a.lam_out && live) {
+    if (a.lam_out && live && (!PLAIN || pl.round == 1)) {
 #pragma unroll
         for (int j = 0; j < D2; ++j)
             if (owned(j)) a.lam_out[shot * a.n + a.view[v * D2 + j]] = lam[j];
@@ -1039,17 +1117,31 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
                 if (signbit_of(S[j])) atomicOr(&ebits[sl * ew32 + (qd >> 5)], 1u << (qd & 31));
             }
     };
+    using State = GlobalState<C, FORM>;
+    State st;
+    bool resumed = false;
+    if constexpr (PLAIN) resumed = pl.round > 1 && live;
+    if (resumed) {
 #pragma unroll
-    for (int j = 0; j < D2; ++j) S[j] = lam[j];
-    GlobalState<C, FORM> st;
-    st.clear();
+        for (int j = 0; j < D2; ++j) S[j] = pl.S[(shot * D2 + j) * a.N + v];
+        st.load(pl.st + shot * State::WORDS * a.N + v, a.N);
+    } else {
+#pragma unroll
+        for (int j = 0; j < D2; ++j) S[j] = lam[j];
+        st.clear();
+    }
     if (!BPERM) __syncthreads();
     bool done = !live;
     bool wdone = false;   // the workgroup's shot has ended (one shot per workgroup, !BPERM)
     int itg = 0, gconv = 0, gfix = 0;
     // lanes of this lane's shot within the wave (one-wave workgroups)
     const uint64_t smask = lane_ok ? ((a.N >= 64 ? ~0ull : ((1ull << a.N) - 1ull)) << (sl * a.N)) : 0ull;
-    for (int t = 1; t <= a.Tg; ++t) {
+    int t0 = 1, t1 = a.Tg;
+    if constexpr (PLAIN) {
+        t0 = pl.round;
+        t1 = pl.round <= a.Tg ? pl.round : a.Tg;   // round Tg + 1: no iteration
+    }
+    for (int t = t0; t <= t1; ++t) {
         // computed by every lane (see local_body); done lanes discard it
         bool same;
         const bool sat = st.check(S, sv, a.beta, a.clampv, same);
@@ -1146,7 +1238,11 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             });
         }
         }
-    const bool ran_out = !done;
+    // plain form before the last round: a shot still running keeps its state
+    // for the next launch and writes nothing else
+    bool hold = false;
+    if constexpr (PLAIN) hold = live && !done && pl.round <= a.Tg;
+    const bool ran_out = !done && !hold;
     const bool psat = parity<C>(S, sv);
     bool shot_final;
     if constexpr (BPERM) {
@@ -1162,10 +1258,19 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
         if constexpr (BPERM) emit();
     }
     if constexpr (!BPERM) {
-        if (live) emit();
+        if (live && !hold) emit();
     }
     __syncthreads();
-    if (live) {
+    if constexpr (PLAIN) {
+        if (hold) {
+#pragma unroll
+            for (int j = 0; j < D2; ++j) pl.S[(shot * D2 + j) * a.N + v] = S[j];
+            st.save(pl.st + shot * State::WORDS * a.N + v, a.N);
+            if (v == 0) atomicAdd(pl.active, 1);
+        }
+        if (live && v == 0) pl.ended[shot] = hold ? 0 : 1;
+    }
+    if (live && !hold) {
         if (a.ehat)
             for (int wd = v; wd < a.ehat_words; wd += a.N) {
                 const uint64_t lo = (2 * wd < ew32) ? ebits[sl * ew32 + 2 * wd] : 0u;

@@ -130,9 +130,13 @@ def test_global_osd_paths_identical_and_limits():
             assert np.array_equal(ref["ehat"][i], b["ehat"][i]) and ref["stats"][i, 0] == b["stats"][i, 0]
     conv = b["stats"][:, 0] == 1
     assert np.array_equal(ref["ehat"][conv], b["ehat"][conv])
+    # the plain per-round form on the compiled kernels, global OSD included
+    dec.set_schedule(specialized=2)
+    pa = dec.decode(st, pr, lam=True, plain=True)
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(pa[k].cpu().numpy().view(ref[k].dtype), ref[k]), k
     # limits
-    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
-        dec.decode(st, pr, plain=True)
     with pytest.raises(P.LeadError, match="UNSUPPORTED"):
         gpu_decoder(spec, global_post=1, stage=1)
     with pytest.raises(P.LeadError, match="ARG"):

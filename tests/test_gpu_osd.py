@@ -56,8 +56,11 @@ def test_local_osd_forms_identical_and_limits():
     assert sc["fused"] == 0 and sc["specialized"] in (1, 2)
     st = torch.from_numpy(s.view(np.int64)).cuda()
     pr = torch.from_numpy(lam).cuda()
-    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
-        dec.decode(st, pr, plain=True)
+    # the plain per-round form runs the compiled kernels, local OSD included
+    pa = dec.decode(st, pr, lam=True, plain=True)
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(pa[k].cpu().numpy().view(runs[2][k].dtype), runs[2][k]), k
     with pytest.raises(P.LeadError, match="UNSUPPORTED"):
         gpu_decoder(spec, local_post=1, stage=2)
 

@@ -263,14 +263,26 @@ def test_argument_errors():
         P.Decoder(code, alpha=0.0)
 
 
-@pytest.mark.parametrize("name,shots,p,T", [("T", 301, 0.05, 32), ("M", 97, 0.05, 50), ("M", 64, 0.02, 50),
-                                            ("L", 5, 0.02, 16)])
-def test_plain_form_bit_identical(name, shots, p, T):
+@pytest.mark.parametrize("name,t,shots,p,T,kw", [
+    ("T", 0, 301, 0.05, 32, {}), ("T", 1, 200, 0.05, 32, dict(specialized=1)), ("M", 0, 97, 0.05, 50, {}),
+    ("M", 0, 64, 0.02, 50, dict(specialized=1)), ("M", 1, 120, 0.03, 50, {}), ("M", 0, 150, 0.05, 20, dict(bp=1)),
+    ("M", 0, 150, 0.05, 20, dict(stage=2)), ("M", 0, 150, 0.05, 12, dict(local_post=1, global_post=1, osd_order=3)),
+    ("L", 0, 40, 0.02, 16, {}), ("L", 1, 40, 0.02, 16, {}), ("L", 0, 24, 0.02, 8, dict(bp=1)),
+    ("M", 0, 64, 0.05, 50, dict(specialized=0)), ("L", 0, 5, 0.02, 16, dict(specialized=0))])
+def test_plain_form_bit_identical(name, t, shots, p, T, kw):
     """lead_decode_plain (one launch per global round, state in HBM, host
-    convergence check) returns exactly what the fused lead_decode returns."""
+    convergence check) returns exactly what lead_decode returns: on the
+    kernels compiled for the code (its per-round kernels, every form, BP
+    flavour, stage and post-processing) and on the precompiled kernels
+    (specialized = 0: min-sum without OSD)."""
+    kw = dict(kw)
+    form = kw.pop("specialized", None)
     spec, oc = code_pair(name)
-    code, dec = gpu_decoder(spec, max_iter_local=T, max_iter_global=T)
-    e, _, lamv = bitflip_inputs(oc, shots, p, seed=71)
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=T, max_iter_global=T, **kw)
+    if form is not None:
+        dec.set_schedule(specialized=form)
+        assert dec.get_schedule()["specialized"] == form
+    e, _, lamv = bitflip_inputs(oc, shots, p, seed=71, t=t)
     s = _gpu_syndrome(dec, e)
     torch = torch_dev()
     synd = torch.from_numpy(s.view(np.int64)).cuda()
@@ -280,7 +292,8 @@ def test_plain_form_bit_identical(name, shots, p, T):
     torch.cuda.synchronize()
     for k in ("ehat", "post", "lam", "stats"):
         assert torch.equal(a[k], b[k]), k
-    log(f"[plain] {name}: {shots} shots bit-identical, conv={float((a['stats'][:, 0] == 1).float().mean()):.3f}")
+    log(f"[plain] {name} t={t} {kw} form={dec.get_schedule()['specialized']}: {shots} shots bit-identical, "
+        f"conv={float((a['stats'][:, 0] != 0).float().mean()):.3f}")
 
 
 @pytest.mark.parametrize("name,shots,p,T", [("T", 500, 0.05, 32), ("M", 300, 0.05, 50), ("M", 300, 0.02, 50),

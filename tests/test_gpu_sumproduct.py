@@ -111,16 +111,23 @@ def test_sum_product_psl27_matches_oracle(t, T, shots, min_well):
     assert well >= min_well
 
 
-def test_sum_product_limits():
-    """The plain per-round form is min-sum only."""
-    import paper_2605_17796_amd as P
+def test_sum_product_plain_form_and_flavour_switch():
+    """The plain per-round form runs sum-product on its compiled round
+    kernel (bit-identical to lead_decode); the precompiled kernels have no
+    sum-product, so schedules keep the compiled form."""
     torch = torch_dev()
     spec, oc = code_pair("T")
-    code, dec = gpu_decoder(spec, bp=SP)
-    s = torch.zeros((4, 1), dtype=torch.int64, device="cuda")
-    lam = torch.full((4,), 2.9, dtype=torch.float32, device="cuda")
-    with pytest.raises(P.LeadError, match="UNSUPPORTED"):
-        dec.decode(s, lam, plain=True)
+    code, dec = gpu_decoder(spec, bp=SP, max_iter_local=20, max_iter_global=20)
+    e, s, lamv = bitflip_inputs(oc, 200, 0.06, seed=5)
+    s = torch.from_numpy(_gpu_syndrome(dec, e).view(np.int64)).cuda()
+    lam = torch.from_numpy(lamv).cuda()
+    a = dec.decode(s, lam, lam=True)
+    b = dec.decode(s, lam, lam=True, plain=True)
+    torch.cuda.synchronize()
+    for k in ("ehat", "post", "lam", "stats"):
+        assert torch.equal(a[k], b[k]), k
+    dec.set_schedule(specialized=0, fused=1)
+    assert dec.get_schedule()["specialized"] == 3 and dec.get_schedule()["fused"] == 0
     # switching flavours on a live decoder
     dec.set_params(bp=0)
     assert dec.get_schedule()["specialized"] in (1, 2)
