@@ -66,3 +66,33 @@ def test_noise_rates_and_determinism():
     assert abs((bx | bz).mean() - 0.03) < 0.003
     assert abs((bx & bz).mean() - 0.01) < 0.002
     assert np.isclose(float(channel_llr(0.05)), np.log(19.0), rtol=1e-7)
+
+
+def test_device_noise_packing_and_rates():
+    """The GPU-side generators (run here on the CPU device) pack bits exactly
+    like pack_bits and draw flips at the stated rates; depolarising X and Z
+    parts overlap on Y errors only (rate p/3)."""
+    import torch
+    from lead_inputs.noise_device import _pack, bitflip_packed_device, depolarizing_packed_device
+    from lead_inputs import pack_bits, unpack_bits
+    rng = np.random.default_rng(0)
+    for n in (1, 63, 64, 65, 1080, 5376):
+        bits = rng.random((7, n)) < 0.3
+        got = _pack(torch.from_numpy(bits)).numpy().view(np.uint64)
+        assert np.array_equal(got, pack_bits(bits.astype(np.uint8)))
+    e = bitflip_packed_device(4000, 1080, 0.05, seed=3, device="cpu").numpy().view(np.uint64)
+    rate = unpack_bits(e, 1080).mean()
+    assert abs(rate - 0.05) < 4 * np.sqrt(0.05 * 0.95 / (4000 * 1080))
+    ps = np.linspace(0.02, 0.08, 2000)
+    e = unpack_bits(bitflip_packed_device(2000, 1080, ps, seed=4, device="cpu").numpy().view(np.uint64), 1080)
+    assert np.corrcoef(e.mean(axis=1), ps)[0, 1] > 0.8
+    xs, zs = depolarizing_packed_device(3000, 1080, 0.06, seed=5, device="cpu")
+    x = unpack_bits(xs.numpy().view(np.uint64), 1080)
+    z = unpack_bits(zs.numpy().view(np.uint64), 1080)
+    tot = 3000 * 1080
+    for r, want in ((x.mean(), 0.04), (z.mean(), 0.04), ((x & z).mean(), 0.02)):
+        assert abs(r - want) < 4 * np.sqrt(want * (1 - want) / tot)
+    # distinct draws per shot, same draws for the same seed
+    a = bitflip_packed_device(50, 1080, 0.05, seed=9, device="cpu")
+    b = bitflip_packed_device(50, 1080, 0.05, seed=9, device="cpu")
+    assert torch.equal(a, b) and len({tuple(r) for r in a.tolist()}) == 50
