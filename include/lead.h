@@ -52,7 +52,8 @@ typedef enum {
     LEAD_E_NOMEM = -6,        /* host or device allocation failed               */
     LEAD_E_DEVICE = -7,       /* HIP runtime error (message has the HIP string) */
     LEAD_E_CAPACITY = -8,     /* batch larger than the decoder was sized for    */
-    LEAD_E_UNSUPPORTED = -9   /* shape the compiled kernels do not cover        */
+    LEAD_E_UNSUPPORTED = -9,  /* shape the compiled kernels do not cover        */
+    LEAD_E_CLOSED = -10       /* the server no longer accepts requests          */
 } lead_status;
 
 typedef enum { LEAD_CHECK_Z = 0, LEAD_CHECK_X = 1 } lead_check_type;
@@ -393,9 +394,22 @@ void lead_batch_graph_destroy(lead_batch_graph *graph);
  * decoder copy (device-resident code tables and workspace), device buffers,
  * pinned staging and stream, and runs copy-in, decode and copy-out.  Requests
  * that arrive while slots are busy are admitted into the next slot that
- * frees, so their work overlaps the work already on the device.  Slots are
- * created until their device memory would exceed `mem_budget_bytes` (at
- * least one per decoder, at most `max_slots_per_decoder`). */
+ * frees, so their work overlaps the work already on the device.
+ *
+ * Admission by device memory: a slot's device memory is counted as its
+ * decoder copy's actual allocation plus its input/output buffers, and the
+ * slots together stay within `mem_budget_bytes`.  One slot per decoder is
+ * created with the server (LEAD_E_CAPACITY if the budget cannot hold them);
+ * further slots are created while a decoder has waiting shots and no idle
+ * slot, up to `max_slots_per_decoder` and within the budget; when the budget
+ * is full, an idle extra slot of a decoder with nothing waiting is freed to
+ * make room.  Waiting requests hold no device memory.
+ *
+ * Back-pressure: at most `max_pending_shots` shots may be pending (submitted
+ * and not yet released by lead_server_result); a submit beyond that returns
+ * LEAD_E_CAPACITY and queues nothing (the caller retries once results have
+ * been collected), and a request larger than the limit on its own is
+ * refused with LEAD_E_CAPACITY as oversize. */
 typedef struct lead_server lead_server;
 
 typedef struct {
@@ -403,12 +417,18 @@ typedef struct {
     int32_t max_batch_shots;        /* shots per launch slot (0 = 4096)             */
     int32_t max_slots_per_decoder;  /* (0 = 4)                                      */
     int32_t return_posteriors;      /* 1: keep L_post of every shot for the result */
+    int32_t reserved;
+    int64_t max_pending_shots;      /* submitted, unreleased shots (0 = 2^24)       */
 } lead_server_config;
 
 typedef struct {
     int64_t submitted, completed, shots_completed, launches;
-    int32_t slots;                  /* launch slots created                         */
-    int32_t reserved;
+    int32_t slots;                  /* launch slots in existence                    */
+    int32_t slots_created;          /* slots created since the server started       */
+    int64_t slot_bytes;             /* device bytes of the slots in existence       */
+    int64_t evictions;              /* idle slots freed to make room for another    */
+    int64_t refused;                /* submits refused (pending limit, oversize)    */
+    int64_t pending_shots;          /* submitted shots not yet released             */
 } lead_server_stats;
 
 /* Decoders are used as templates: the server clones them (parameters and
@@ -416,7 +436,10 @@ typedef struct {
 lead_status lead_server_create(lead_decoder *const *decoders, int32_t n_decoders, const lead_server_config *config,
                                lead_server **out);
 /* Copies the request's inputs (h_synd: shots x synd_words, h_prior: shots
- * LLRs, one per shot) and queues it; *ticket identifies it.  Thread-safe. */
+ * LLRs, one per shot) and queues it; *ticket identifies it.  Thread-safe.
+ * LEAD_E_CAPACITY (nothing queued) when the pending-shot limit would be
+ * exceeded or the request alone exceeds it; LEAD_E_CLOSED after
+ * lead_server_close. */
 lead_status lead_server_submit(lead_server *server, int32_t decoder_index, int64_t shots, const uint64_t *h_synd,
                                int64_t synd_words, const float *h_prior, int64_t *ticket);
 /* *done = 1 once every shot of the request is decoded (0 otherwise). */
@@ -430,6 +453,10 @@ lead_status lead_server_wait(lead_server *server, int64_t ticket);
 lead_status lead_server_result(lead_server *server, int64_t ticket, uint64_t *h_ehat, float *h_post,
                                lead_shot_stats *h_stats, int64_t *submit_ns, int64_t *done_ns);
 lead_status lead_server_get_stats(lead_server *server, lead_server_stats *out);
+/* Stops accepting requests (later submits return LEAD_E_CLOSED) and blocks
+ * until every request already submitted is decoded; their results stay
+ * available to lead_server_result.  LEAD_E_DEVICE if a launch failed. */
+lead_status lead_server_close(lead_server *server);
 /* Current value of the clock used for request timestamps. */
 int64_t lead_server_clock_ns(void);
 /* Finishes the work on the device, stops the worker, frees everything;

@@ -26,7 +26,7 @@ LEAD_STAGE_FULL, LEAD_STAGE_LOCAL, LEAD_STAGE_GLOBAL = 0, 1, 2
 LEAD_BP_MINSUM, LEAD_BP_SUMPRODUCT = 0, 1
 STATUS_NAMES = {0: "LEAD_OK", -1: "LEAD_E_ARG", -2: "LEAD_E_GROUP", -3: "LEAD_E_SYMMETRY", -4: "LEAD_E_TNC",
                 -5: "LEAD_E_LOCALCODE", -6: "LEAD_E_NOMEM", -7: "LEAD_E_DEVICE", -8: "LEAD_E_CAPACITY",
-                -9: "LEAD_E_UNSUPPORTED"}
+                -9: "LEAD_E_UNSUPPORTED", -10: "LEAD_E_CLOSED"}
 
 
 class LeadError(RuntimeError):
@@ -72,12 +72,15 @@ class lead_batch_item(C.Structure):
 
 class lead_server_config(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("max_batch_shots", C.c_int32),
-                ("max_slots_per_decoder", C.c_int32), ("return_posteriors", C.c_int32)]
+                ("max_slots_per_decoder", C.c_int32), ("return_posteriors", C.c_int32), ("reserved", C.c_int32),
+                ("max_pending_shots", C.c_int64)]
 
 
 class lead_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("shots_completed", C.c_int64),
-                ("launches", C.c_int64), ("slots", C.c_int32), ("reserved", C.c_int32)]
+                ("launches", C.c_int64), ("slots", C.c_int32), ("slots_created", C.c_int32),
+                ("slot_bytes", C.c_int64), ("evictions", C.c_int64), ("refused", C.c_int64),
+                ("pending_shots", C.c_int64)]
 
 
 STATS_FIELDS = ("converged", "global_iters", "local_iters_sum", "local_iters_max", "local_converged_views",
@@ -90,7 +93,7 @@ SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_
            "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
            "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_server_create", "lead_server_submit",
            "lead_server_poll", "lead_server_wait", "lead_server_result", "lead_server_get_stats",
-           "lead_server_clock_ns", "lead_server_destroy"]
+           "lead_server_clock_ns", "lead_server_close", "lead_server_destroy"]
 
 _lib = None
 
@@ -140,6 +143,7 @@ def lib():
         L.lead_server_wait.argtypes = [P, I64]
         L.lead_server_result.argtypes = [P, I64, P, P, P, C.POINTER(I64), C.POINTER(I64)]
         L.lead_server_get_stats.argtypes = [P, C.POINTER(lead_server_stats)]
+        L.lead_server_close.argtypes = [P]
         L.lead_server_clock_ns.argtypes = []
         L.lead_server_destroy.argtypes = [P]
         L.lead_server_destroy.restype = None
@@ -508,10 +512,11 @@ class Server:
     requests in, host results out)."""
 
     def __init__(self, decoders, mem_budget_bytes=1 << 30, max_batch_shots=4096, max_slots_per_decoder=4,
-                 return_posteriors=False):
+                 return_posteriors=False, max_pending_shots=0):
         self.decoders = list(decoders)
         arr = (C.c_void_p * len(self.decoders))(*[d._h.value for d in self.decoders])
-        cfg = lead_server_config(mem_budget_bytes, max_batch_shots, max_slots_per_decoder, int(return_posteriors))
+        cfg = lead_server_config(mem_budget_bytes, max_batch_shots, max_slots_per_decoder, int(return_posteriors), 0,
+                                 max_pending_shots)
         self.return_posteriors = return_posteriors
         h = C.c_void_p()
         _check(lib().lead_server_create(arr, len(self.decoders), C.byref(cfg), C.byref(h)))
@@ -554,7 +559,13 @@ class Server:
     def clock_ns() -> int:
         return lib().lead_server_clock_ns()
 
+    def drain(self):
+        """lead_server_close: refuse new requests, wait for the admitted ones
+        (their results stay available)."""
+        _check(lib().lead_server_close(self._h))
+
     def close(self):
+        """Finish the device work and free the server (lead_server_destroy)."""
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             _lib.lead_server_destroy(h)

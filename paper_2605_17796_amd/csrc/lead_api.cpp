@@ -728,6 +728,20 @@ void decoder_shape(const lead_decoder *d, int *n, int *m) {
     *m = d->m;
 }
 
+int64_t decoder_device_bytes(const lead_decoder *d) {
+    const lead::TypeTables &tt = d->code->t[d->type];
+    const int64_t D2 = (int64_t)d->D * d->D, N = d->N, ws = d->ws_shots;
+    int64_t b = 4 * (int64_t)tt.view.size() + 4 * N * d->own_max;            // view table, owner lists
+    b += ws * (N * D2 * 4 + N * 4 + N * 4) + 4 * 8;                          // workspace, counters
+    if (d->d_pv) b += 4 * N * ((D2 + 1) / 2) + 8 * N;                        // partner tables
+    if (d->d_rptr) b += 4 * (int64_t)(tt.csr_ptr.size() + tt.csr_idx.size());
+    if (d->d_gpost) b += ws * (4 * (int64_t)d->n * 2 + (int64_t)sizeof(lead_shot_stats));
+    if (d->d_osd_mat) b += (int64_t)lead::jit::osd_big_slot_bytes(*d->code, d->type) * d->osd_slots;
+    if (d->d_pS)
+        b += d->plain_shots * (N * D2 * 4 + N * 4 * lead::jit::plain_state_words(*d->code, d->type) + 4) + 8;
+    return b;
+}
+
 lead_status set_error(lead_status s, const char *msg) { return fail(s, msg); }
 
 }  // namespace lead

@@ -8,12 +8,16 @@
 //      decode and copy-out on the slot's stream.
 // A request that arrives while all slots are busy is admitted into the next
 // slot that frees, so its decode overlaps the launches already on the
-// device.
+// device.  Device memory is admitted slot by slot against the budget: one
+// slot per decoder from the start, more while the budget allows, and an
+// idle extra slot of a decoder with nothing waiting is freed when another
+// decoder's shots wait and the budget is full.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -65,6 +69,8 @@ struct Slot {
     float *h_prior = nullptr, *h_post = nullptr;
     lead_shot_stats *h_stats = nullptr;
     bool busy = false;
+    bool pinned = false;             // the decoder's first slot: never freed early
+    int64_t bytes = 0;               // device bytes (decoder copy + buffers)
     std::vector<Part> parts;
 };
 
@@ -84,10 +90,13 @@ struct lead_server {
     std::condition_variable cv_work, cv_done;
     std::thread worker;
     bool stop = false;
+    bool closed = false;             // no more submits (lead_server_close)
     std::string fault;               // sticky device error
     int64_t next_ticket = 1;
     lead_server_stats st{};
     int device = 0;
+    int64_t used = 0;                // device bytes of the slots in existence
+    std::vector<int> nslots;         // slots per decoder
 };
 
 namespace {
@@ -127,17 +136,52 @@ hipError_t alloc_slot(lead_server *sv, int dec, lead_decoder *tmpl, Slot &s) {
     if (e == hipSuccess) e = hipHostMalloc(&s.h_stats, sizeof(lead_shot_stats) * cap, hipHostMallocDefault);
     if (e == hipSuccess && sv->cfg.return_posteriors)
         e = hipHostMalloc(&s.h_post, sizeof(float) * cap * sh.n, hipHostMallocDefault);
+    if (e == hipSuccess) {
+        // the decoder copy's own allocation plus the slot's device buffers
+        s.bytes = lead::decoder_device_bytes(s.decoder) +
+                  cap * (8 * sh.sw + 4 + 8 * sh.ew + (int64_t)sizeof(lead_shot_stats)) +
+                  (sv->cfg.return_posteriors ? cap * 4 * sh.n : 0);
+    }
     return e;
 }
 
-// Device bytes of one slot of decoder `dec` (buffers plus the decoder copy's
-// workspace; the code tables are small and ignored).
-int64_t slot_bytes(const lead_server *sv, int dec, int64_t workspace_per_shot) {
-    const DecShape &sh = sv->shapes[dec];
-    const int64_t cap = sv->cfg.max_batch_shots;
-    int64_t b = cap * (8 * sh.sw + 4 + 8 * sh.ew + (int64_t)sizeof(lead_shot_stats));
-    if (sv->cfg.return_posteriors) b += cap * 4 * sh.n;
-    return b + cap * workspace_per_shot;
+// Called with the lock held: a new slot of decoder `dec`, cloned from its
+// first slot, if the budget allows; false otherwise (or on failure).
+bool grow(lead_server *sv, int dec) {
+    lead_decoder *tmpl = nullptr;
+    int64_t bytes = 0;
+    for (const Slot &x : sv->slots)
+        if (x.dec == dec && x.pinned) {
+            tmpl = x.decoder;
+            bytes = x.bytes;
+        }
+    if (!tmpl || sv->used + bytes > sv->cfg.mem_budget_bytes) return false;
+    Slot s;
+    if (alloc_slot(sv, dec, tmpl, s) != hipSuccess) {
+        free_slot(s);
+        return false;
+    }
+    sv->used += s.bytes;
+    sv->nslots[dec]++;
+    sv->st.slots_created++;
+    sv->slots.push_back(std::move(s));
+    return true;
+}
+
+// Called with the lock held: frees an idle extra slot of a decoder that has
+// nothing waiting, to make room for another decoder's waiting shots.
+bool evict(lead_server *sv, int for_dec) {
+    for (size_t i = 0; i < sv->slots.size(); ++i) {
+        Slot &x = sv->slots[i];
+        if (x.busy || x.pinned || x.dec == for_dec || !sv->waiting[x.dec].empty()) continue;
+        sv->used -= x.bytes;
+        sv->nslots[x.dec]--;
+        free_slot(x);
+        sv->slots.erase(sv->slots.begin() + (std::ptrdiff_t)i);
+        sv->st.evictions++;
+        return true;
+    }
+    return false;
 }
 
 // Called with the lock held: copy the results of a finished slot out.
@@ -221,6 +265,16 @@ void worker_loop(lead_server *sv) {
         }
         if (progress) sv->cv_done.notify_all();
         if (sv->fault.empty()) {
+            // admission: a decoder with waiting shots and every slot busy
+            // gets another slot within the budget (freeing an idle slot of
+            // a decoder with nothing waiting if needed)
+            for (int dec = 0; dec < (int)sv->waiting.size(); ++dec) {
+                if (sv->waiting[dec].empty() || sv->nslots[dec] >= sv->cfg.max_slots_per_decoder) continue;
+                bool idle = false;
+                for (const Slot &x : sv->slots) idle = idle || (x.dec == dec && !x.busy);
+                if (idle) continue;
+                if (!grow(sv, dec) && evict(sv, dec)) (void)grow(sv, dec);
+            }
             for (Slot &s : sv->slots) {
                 if (s.busy || sv->waiting[s.dec].empty()) continue;
                 hipError_t e = fill_and_launch(sv, s);
@@ -268,36 +322,41 @@ lead_status lead_server_create(lead_decoder *const *decoders, int32_t nd, const 
     if (sv->cfg.mem_budget_bytes <= 0) sv->cfg.mem_budget_bytes = int64_t(1) << 30;
     if (sv->cfg.max_batch_shots <= 0) sv->cfg.max_batch_shots = 4096;
     if (sv->cfg.max_slots_per_decoder <= 0) sv->cfg.max_slots_per_decoder = 4;
+    if (sv->cfg.max_pending_shots <= 0) sv->cfg.max_pending_shots = int64_t(1) << 24;
     if (hipGetDevice(&sv->device) != hipSuccess) return lead::set_error(LEAD_E_DEVICE, "hipGetDevice failed");
     sv->shapes.resize(nd);
-    std::vector<int64_t> ws_per_shot(nd);
     for (int i = 0; i < nd; ++i) {
         if (!decoders[i]) return lead::set_error(LEAD_E_ARG, "NULL decoder");
         int n, m;
         lead::decoder_shape(decoders[i], &n, &m);
         sv->shapes[i] = DecShape{n, m, (m + 63) / 64, (n + 63) / 64};
-        ws_per_shot[i] = (int64_t)2 * n * 4 + (int64_t)8 * 4;   // local posteriors + view flags (approx.)
     }
     sv->waiting.resize(nd);
-    // slots: round-robin over decoders while the budget allows
-    int64_t used = 0;
-    std::vector<int> per(nd, 0);
-    for (int round = 0; round < sv->cfg.max_slots_per_decoder; ++round)
-        for (int i = 0; i < nd; ++i) {
-            const int64_t b = slot_bytes(sv.get(), i, ws_per_shot[i]);
-            if (round > 0 && used + b > sv->cfg.mem_budget_bytes) continue;
-            Slot s;
-            hipError_t e = alloc_slot(sv.get(), i, decoders[i], s);
-            if (e != hipSuccess) {
-                free_slot(s);
-                for (Slot &x : sv->slots) free_slot(x);
-                return lead::set_error(LEAD_E_NOMEM, "slot allocation failed");
-            }
-            sv->slots.push_back(std::move(s));
-            used += b;
-            per[i]++;
+    sv->nslots.assign(nd, 0);
+    // one slot per decoder (kept for the server's life), then more,
+    // round-robin, while the budget allows
+    for (int i = 0; i < nd; ++i) {
+        Slot s;
+        hipError_t e = alloc_slot(sv.get(), i, decoders[i], s);
+        if (e != hipSuccess || sv->used + s.bytes > sv->cfg.mem_budget_bytes) {
+            const int64_t need = s.bytes;
+            free_slot(s);
+            for (Slot &x : sv->slots) free_slot(x);
+            if (e != hipSuccess) return lead::set_error(LEAD_E_NOMEM, "slot allocation failed");
+            return lead::set_error(LEAD_E_CAPACITY,
+                                   ("mem_budget_bytes " + std::to_string(sv->cfg.mem_budget_bytes) +
+                                    " cannot hold one launch slot per decoder (decoder " + std::to_string(i) +
+                                    " needs " + std::to_string(need) + " bytes beyond " + std::to_string(sv->used) + ")")
+                                       .c_str());
         }
-    sv->st.slots = (int32_t)sv->slots.size();
+        s.pinned = true;
+        sv->used += s.bytes;
+        sv->nslots[i] = 1;
+        sv->slots.push_back(std::move(s));
+    }
+    sv->st.slots_created = nd;
+    for (int round = 1; round < sv->cfg.max_slots_per_decoder; ++round)
+        for (int i = 0; i < nd; ++i) (void)grow(sv.get(), i);
     lead_server *raw = sv.get();
     try {
         sv->worker = std::thread(worker_loop, raw);
@@ -315,7 +374,35 @@ lead_status lead_server_submit(lead_server *sv, int32_t dec, int64_t shots, cons
     if (dec < 0 || dec >= (int32_t)sv->shapes.size()) return lead::set_error(LEAD_E_ARG, "decoder index out of range");
     const DecShape &sh = sv->shapes[dec];
     if (synd_words < sh.sw) return lead::set_error(LEAD_E_ARG, "synd_words < ceil(m/64)");
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->closed || sv->stop) return lead::set_error(LEAD_E_CLOSED, "the server is closed");
+        if (shots > sv->cfg.max_pending_shots) {
+            sv->st.refused++;
+            return lead::set_error(LEAD_E_CAPACITY, ("oversize request: " + std::to_string(shots) +
+                                                     " shots, the server holds at most " +
+                                                     std::to_string(sv->cfg.max_pending_shots) + " pending")
+                                                        .c_str());
+        }
+        if (sv->st.pending_shots + shots > sv->cfg.max_pending_shots) {
+            sv->st.refused++;
+            return lead::set_error(LEAD_E_CAPACITY, ("server busy: " + std::to_string(sv->st.pending_shots) +
+                                                     " shots pending of at most " +
+                                                     std::to_string(sv->cfg.max_pending_shots) +
+                                                     "; collect results and retry")
+                                                        .c_str());
+        }
+        sv->st.pending_shots += shots;   // reserved now; released by lead_server_result
+    }
+    auto unreserve = [&] {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->st.pending_shots -= shots;
+    };
     std::unique_ptr<Request> r(new (std::nothrow) Request());
+    if (!r) {
+        unreserve();
+        return lead::set_error(LEAD_E_NOMEM, "out of host memory");
+    }
     if (!r) return lead::set_error(LEAD_E_NOMEM, "out of host memory");
     try {
         r->dec = dec;
@@ -328,13 +415,17 @@ lead_status lead_server_submit(lead_server *sv, int32_t dec, int64_t shots, cons
         r->stats.resize(shots);
         if (sv->cfg.return_posteriors) r->post.resize((size_t)shots * sh.n);
     } catch (const std::bad_alloc &) {
+        unreserve();
         return lead::set_error(LEAD_E_NOMEM, "out of host memory");
     }
     r->t_submit = now_ns();
     {
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (!sv->fault.empty()) return lead::set_error(LEAD_E_DEVICE, sv->fault.c_str());
-        if (sv->stop) return lead::set_error(LEAD_E_ARG, "server is stopping");
+        if (!sv->fault.empty() || sv->closed || sv->stop) {
+            sv->st.pending_shots -= shots;
+            if (!sv->fault.empty()) return lead::set_error(LEAD_E_DEVICE, sv->fault.c_str());
+            return lead::set_error(LEAD_E_CLOSED, "the server is closed");
+        }
         *ticket = sv->next_ticket++;
         sv->waiting[dec].push_back(r.get());
         sv->requests[*ticket] = std::move(r);
@@ -378,6 +469,7 @@ lead_status lead_server_result(lead_server *sv, int64_t ticket, uint64_t *h_ehat
             return lead::set_error(LEAD_E_ARG, "server was created without return_posteriors");
         r = std::move(it->second);
         sv->requests.erase(it);
+        sv->st.pending_shots -= r->shots;
     }
     if (h_ehat) std::memcpy(h_ehat, r->ehat.data(), sizeof(uint64_t) * r->ehat.size());
     if (h_post) std::memcpy(h_post, r->post.data(), sizeof(float) * r->post.size());
@@ -391,6 +483,17 @@ lead_status lead_server_get_stats(lead_server *sv, lead_server_stats *out) {
     if (!sv || !out) return lead::set_error(LEAD_E_ARG, "bad argument");
     std::lock_guard<std::mutex> lk(sv->mu);
     *out = sv->st;
+    out->slots = (int32_t)sv->slots.size();
+    out->slot_bytes = sv->used;
+    return LEAD_OK;
+}
+
+lead_status lead_server_close(lead_server *sv) {
+    if (!sv) return lead::set_error(LEAD_E_ARG, "bad argument");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->closed = true;
+    sv->cv_done.wait(lk, [sv] { return sv->st.completed == sv->st.submitted || !sv->fault.empty(); });
+    if (sv->st.completed != sv->st.submitted) return lead::set_error(LEAD_E_DEVICE, sv->fault.c_str());
     return LEAD_OK;
 }
 
