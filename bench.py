@@ -602,12 +602,24 @@ def main():
             o = d2.alloc_outputs(sizes[name])
             if name != "M":
                 d2.autotune(s, pr)
+                sc = d2.get_schedule()
+                if sc["specialized"] == 0 or sc["fused"]:
+                    # every leg of this comparison runs the kernels compiled
+                    # for the code (the fused batch needs them)
+                    d2.set_schedule(**{**sc, "specialized": 2, "fused": 0})
             entries.append((d2, s, pr, o, P.LEAD_PRIOR_PER_SHOT))
             plain_items.append((d2, s, pr, o))
         batch = P.Batch(entries).capture()
         batch.replay()
         bw, _ = timed(torch, lambda i: batch.replay(), 3)
         bw /= 3
+        # the same requests fused: one persistent Phase 1 launch and one
+        # Phases 2-3 launch for the three codes, replayed as a graph
+        fused = P.FusedBatch(entries)
+        fused.launch()
+        fw, _ = timed(torch, lambda i: fused.launch(), 3)
+        fw /= 3
+        del fused
         for d2, s, pr, o in plain_items:   # warm-up: per-round state allocated here
             d2.decode(s, pr, out=o, plain=True)
         pw2, _ = timed(torch, lambda i: [d2.decode(s, pr, out=o, plain=True) for d2, s, pr, o in plain_items], 2)
@@ -616,11 +628,15 @@ def main():
         ew2 /= 2
         total = sum(sizes.values())
         mixed = {"shots": sizes, "batched_graph_shots_per_s": round(total / bw, 1),
+                 "fused_graph_shots_per_s": round(total / fw, 1),
                  "plain_per_code_shots_per_s": round(total / pw2, 1), "batched_over_plain": round(pw2 / bw, 3),
+                 "fused_over_plain": round(pw2 / fw, 3),
                  "eager_per_code_one_stream_shots_per_s": round(total / ew2, 1),
-                 "batched_over_eager": round(ew2 / bw, 3),
-                 "form": "one captured graph: the three codes' launch sequences on forked library streams; "
-                         "plain = lead_decode_plain per code in turn (same compiled kernels)"}
+                 "batched_over_eager": round(ew2 / bw, 3), "fused_over_eager": round(ew2 / fw, 3),
+                 "form": "batched: one captured graph of the three codes' launch sequences on forked library "
+                         "streams; fused: one persistent Phase 1 launch draining the three codes' work queues in "
+                         "turn and one Phases 2-3 grid over all three, captured as a graph; plain = "
+                         "lead_decode_plain per code in turn (same compiled kernels)"}
         del batch
 
     # ---- serving loop: Poisson streams of host requests (copy-in, decode,

@@ -383,6 +383,42 @@ lead_status lead_batch_graph_create(const lead_batch_item *items, int32_t n_item
 lead_status lead_batch_graph_launch(lead_batch_graph *graph, void *stream);
 void lead_batch_graph_destroy(lead_batch_graph *graph);
 
+/* Fused batch: the requests of up to 8 items (codes of different sizes,
+ * check types, shot counts, priors) decoded by one persistent Phase 1
+ * launch and one Phases 2-3 launch shared by all of them, captured as a
+ * hipGraph and replayed by lead_batch_fused_launch.
+ *   Phase 1: 64-lane waves, as many as the device holds; every wave drains
+ *   the local-BP work queue of item 0 (its lanes refilled one (shot, vertex)
+ *   view at a time as their runs end, Alg. 1 Phase 1), then moves on to
+ *   item 1's queue, and so on, so no lane waits at the end of one item's
+ *   work while another's remains.
+ *   Phases 2-3: one grid holding every item's per-shot blocks (a workgroup
+ *   of the largest per-shot block size runs one block of a large code, or
+ *   several of a small one, each wave-aligned with its own LDS); the branch
+ *   on the item is uniform per workgroup.
+ * The phases are ordered by the stream (no workgroup waits on another).
+ * Outputs are those of lead_decode on each item bit for bit.  Every item's
+ * decoder must run the kernels compiled for its code (schedule specialized
+ * > 0, not fused) without OSD post-processing (LEAD_E_UNSUPPORTED
+ * otherwise); the kernels of a batch's composition (codes, check types,
+ * forms, prior modes) are compiled on first use, or ahead of time with
+ * lead_batch_fused_specialize.  The batch owns its own workspace (local
+ * posteriors and flags for every item's shots; several items may share a
+ * decoder) and reads and writes the buffers named in `items` at creation:
+ * callers refill those between launches.  Work on other streams that uses
+ * the same output buffers must be ordered by the caller. */
+typedef struct lead_batch_fused lead_batch_fused;
+lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n_items, lead_batch_fused **out);
+lead_status lead_batch_fused_launch(lead_batch_fused *fused, void *stream);
+void lead_batch_fused_destroy(lead_batch_fused *fused);
+/* Compiles (no GPU) the fused kernels of a batch composition: item i of
+ * code codes[i], check type types[i], kernel form forms[i] (as
+ * lead_schedule.specialized: 1 compressed, 2 one register per message, 3
+ * sum-product) and prior mode modes[i]; cached in the process and on disk
+ * like lead_code_specialize. */
+lead_status lead_batch_fused_specialize(const lead_code *const *codes, const lead_check_type *types,
+                                        const int32_t *forms, const lead_prior_mode *modes, int32_t n);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: a request loop with continuous batching.                          */
 /* ------------------------------------------------------------------------ */

@@ -91,7 +91,8 @@ SYMBOLS = ["lead_last_error", "lead_code_create", "lead_code_query", "lead_code_
            "lead_decode", "lead_decode_noalloc", "lead_decode_plain", "lead_syndrome", "lead_decoder_set_schedule",
            "lead_decoder_get_schedule", "lead_decoder_time_phases", "lead_decoder_phase_times",
            "lead_decoder_autotune", "lead_batch_decode", "lead_batch_graph_create",
-           "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_server_create", "lead_server_submit",
+           "lead_batch_graph_launch", "lead_batch_graph_destroy", "lead_batch_fused_create", "lead_batch_fused_launch",
+           "lead_batch_fused_destroy", "lead_batch_fused_specialize", "lead_server_create", "lead_server_submit",
            "lead_server_poll", "lead_server_wait", "lead_server_result", "lead_server_get_stats",
            "lead_server_clock_ns", "lead_server_close", "lead_server_destroy"]
 
@@ -137,6 +138,11 @@ def lib():
         L.lead_batch_graph_launch.argtypes = [P, P]
         L.lead_batch_graph_destroy.argtypes = [P]
         L.lead_batch_graph_destroy.restype = None
+        L.lead_batch_fused_create.argtypes = [C.POINTER(lead_batch_item), I32, C.POINTER(P)]
+        L.lead_batch_fused_launch.argtypes = [P, P]
+        L.lead_batch_fused_destroy.argtypes = [P]
+        L.lead_batch_fused_destroy.restype = None
+        L.lead_batch_fused_specialize.argtypes = [P, P, P, P, I32]
         L.lead_server_create.argtypes = [C.POINTER(P), I32, C.POINTER(lead_server_config), C.POINTER(P)]
         L.lead_server_submit.argtypes = [P, I32, I64, P, I64, P, C.POINTER(I64)]
         L.lead_server_poll.argtypes = [P, I64, C.POINTER(I32)]
@@ -152,7 +158,7 @@ def lib():
             if name == "lead_server_clock_ns":
                 fn.restype = C.c_int64
             elif name not in ("lead_code_destroy", "lead_decoder_destroy", "lead_last_error",
-                              "lead_batch_graph_destroy", "lead_server_destroy"):
+                              "lead_batch_graph_destroy", "lead_batch_fused_destroy", "lead_server_destroy"):
                 fn.restype = C.c_int
         _lib = L
     return _lib
@@ -505,6 +511,42 @@ class Batch:
             except Exception:
                 pass
             self._graph = None
+
+
+class FusedBatch:
+    """Several decode requests (codes, check types, shot counts, priors)
+    fused into one persistent Phase 1 launch and one Phases 2-3 launch,
+    captured as a graph (lead_batch_fused_*).  entries: (decoder, synd,
+    prior, out[, mode]) as for Batch; the buffers are bound at creation."""
+
+    def __init__(self, entries):
+        self._keep = list(entries)
+        items = (lead_batch_item * len(entries))(*[e[0].batch_item(e[1], e[2], e[3], *e[4:]) for e in entries])
+        h = C.c_void_p()
+        _check(lib().lead_batch_fused_create(items, len(entries), C.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().lead_batch_fused_launch(self._h, _stream(stream)))
+
+    @staticmethod
+    def specialize(parts):
+        """Compile ahead of time: parts = [(Code, check type, form, prior mode)]."""
+        n = len(parts)
+        codes = (C.c_void_p * n)(*[p[0]._h.value for p in parts])
+        types = np.array([p[1] for p in parts], dtype=np.int32)
+        forms = np.array([p[2] for p in parts], dtype=np.int32)
+        modes = np.array([p[3] for p in parts], dtype=np.int32)
+        _check(lib().lead_batch_fused_specialize(codes, _np_ptr(types), _np_ptr(forms), _np_ptr(modes), n))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            try:
+                _lib.lead_batch_fused_destroy(h)
+            except Exception:
+                pass
+            self._h = None
 
 
 class Server:

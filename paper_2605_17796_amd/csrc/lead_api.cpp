@@ -30,6 +30,17 @@ struct lead_batch_graph {
     hipGraphExec_t exec = nullptr;
 };
 
+struct lead_batch_fused {
+    std::shared_ptr<const lead::jit::FusedKernels> k;
+    lead::FusedArgs args{};
+    int n = 0;
+    int64_t local_waves = 0, global_wgs = 0;
+    std::vector<void *> bufs;               // per request: local posteriors, view flags
+    int64_t *counters = nullptr;            // 2 per request: queue head, local OSD list
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct lead_decoder {
     lead::Code const *code = nullptr;
     std::shared_ptr<lead::Code> keep;       // decoders keep their own copy of the tables
@@ -568,6 +579,24 @@ lead_status lead_code_specialize(const lead_code *code, lead_check_type t) {
     // the sum-product form, where a view is small enough for it
     const std::string sp = lead::jit::source(code->c, t, true);
     if (!sp.empty() && !lead::jit::compile(sp, obj, err)) return fail(LEAD_E_UNSUPPORTED, err);
+    return LEAD_OK;
+}
+
+lead_status lead_batch_fused_specialize(const lead_code *const *codes, const lead_check_type *types,
+                                        const int32_t *forms, const lead_prior_mode *modes, int32_t n) {
+    if (!codes || !types || !forms || !modes || n <= 0) return fail(LEAD_E_ARG, "bad argument");
+    std::vector<lead::jit::FusedPart> parts;
+    for (int i = 0; i < n; ++i) {
+        if (!codes[i] || (types[i] != LEAD_CHECK_Z && types[i] != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad request");
+        parts.push_back(lead::jit::FusedPart{&codes[i]->c, (int)types[i], (int)forms[i],
+                                             modes[i] == LEAD_PRIOR_PER_SHOT ? 0 : 1});
+    }
+    lead::jit::FusedKernels k;
+    std::string err;
+    const std::string src = lead::jit::fused_source(parts, k, err);
+    if (src.empty()) return fail(LEAD_E_UNSUPPORTED, err);
+    std::vector<char> obj;
+    if (!lead::jit::compile(src, obj, err)) return fail(LEAD_E_UNSUPPORTED, err);
     return LEAD_OK;
 }
 
@@ -1185,6 +1214,137 @@ lead_status lead_batch_graph_create(const lead_batch_item *items, int32_t n, voi
     }
     *out = g.release();
     return LEAD_OK;
+}
+
+lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lead_batch_fused **out) {
+    if (!out || n <= 0 || !items) return fail(LEAD_E_ARG, "bad argument");
+    *out = nullptr;
+    if (n > lead::kFusedMax)
+        return fail(LEAD_E_UNSUPPORTED, "a fused batch holds at most " + std::to_string(lead::kFusedMax) + " requests");
+    std::vector<lead::jit::FusedPart> parts;
+    int device = -1;
+    for (int i = 0; i < n; ++i) {
+        const lead_batch_item &it = items[i];
+        lead_status st = check_item(it);
+        if (st != LEAD_OK) return fail(st, "item " + std::to_string(i) + ": " + g_err);
+        if (it.shots <= 0) return fail(LEAD_E_ARG, "item " + std::to_string(i) + ": a fused request needs shots > 0");
+        const lead_decoder *d = it.decoder;
+        if (!use_spec(d))
+            return fail(LEAD_E_UNSUPPORTED, "item " + std::to_string(i) + ": the fused batch runs the kernels compiled "
+                                            "for the code (schedule specialized > 0, not fused)");
+        if (d->params.local_post || d->params.global_post)
+            return fail(LEAD_E_UNSUPPORTED, "item " + std::to_string(i) + ": OSD post-processing needs launches of its "
+                                            "own; decode this request with lead_decode or lead_batch_decode");
+        if (device < 0) device = d->device;
+        if (d->device != device) return fail(LEAD_E_ARG, "the fused batch's decoders must share one device");
+        parts.push_back(lead::jit::FusedPart{d->code, d->type, d->sched.specialized,
+                                             it.mode == LEAD_PRIOR_PER_SHOT ? 0 : 1});
+    }
+    std::string jerr;
+    auto k = lead::jit::load_fused(parts, device, jerr);
+    if (!k) return fail(LEAD_E_UNSUPPORTED, jerr);
+    std::unique_ptr<lead_batch_fused> f(new (std::nothrow) lead_batch_fused());
+    if (!f) return fail(LEAD_E_NOMEM, "out of host memory");
+    f->k = k;
+    f->n = n;
+    auto cleanup = [&](lead_batch_fused *x) {
+        for (void *b : x->bufs) (void)hipFree(b);
+        (void)hipFree(x->counters);
+    };
+    hipError_t e = hipMalloc(&f->counters, sizeof(int64_t) * 2 * n);
+    int64_t first = 0, items_total = 0;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const lead_batch_item &it = items[i];
+        lead_decoder *d = it.decoder;
+        const int D2 = d->D * d->D;
+        float *Lv = nullptr;
+        uint32_t *vflag = nullptr;
+        e = hipMalloc(&Lv, sizeof(float) * (size_t)it.shots * d->N * D2);
+        if (e == hipSuccess) f->bufs.push_back(Lv);
+        if (e == hipSuccess) e = hipMalloc(&vflag, sizeof(uint32_t) * (size_t)it.shots * d->N);
+        if (e == hipSuccess) f->bufs.push_back(vflag);
+        if (e != hipSuccess) break;
+        lead::DecodeArgs a = base_args(d);
+        a.synd = it.d_synd;
+        a.synd_words = it.synd_words;
+        a.prior = it.d_prior;
+        a.prior_mode = it.mode;
+        a.ehat = it.d_ehat;
+        a.ehat_words = it.ehat_words;
+        a.post = it.d_post;
+        a.lam_out = it.d_prior_llr;
+        a.stats = it.d_stats;
+        a.shots = it.shots;
+        a.stage = d->params.stage == LEAD_STAGE_LOCAL ? LEAD_STAGE_LOCAL : LEAD_STAGE_FULL;
+        a.global_only = d->params.stage == LEAD_STAGE_GLOBAL ? 1 : 0;
+        a.spw = k->spw[i];
+        lead::LocalArgs w{};
+        w.Lv = Lv;
+        w.vflag = vflag;
+        w.counter = f->counters + 2 * i;
+        w.osd_list = nullptr;
+        w.items = it.shots * d->N;
+        w.chunk = d->sched.local_chunk;
+        w.waves = 0;
+        if (!a.global_only) items_total += w.items;
+        f->args.it[i] = lead::FusedItem{a, w, lead::SpecArgs{d->d_pv, d->d_fown}};
+        f->args.first[i] = first;
+        const int64_t blocks = (it.shots + k->spw[i] - 1) / k->spw[i];
+        first += (blocks + k->sub[i] - 1) / k->sub[i];
+    }
+    if (e != hipSuccess) {
+        cleanup(f.get());
+        return hip_fail(e, "fused batch allocation");
+    }
+    for (int i = n; i <= lead::kFusedMax; ++i) f->args.first[i] = first;
+    f->global_wgs = first;
+    // Phase 1: as many waves as fit the device, at most one per 64 queue items
+    const int cus = items[0].decoder->cus;
+    f->local_waves = std::max<int64_t>(1, std::min<int64_t>((int64_t)k->local_waves_per_cu * cus, (items_total + 63) / 64));
+    // the launch sequence, captured once: clear the queue counters (a fill
+    // kernel), Phase 1 of every request, Phases 2-3 of every request
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = lead::launch_clear_i64(f->counters, 2 * n, cap);
+        void *args[] = {&f->args};
+        if (le == hipSuccess && items_total > 0)
+            le = hipModuleLaunchKernel(k->local, (unsigned)f->local_waves, 1, 1, 64, 1, 1, 0, cap, args, nullptr);
+        if (le == hipSuccess)
+            le = hipModuleLaunchKernel(k->global, (unsigned)f->global_wgs, 1, 1, (unsigned)k->wg, 1, 1,
+                                       (unsigned)k->lds_bytes, cap, args, nullptr);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess && le != hipSuccess) e = le;
+        f->graph = graph;
+        if (e == hipSuccess) e = hipGraphInstantiate(&f->exec, graph, nullptr, nullptr, 0);
+    }
+    if (cap) (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        if (f->exec) (void)hipGraphExecDestroy(f->exec);
+        if (f->graph) (void)hipGraphDestroy(f->graph);
+        cleanup(f.get());
+        return hip_fail(e, "fused batch capture");
+    }
+    *out = f.release();
+    return LEAD_OK;
+}
+
+lead_status lead_batch_fused_launch(lead_batch_fused *f, void *stream) {
+    if (!f || !f->exec) return fail(LEAD_E_ARG, "fused batch is NULL");
+    hipError_t e = hipGraphLaunch(f->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return LEAD_OK;
+}
+
+void lead_batch_fused_destroy(lead_batch_fused *f) {
+    if (!f) return;
+    if (f->exec) (void)hipGraphExecDestroy(f->exec);
+    if (f->graph) (void)hipGraphDestroy(f->graph);
+    for (void *b : f->bufs) (void)hipFree(b);
+    (void)hipFree(f->counters);
+    delete f;
 }
 
 lead_status lead_batch_graph_launch(lead_batch_graph *g, void *stream) {

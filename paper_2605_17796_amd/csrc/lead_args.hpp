@@ -90,6 +90,21 @@ struct PlainArgs {
     int32_t round;
 };
 
+// Arguments of the kernels fusing the decode requests of several codes into
+// one launch per phase (lead_batch_fused_*): per request its decode
+// arguments, workspace and partner tables, and for the Phases 2-3 kernel the
+// first workgroup of each request's range of the grid (first[k] .. first[k+1]).
+constexpr int kFusedMax = 8;
+struct FusedItem {
+    DecodeArgs a;
+    LocalArgs w;
+    SpecArgs x;
+};
+struct FusedArgs {
+    FusedItem it[kFusedMax];
+    int64_t first[kFusedMax + 1];
+};
+
 // Workspace of the global OSD kernel that keeps [H_t | s] in device memory
 // (codes whose rows do not fit in registers): one matrix slot per
 // workgroup, (ceil(n/64) + 1) x m words, word-major (word k of row r at

@@ -1,6 +1,7 @@
 // Run-time compilation of the specialised kernels (see lead_jit.hpp), with a
 // cache of code objects on disk.
 #include "lead_jit.hpp"
+#include "lead_args.hpp"
 
 #include <dlfcn.h>
 #include <hip/hiprtc.h>
@@ -240,17 +241,16 @@ size_t osd_big_slot_bytes(const Code &c, int t) {
     return sizeof(uint64_t) * ((size_t)(c.n + 63) / 64 + 1) * m;
 }
 
-std::string source(const Code &c, int t, bool sp) {
+namespace {
+
+// The compile-time description of check type t of code c (check masks,
+// position map, edge tables) as a struct named `name`.
+void emit_code_struct(std::ostringstream &o, const Code &c, int t, const std::string &name) {
     const TypeTables &tt = c.t[t];
     const int D = c.delta, D2 = D * D;
-    if (tt.sigma.empty() || (int)tt.sigma.size() != D2) return std::string();
-    if (sp && tt.eloc > kSumProductMaxEdges) return std::string();
     int nfix = 0;
     for (int j = 0; j < D2; ++j) nfix += tt.sigma[j] == j;
-    const int wg = workgroup_for(c.order);
-    std::ostringstream o;
-    o << "#include \"lead_spec.hpp\"\n"
-      << "struct LeadCode {\n"
+    o << "struct " << name << " {\n"
       << "    static constexpr int D = " << D << ", R = " << tt.r << ", NFIX = " << nfix << ";\n"
       << "    static constexpr bool SPLIT = " << (tt.eloc > kTwoWaveMaxEdges ? "true" : "false") << ";\n"
       << "    static constexpr int HYB = " << hybrid_degree(tt) << ";\n"
@@ -272,6 +272,19 @@ std::string source(const Code &c, int t, bool sp) {
     o << "    static constexpr int E = " << e << ";\n"
       << "    static constexpr int deg[" << tt.r << "] = {" << deg.str() << "};\n"
       << "    static constexpr int base[" << tt.r << "] = {" << base.str() << "};\n};\n";
+}
+
+}  // namespace
+
+std::string source(const Code &c, int t, bool sp) {
+    const TypeTables &tt = c.t[t];
+    const int D = c.delta, D2 = D * D;
+    if (tt.sigma.empty() || (int)tt.sigma.size() != D2) return std::string();
+    if (sp && tt.eloc > kSumProductMaxEdges) return std::string();
+    const int wg = workgroup_for(c.order);
+    std::ostringstream o;
+    o << "#include \"lead_spec.hpp\"\n";
+    emit_code_struct(o, c, t, "LeadCode");
     for (int form = kCompressed; form <= kSumProduct; ++form) {
         if ((form == kSumProduct) != sp) continue;
         if (form != kCompressed && tt.eloc > kExplicitMaxEdges) continue;
@@ -455,6 +468,117 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
 }
 
 int plain_state_words(const Code &c, int t) { return c.t[t].eloc + 4 * c.t[t].r; }
+
+namespace {
+std::map<std::pair<int, std::string>, std::shared_ptr<const FusedKernels>> g_fused;
+}
+
+std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, std::string &err) {
+    if (parts.empty() || parts.size() > (size_t)lead::kFusedMax) {
+        err = "a fused batch holds 1 to " + std::to_string(lead::kFusedMax) + " requests";
+        return std::string();
+    }
+    FusedKernels *k = &kk;
+    std::ostringstream o, structs, loc, glob;
+    o << "#include \"lead_spec.hpp\"\n";
+    std::map<std::string, std::string> names;   // struct text -> name
+    std::vector<std::string> pname;
+    bool whole_file = false;
+    for (const FusedPart &p : parts) {
+        const TypeTables &tt = p.code->t[p.t];
+        const int D2 = p.code->delta * p.code->delta;
+        if (tt.sigma.empty() || (int)tt.sigma.size() != D2 || p.form < kCompressed || p.form > kSumProduct ||
+            (p.form != kCompressed && tt.eloc > kExplicitMaxEdges) || (p.form == kSumProduct && tt.eloc > kSumProductMaxEdges)) {
+            err = "a request's code has no compiled kernels of its form";
+            return std::string();
+        }
+        std::ostringstream body;
+        emit_code_struct(body, *p.code, p.t, "@");
+        std::string text = body.str();
+        auto it = names.find(text);
+        if (it == names.end()) {
+            const std::string nm = "LeadCode" + std::to_string(names.size());
+            it = names.emplace(text, nm).first;
+            text.replace(text.find('@'), 1, nm);
+            structs << text;
+        }
+        pname.push_back(it->second);
+        const int wg = workgroup_for(p.code->order);
+        k->wg = std::max(k->wg, wg);
+        whole_file = whole_file || (p.form == kSumProduct && tt.eloc > kTwoWaveMaxEdges);
+    }
+    o << structs.str();
+    o << "extern \"C\" __global__ void __launch_bounds__(64) lead_fused_local(lead::FusedArgs f) {\n";
+    for (size_t i = 0; i < parts.size(); ++i)
+        o << "    if (!f.it[" << i << "].a.global_only) lead_spec::local_body<" << pname[i] << ", " << parts[i].pm << ", "
+          << parts[i].form << ">(f.it[" << i << "].a, f.it[" << i << "].w);\n";
+    o << "}\n";
+    o << "extern \"C\" __global__ void __launch_bounds__(" << k->wg << (whole_file ? "" : ", 2")
+      << ") lead_fused_global(lead::FusedArgs f) {\n"
+         "    extern __shared__ float lds_f[];\n"
+         "    const int64_t b = blockIdx.x;\n";
+    for (size_t i = 0; i < parts.size(); ++i) {
+        const FusedPart &p = parts[i];
+        const Code &c = *p.code;
+        const TypeTables &tt = c.t[p.t];
+        const int D2 = c.delta * c.delta, wg = workgroup_for(c.order);
+        if (k->wg % wg != 0) {
+            err = "the codes' per-shot workgroups (" + std::to_string(wg) + " and " + std::to_string(k->wg) +
+                  " lanes) do not divide one another";
+            return std::string();
+        }
+        const bool bperm = wg == 64;
+        const int spw = wg / c.order, sub = k->wg / wg;
+        int slots = 0;
+        if (!bperm && lam_lds_fits(c, p.t))
+            for (int j = 0; j < D2; ++j) slots += tt.sigma[j] >= j ? 1 : 0;
+        const bool lam_in_lds = p.form == kCompressed || (p.form == kExplicit && hybrid_degree(tt) > 0);
+        const int words = (bperm ? 0 : D2 * wg) + (lam_in_lds ? slots * wg : 0) + 9 * spw + spw * ((c.n + 31) / 32);
+        k->sub.push_back(sub);
+        k->lds_words.push_back(words);
+        k->spw.push_back(spw);
+        k->lds_bytes = std::max(k->lds_bytes, sizeof(float) * (size_t)words * sub);
+        o << "    " << (i ? "else " : "") << "if (b < f.first[" << i + 1 << "]) {\n";
+        if (sub == 1)   // the block is the workgroup: the launch's lane and LDS, as in the per-code kernel
+            o << "        const lead_spec::Blk blk{b - f.first[" << i << "], (int)threadIdx.x, lds_f};\n";
+        else
+            o << "        const int sb = (int)threadIdx.x / " << wg << ";\n"
+              << "        const lead_spec::Blk blk{(b - f.first[" << i << "]) * " << sub << " + sb, (int)threadIdx.x - sb * "
+              << wg << ", lds_f + sb * " << words << "};\n";
+        o
+          << "        lead_spec::global_body<" << pname[i] << ", " << wg << ", " << (bperm ? "true" : "false") << ", "
+          << p.form << ">(f.it[" << i << "].a, f.it[" << i << "].w, f.it[" << i << "].x, lead::PlainArgs{}, blk);\n"
+          << "    }\n";
+    }
+    o << "}\n";
+    return o.str();
+}
+
+std::shared_ptr<const FusedKernels> load_fused(const std::vector<FusedPart> &parts, int device, std::string &err) {
+    auto k = std::make_shared<FusedKernels>();
+    const std::string src = fused_source(parts, *k, err);
+    if (src.empty()) return nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_fused.find({device, src});
+        if (it != g_fused.end()) return it->second;
+    }
+    std::vector<char> obj;
+    if (!compile(src, obj, err)) return nullptr;
+    hipError_t e = hipModuleLoadData(&k->module, obj.data());
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->local, k->module, "lead_fused_local");
+    if (e == hipSuccess) e = hipModuleGetFunction(&k->global, k->module, "lead_fused_global");
+    if (e != hipSuccess) {
+        err = std::string("fused module load: ") + hipGetErrorString(e);
+        if (k->module) (void)hipModuleUnload(k->module);
+        return nullptr;
+    }
+    int nb = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->local, 64, 0) == hipSuccess && nb > 0)
+        k->local_waves_per_cu = nb;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_fused.emplace(std::make_pair(device, src), k).first->second;
+}
 
 void partner_tables(const Code &c, int t, std::vector<uint32_t> &pv, std::vector<uint64_t> &fown) {
     const TypeTables &tt = c.t[t];

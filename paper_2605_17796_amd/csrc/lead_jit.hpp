@@ -93,6 +93,32 @@ bool compile(const std::string &src, std::vector<char> &obj, std::string &err);
 // `device`), compiled and loaded on first use.
 std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, std::string &err);
 
+// One request of a fused multi-code module: its code, check type, kernel
+// form, prior mode (0 per shot, 1 per qubit) and whether it runs Phase 1.
+struct FusedPart {
+    const Code *code;
+    int t, form, pm;
+};
+// Kernels of a fused module: the Phase 1 kernel (64-lane workgroups; each
+// wave drains the queues of the requests in order) and the Phases 2-3
+// kernel (workgroups of `wg` lanes, each running sub[k] per-shot blocks of
+// request k, with lds_words[k] floats of LDS per block).
+struct FusedKernels {
+    hipModule_t module = nullptr;
+    hipFunction_t local = nullptr, global = nullptr;
+    int wg = 64;
+    std::vector<int> sub, lds_words, spw;
+    int local_waves_per_cu = 1;
+    size_t lds_bytes = 0;
+};
+// Source and kernels of the fused module of `parts` (at most
+// lead::kFusedMax), compiled and loaded on first use; nullptr with the
+// reason in err when a part has no compiled kernels of its form.
+std::shared_ptr<const FusedKernels> load_fused(const std::vector<FusedPart> &parts, int device, std::string &err);
+// The fused module's source, with its launch shape filled into `k` (no
+// compilation, no device).  Empty with the reason in err when unsupported.
+std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &k, std::string &err);
+
 // Words of check state per view the plain per-round kernels save between
 // launches, at most (an upper bound over the forms): E + 4 r.
 int plain_state_words(const Code &c, int t);

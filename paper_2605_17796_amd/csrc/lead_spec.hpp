@@ -943,10 +943,10 @@ __device__ __forceinline__ void partner_all(const float (&X)[C::D * C::D], float
 }
 
 template <class C, int WG, bool BPERM>
-__device__ __forceinline__ void store_all(const float (&X)[C::D * C::D], float *buf) {
+__device__ __forceinline__ void store_all(const float (&X)[C::D * C::D], float *buf, int tid) {
     if (!BPERM) {
 #pragma unroll
-        for (int j = 0; j < C::D * C::D; ++j) buf[j * WG + threadIdx.x] = X[j];
+        for (int j = 0; j < C::D * C::D; ++j) buf[j * WG + tid] = X[j];
         __syncthreads();
     }
 }
@@ -969,7 +969,7 @@ template <class C, bool BPERM, int FORM>
 constexpr bool lam_in_lds() { return !BPERM && C::LAM_LDS && (FORM == 1 || (FORM == 2 && C::HYB > 0)); }
 
 // Phases 2-3 of `spw` shots per workgroup after the Phase 1 queue kernel;
-// lane (slot, v) holds vertex v of shot blockIdx.x * spw + slot.  The same
+// lane (slot, v) holds vertex v of shot blk.index * spw + slot.  The same
 // computation as the precompiled split kernel: lambda' of every qubit from
 // its two clamped local posteriors, then global min-sum rounds in which each
 // view forms its partial sum P_j (lambda' on owned positions, then its
@@ -980,9 +980,25 @@ constexpr bool lam_in_lds() { return !BPERM && C::LAM_LDS && (FORM == 1 || (FORM
 // launches, the same arithmetic in the same order (outputs identical bit for
 // bit); a shot writes its outputs in the launch where its run ends, and the
 // launch of round Tg + 1 ends the shots that ran to the cap.
+// The block a call of global_body decodes: its index in the code's grid of
+// per-shot blocks, the lane within it, and its LDS.  A kernel launched for
+// one code uses the launch's block (of_launch); a kernel fusing several
+// codes runs several blocks of a code with a smaller block in one workgroup
+// (one per wave or group of waves), each with its own LDS region.
+struct Blk {
+    int64_t index;
+    int tid;
+    float *lds;
+    __device__ static Blk of_launch() {
+        extern __shared__ float lds_launch[];
+        return Blk{(int64_t)blockIdx.x, (int)threadIdx.x, lds_launch};
+    }
+};
+
 template <class C, int WG, bool BPERM, int FORM, bool PLAIN = false>
 __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x,
-                                            const lead::PlainArgs &pl = lead::PlainArgs{}) {
+                                            const lead::PlainArgs &pl = lead::PlainArgs{},
+                                            const Blk blk = Blk::of_launch()) {
     constexpr int D2 = C::D * C::D;
     constexpr int NP = (D2 + 1) / 2;                          // words of the host's 16-bit table
     constexpr int NW = PartnerAddr<BPERM, WG>::template words<D2>();  // words of the packed addresses
@@ -991,23 +1007,23 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     // rounds, not in VGPRs (two waves per SIMD)
     constexpr bool LAML = lam_in_lds<C, BPERM, FORM>();
     constexpr int NO = LAML ? owner_slots<C>() : 0;
-    extern __shared__ float lds[];
+    float *lds = blk.lds;
     float *buf = lds;
     float *laml = lds + (BPERM ? 0 : D2 * WG);
     int *shf = reinterpret_cast<int *>(lds + (BPERM ? 0 : D2 * WG) + NO * WG);
     const int ew32 = (a.n + 31) >> 5;
     uint32_t *ebits = reinterpret_cast<uint32_t *>(shf + a.spw * SF_STRIDE);
-    const int tid = threadIdx.x;
+    const int tid = blk.tid;
     const int sl = tid / a.N, v = tid - sl * a.N;
     const bool lane_ok = sl < a.spw;
-    const int64_t shot = (int64_t)blockIdx.x * a.spw + sl;
+    const int64_t shot = blk.index * a.spw + sl;
     bool live = lane_ok && shot < a.shots;
     if constexpr (PLAIN) {
         // a shot whose run ended in an earlier launch is left alone (with
         // one shot per workgroup the whole workgroup leaves)
         if (pl.round > 1) {
             if constexpr (!BPERM) {
-                const int64_t ws = (int64_t)blockIdx.x * a.spw;
+                const int64_t ws = blk.index * a.spw;
                 if (ws >= a.shots || pl.ended[ws] != 0) return;
             }
             if (live && pl.ended[shot] != 0) live = false;
@@ -1076,7 +1092,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             lam[j] = live ? (a.prior_mode == 0 ? a.prior[shot] : a.prior[base + a.view[v * D2 + j]]) + 0.f : 0.f;
     } else {
         float Lp[D2];
-        store_all<C, WG, BPERM>(S, buf);
+        store_all<C, WG, BPERM>(S, buf, tid);
         partner_all<C, WG, BPERM, NW>(S, Lp, buf, pa);
 #pragma unroll
         for (int j = 0; j < D2; ++j) lam[j] = aggregate_llr(clampf(S[j], a.clampv), clampf(Lp[j], a.clampv), a.alpha, a.clampv);
@@ -1222,7 +1238,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             // across the loop
 #pragma unroll
             for (int k = 0; k < NW; ++k) asm volatile("" : "+v"(pa[k]));
-            store_all<C, WG, BPERM>(S, buf);
+            store_all<C, WG, BPERM>(S, buf, tid);
             static_for<0, (D2 + 15) / 16>([&](auto qq) {
                 constexpr int j0 = 16 * decltype(qq)::value;
                 float Q[16];
