@@ -265,6 +265,40 @@ def request_mix(torch, decs_named, n_requests, seed, codes):
     return reqs
 
 
+def osd_only():
+    """LEAD followed by global OSD-0 and by the order-3 sweep, one decode
+    each after a warm-up, on the A5 headline batch (rows of H in registers)
+    and on PSL(2,7) X errors at depolarising p = 0.03 (matrix in device
+    memory); prints the time and the shots OSD resolved."""
+    import torch
+    import paper_2605_17796_amd as P
+    from lead_inputs import channel_llr, standard
+    from lead_inputs.noise_device import depolarizing_packed_device
+    torch.cuda.set_device(0)
+    res = {}
+    for name, shots in (("M", SHOTS), ("L", 20_000)):
+        code = P.Code.from_spec(standard(name))
+        for order in (0, 3):
+            dec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS[name], max_iter_global=ROUNDS[name],
+                            global_post=1, osd_order=order)
+            if name == "M":
+                synd = syndromes(torch, dec, code.n, shots, P_FLIP, seed=1000)
+                lam = torch.full((shots,), float(channel_llr(P_FLIP)), dtype=torch.float32, device="cuda")
+            else:
+                xs, _ = depolarizing_packed_device(shots, code.n, 0.03, seed=3000)
+                synd = dec.syndrome(xs)
+                lam = torch.full((shots,), float(channel_llr(0.02)), dtype=torch.float32, device="cuda")
+            out = dec.alloc_outputs(shots)
+            dec.decode(synd[:256], lam[:256], out={k: (v[:256] if v is not None else None) for k, v in out.items()})
+            w, _ = timed(torch, lambda i: dec.decode(synd, lam, out=out), 1)
+            st = out["stats"].cpu().numpy()
+            res[f"{name}_order{order}"] = {"shots": shots, "ms": round(w * 1e3, 3),
+                                           "resolved_by_osd": int((st[:, 0] == 2).sum()),
+                                           "form": dec.get_schedule()["global_osd_form"]}
+            del dec, out
+    print(json.dumps({"osd_only": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,9 +325,15 @@ def main():
                          "code (p = 0.03, 64 + 64 rounds, 5*10^4 shots)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--osd-only", action="store_true",
+                    help="only decodes with global OSD (OSD-0, then the order-3 sweep): A5 headline batch, and "
+                         "PSL(2,7) depolarising p = 0.03 (X part, 2*10^4 shots), for profilers")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.osd_only:
+        osd_only()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); shots are independent, "
