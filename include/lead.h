@@ -322,6 +322,20 @@ typedef struct {
                                      per compute unit); 0: 1 where it fits, else
                                      2.  Same outputs.  Reads back as the form
                                      in use (2 where 1 does not fit). */
+    int32_t global_tiles;         /* Phases 2-3 kernel of the compiled min-sum
+                                     forms for codes of more than 64 views
+                                     (views spanning several waves):
+                                     1: persistent workgroups of 512 lanes
+                                     (eight waves, two per SIMD), each holding
+                                     floor(512 / views) shots and taking the
+                                     next shot from a device counter when one
+                                     ends (compiled where that many shots fit
+                                     in LDS, at least two); 2: one workgroup
+                                     of whole waves per shot.  0: 1 where
+                                     compiled.  Same outputs bit for bit.
+                                     Reads back as the kernel in use (0 for
+                                     codes of at most 64 views, which run
+                                     whole shots in one wave). */
 } lead_schedule;
 lead_status lead_decoder_set_schedule(lead_decoder *dec, const lead_schedule *schedule);
 lead_status lead_decoder_get_schedule(const lead_decoder *dec, lead_schedule *schedule);

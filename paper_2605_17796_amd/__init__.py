@@ -56,7 +56,7 @@ class lead_params(C.Structure):
 class lead_schedule(C.Structure):
     _fields_ = [("shots_per_workgroup", C.c_int32), ("fused", C.c_int32), ("local_chunk", C.c_int32),
                 ("local_waves", C.c_int32), ("specialized", C.c_int32), ("chunk_shots", C.c_int32),
-                ("global_osd_form", C.c_int32)]
+                ("global_osd_form", C.c_int32), ("global_tiles", C.c_int32)]
 
 
 class lead_phase_times(C.Structure):
@@ -393,9 +393,9 @@ class Decoder:
         lead_decoder_set_params(self._h, self.params)
 
     def set_schedule(self, shots_per_workgroup=0, fused=0, local_chunk=0, local_waves=0, specialized=2,
-                     chunk_shots=0, global_osd_form=0):
+                     chunk_shots=0, global_osd_form=0, global_tiles=0):
         lead_decoder_set_schedule(self._h, lead_schedule(shots_per_workgroup, fused, local_chunk, local_waves,
-                                                         specialized, chunk_shots, global_osd_form))
+                                                         specialized, chunk_shots, global_osd_form, global_tiles))
 
     def get_schedule(self) -> dict:
         sc = lead_decoder_get_schedule(self._h)

@@ -216,6 +216,13 @@ int spec_form(const lead_decoder *d, int want) {
     return d->spec->best_form();
 }
 
+// Whether the Phases 2-3 kernel of form f + 1 is the persistent one
+// (compiled for codes whose views span several waves, unless the schedule
+// asks for one workgroup per shot).
+bool use_tiles(const lead_decoder *d, int f) {
+    return d->spec && f >= 0 && f < lead::jit::kForms && d->spec->tile[f] && d->sched.global_tiles != 2;
+}
+
 // LDS bytes of the Phases 2-3 kernel compiled for the code (form f + 1).
 size_t spec_global_lds(const lead_decoder *d, int f) {
     const lead::jit::Kernels &k = *d->spec;
@@ -251,11 +258,22 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
     if (e != hipSuccess) return e;
     a.spw = k.spw;
     lead::SpecArgs x{d->d_pv, d->d_fown};
-    const size_t lds = spec_global_lds(d, f);
-    const int64_t grid = (a.shots + k.spw - 1) / k.spw;
     void *gargs[] = {&a, &w, &x};
-    e = hipModuleLaunchKernel(k.global[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
-                              nullptr);
+    if (use_tiles(d, f) && a.stage != LEAD_STAGE_LOCAL) {
+        // persistent workgroups taking shots from w.counter[3] (cleared with
+        // the queue counters before Phase 1, here when there is none)
+        if (a.global_only) e = lead::launch_reset_counter(w.counter, s);
+        const int64_t need = (a.shots + k.tile_shots - 1) / k.tile_shots;
+        const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(need, d->cus));
+        if (e == hipSuccess)
+            e = hipModuleLaunchKernel(k.tile[f], (unsigned)grid, 1, 1, (unsigned)lead::kTileWG, 1, 1,
+                                      (unsigned)k.tile_lds, s, gargs, nullptr);
+    } else {
+        const size_t lds = spec_global_lds(d, f);
+        const int64_t grid = (a.shots + k.spw - 1) / k.spw;
+        e = hipModuleLaunchKernel(k.global[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
+                                  nullptr);
+    }
     if (e == hipSuccess && ev) e = hipEventRecord((*ev)[2], s);
     return e;
 }
@@ -829,6 +847,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     if (sc->shots_per_workgroup < 0 || sc->local_chunk < 0 || sc->local_waves < 0 || sc->chunk_shots < 0)
         return fail(LEAD_E_ARG, "negative schedule field");
     if (sc->global_osd_form < 0 || sc->global_osd_form > 2) return fail(LEAD_E_ARG, "bad global_osd_form");
+    if (sc->global_tiles < 0 || sc->global_tiles > 2) return fail(LEAD_E_ARG, "bad global_tiles");
     const int spw = sc->shots_per_workgroup ? sc->shots_per_workgroup : default_spw(d->N);
     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup)
         return fail(LEAD_E_UNSUPPORTED, "shots_per_workgroup too large for the workgroup limit");
@@ -841,6 +860,7 @@ lead_status lead_decoder_set_schedule(lead_decoder *d, const lead_schedule *sc) 
     d->sched.local_waves = sc->local_waves;
     d->sched.chunk_shots = sc->chunk_shots;
     d->sched.global_osd_form = sc->global_osd_form;
+    d->sched.global_tiles = sc->global_tiles;
     d->sched.specialized = spec_form(d, sc->specialized);
     if (needs_spec(d)) {   // sum-product and OSD-0 run the kernels compiled for the code only
         d->sched.fused = 0;
@@ -857,6 +877,9 @@ lead_status lead_decoder_get_schedule(const lead_decoder *d, lead_schedule *sc) 
     if (!d || !sc) return fail(LEAD_E_ARG, "bad argument");
     *sc = d->sched;
     if (d->spec) sc->global_osd_form = osd_big(d) ? 2 : (d->spec->osd ? 1 : 0);
+    sc->global_tiles = d->spec && !d->spec->bperm && d->sched.specialized > 0
+                           ? (use_tiles(d, d->sched.specialized - 1) ? 1 : 2)
+                           : 0;
     return LEAD_OK;
 }
 
@@ -1390,13 +1413,14 @@ lead_status lead_decoder_autotune(lead_decoder *d, int64_t shots, const uint64_t
                     if (fused && chunk != 256) continue;
                     if (lead::workgroup_size(d->N, spw) > lead::kMaxWorkgroup) continue;
                     if (lead::decode_lds_bytes(d->D, lead::workgroup_size(d->N, spw), spw, d->n) > 65536) continue;
-                    cand.push_back(lead_schedule{spw, fused, chunk, 0, 0, 0, saved.global_osd_form});
+                    cand.push_back(lead_schedule{spw, fused, chunk, 0, 0, 0, saved.global_osd_form, saved.global_tiles});
                 }
         // the specialised split kernels fix their own workgroup shape
         for (int form : {lead::jit::kCompressed, lead::jit::kExplicit, lead::jit::kSumProduct})
             if (d->spec && d->spec->has[form - 1])
                 for (int chunk : {64, 256, 1024})
-                    cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, form, 0, saved.global_osd_form});
+                    cand.push_back(lead_schedule{saved.shots_per_workgroup, 0, chunk, 0, form, 0, saved.global_osd_form,
+                                                 saved.global_tiles});
         for (const lead_schedule &c : cand) {
             if (lead_decoder_set_schedule(d, &c) != LEAD_OK) continue;
             float ms_best = 1e30f;

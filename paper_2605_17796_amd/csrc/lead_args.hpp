@@ -16,6 +16,9 @@ namespace lead {
 constexpr int kMaxChecks = 16;       // checks per vertex covered by the kernels
 constexpr int kMaxOsdOrder = 8;      // largest order of the OSD combination sweep
 constexpr int kMaxOsdOrderLocal = kMaxOsdOrder;
+// Lanes of a workgroup of the persistent Phases 2-3 kernel for views that
+// span several waves (eight waves: two per SIMD).
+constexpr int kTileWG = 512;
 
 // Per-shot statistics as the kernels write them (the layout of the public
 // lead_shot_stats).
@@ -51,7 +54,8 @@ struct LocalArgs {
     float *Lv;                 // [shots][N][D2] clamped local posteriors
     uint32_t *vflag;           // [shots][N] iterations | converged << 16 | fixed point << 17
                                //            | resolved by OSD-0 << 18
-    int64_t *counter;          // [0] work-queue head, [1] entries of osd_list
+    int64_t *counter;          // [0] work-queue head, [1] entries of osd_list,
+                               // [3] next shot of the persistent Phases 2-3 kernel
     uint32_t *osd_list;        // items whose local BP missed the local syndrome (local OSD-0 pending)
     int64_t items;             // shots * N
     int32_t chunk;             // items a wave takes at a time

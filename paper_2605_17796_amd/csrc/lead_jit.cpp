@@ -129,6 +129,15 @@ std::string cache_key(const std::string &src) {
     const Rtc &r = rtc();
     if (r.ok && r.version) r.version(&ma, &mi);
     k += "hiprtc " + std::to_string(ma) + "." + std::to_string(mi) + "\n";
+    // the library file itself: builds of one version number (the system's
+    // and one bundled with another package that loaded first) generate
+    // different code
+    Dl_info info{};
+    struct stat st {};
+    if (r.ok && dladdr(reinterpret_cast<void *>(r.create), &info) && info.dli_fname &&
+        stat(info.dli_fname, &st) == 0)
+        k += std::string(info.dli_fname) + " " + std::to_string((long long)st.st_size) + " " +
+             std::to_string((long long)st.st_mtime) + "\n";
     for (int i = 0; i < kNumHeaders; ++i) {
         k += kHeaderNames[i];
         k += '\0';
@@ -221,6 +230,31 @@ bool osd_fits(const Code &c, int t) {
     return m > 0 && c.n > 0 && RPL * W <= kOsdMaxWords && RPL <= 32;
 }
 
+bool tile_fits(const Code &c, int t) {
+    const int D2 = c.delta * c.delta;
+    if (c.order <= 64 || lead::kTileWG / c.order < 2 || (int)c.t[t].sigma.size() != D2) return false;
+    // a slot's e_hat bitmap and words live at its lane offset
+    if ((c.n + 31) / 32 > c.order || c.order < 16) return false;
+    return tile_lds_bytes(c, t) <= 160u * 1024u;
+}
+
+size_t tile_lds_bytes(const Code &c, int t) {
+    const int D2 = c.delta * c.delta;
+    const std::vector<int> &sg = c.t[t].sigma;
+    int na = 0, nb = 0, no = 0;
+    for (int j = 0; j < D2 && j < (int)sg.size(); ++j) {
+        na += sg[j] <= j ? 1 : 0;
+        nb += sg[j] > j ? 1 : 0;
+        no += sg[j] >= j ? 1 : 0;
+    }
+    const size_t rows = (size_t)std::max(na, nb) + no;   // exchange and lambda' rows
+    const size_t npw = (size_t)(D2 + 15) / 16 * 4;       // partner-table words per view
+    // rows, the slots' words (16 beyond the workgroup), four control words,
+    // the e_hat bitmaps, the partner tables
+    return rows * lead::kTileWG * 4 + (size_t)(lead::kTileWG + 16) * 4 + 4 * 4 + (size_t)lead::kTileWG * 4 +
+           (size_t)c.order * npw * 4;
+}
+
 int osd_workgroup(const Code &c, int t) {
     const int m = c.order * c.t[t].r, RPL = (m + 255) / 256;
     return 64 * ((m + 64 * RPL - 1) / (64 * RPL));
@@ -253,6 +287,7 @@ void emit_code_struct(std::ostringstream &o, const Code &c, int t, const std::st
     o << "struct " << name << " {\n"
       << "    static constexpr int D = " << D << ", R = " << tt.r << ", NFIX = " << nfix << ";\n"
       << "    static constexpr bool SPLIT = " << (tt.eloc > kTwoWaveMaxEdges ? "true" : "false") << ";\n"
+
       << "    static constexpr int HYB = " << hybrid_degree(tt) << ";\n"
       << "    static constexpr bool LAM_LDS = " << (lam_lds_fits(c, t) ? "true" : "false") << ";\n"
       << "    static constexpr uint64_t mask[" << tt.r << "] = {";
@@ -309,6 +344,11 @@ std::string source(const Code &c, int t, bool sp) {
           << ") lead_spec_global_" << form
           << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_body<LeadCode, " << wg
           << ", " << (wg == 64 ? "true" : "false") << ", " << form << ">(a, w, x); }\n";
+        // the persistent form for views spanning several waves
+        if (form != kSumProduct && tile_fits(c, t))
+            o << "extern \"C\" __global__ void __launch_bounds__(" << lead::kTileWG << ") lead_spec_tile_" << form
+              << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_tile_body<LeadCode, "
+              << form << ">(a, w, x); }\n";
         // the plain per-round form of the same kernel
         o << "extern \"C\" __global__ void __launch_bounds__(" << wg
           << (whole_file ? "" : ", 2")
@@ -427,6 +467,8 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
             e = hipModuleGetFunction(&k->local[form - 1][pm], k->module, ("lead_spec_local_" + f + std::to_string(pm)).c_str());
         if (e == hipSuccess) e = hipModuleGetFunction(&k->global[form - 1], k->module, ("lead_spec_global_" + f).c_str());
         if (e == hipSuccess) e = hipModuleGetFunction(&k->round[form - 1], k->module, ("lead_spec_round_" + f).c_str());
+        if (e == hipSuccess && form != kSumProduct && tile_fits(c, t))
+            e = hipModuleGetFunction(&k->tile[form - 1], k->module, ("lead_spec_tile_" + f).c_str());
         if (e == hipSuccess) k->has[form - 1] = true;
         for (int pm = 0; pm < 2 && e == hipSuccess; ++pm) {
             int nb = 0;
@@ -453,6 +495,10 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
     }
     k->wg = workgroup_for(c.order);
     k->spw = k->wg / c.order;
+    if (tile_fits(c, t)) {
+        k->tile_shots = lead::kTileWG / c.order;
+        k->tile_lds = tile_lds_bytes(c, t);
+    }
     k->bperm = k->wg == 64;
     k->hybrid = hybrid_degree(c.t[t]) > 0;
     if (!k->bperm && lam_lds_fits(c, t)) {

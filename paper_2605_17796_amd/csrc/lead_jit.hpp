@@ -36,6 +36,14 @@ constexpr int kSumProductMaxEdges = 192;
 constexpr int kTwoWaveMaxEdges = 128;
 constexpr int kHybridExplicitEdges = 72;
 
+// The persistent Phases 2-3 kernel (lead_spec::global_tile_body) for codes
+// whose views span several waves: compiled, for the min-sum forms, where a
+// workgroup of lead::kTileWG lanes holds at least two shots and its LDS
+// (exchange rows, lambda' rows, partner tables, per-slot words and e_hat
+// bitmaps) fits the compute unit's 160 KB.
+bool tile_fits(const Code &c, int t);
+size_t tile_lds_bytes(const Code &c, int t);
+
 // The global OSD-0 kernel keeps ceil(m/256) rows of ceil(n/64) words per lane
 // in registers; it is compiled when that product is at most this.
 constexpr int kOsdMaxWords = 64;
@@ -61,6 +69,9 @@ struct Kernels {
     hipFunction_t local[kForms][2] = {};
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
     hipFunction_t round[kForms] = {};    // [form - 1]: one global round (plain form)
+    hipFunction_t tile[kForms] = {};     // [form - 1]: persistent Phases 2-3 (views over several waves)
+    int tile_shots = 0;                  // shots per workgroup of `tile`
+    size_t tile_lds = 0;                 // its LDS bytes
     hipFunction_t local_osd = nullptr;   // OSD-0 on the views listed by the queue kernel
     hipFunction_t osd = nullptr;         // OSD-0 on H_t after global BP (when it fits)
     hipFunction_t osd_cs = nullptr;      // the same with the combination sweep

@@ -307,6 +307,7 @@ __global__ void clear_i64_kernel(int64_t *p, int n) {
 __global__ void reset_counter_kernel(int64_t *counter) {
     counter[0] = 0;   // work-queue head
     counter[1] = 0;   // local OSD-0 list
+    counter[3] = 0;   // next shot of the persistent Phases 2-3 kernel
 }
 
 // Phases 2-3 of a shot group (and, for SPLIT = false, Phase 1 as well: every

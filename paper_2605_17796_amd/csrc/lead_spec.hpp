@@ -145,6 +145,16 @@ struct Compressed {
 #pragma unroll
         for (int c = 0; c < R; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
     }
+    // clear() where z holds, by selects (no branch around the state)
+    __device__ __forceinline__ void reset_where(bool z) {
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            m1[c] = z ? 0.f : m1[c];
+            m2[c] = z ? 0.f : m2[c];
+            am[c] = z ? 0u : am[c];
+            q[c] = z ? 0u : q[c];
+        }
+    }
     // Check update of every check of the view from the sums S of the
     // previous iteration.  Returns whether [S_j < 0] satisfies every check;
     // `same` tells whether every outgoing message is unchanged bit for bit.
@@ -284,6 +294,10 @@ struct Explicit {
 #pragma unroll
         for (int e = 0; e < E; ++e) m[e] = 0.f;
     }
+    __device__ __forceinline__ void reset_where(bool z) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) m[e] = z ? 0.f : m[e];
+    }
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
         bool sat = true;
@@ -348,6 +362,17 @@ struct Hybrid {
         for (int e = 0; e < EX; ++e) m[e] = 0.f;
 #pragma unroll
         for (int c = 0; c < NC; ++c) { m1[c] = 0.f; m2[c] = 0.f; am[c] = 0u; q[c] = 0u; }
+    }
+    __device__ __forceinline__ void reset_where(bool z) {
+#pragma unroll
+        for (int e = 0; e < EX; ++e) m[e] = z ? 0.f : m[e];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            m1[c] = z ? 0.f : m1[c];
+            m2[c] = z ? 0.f : m2[c];
+            am[c] = z ? 0u : am[c];
+            q[c] = z ? 0u : q[c];
+        }
     }
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
@@ -1305,6 +1330,373 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             s.global_fixed_iter = gfix;
             reinterpret_cast<lead::ShotStats *>(a.stats)[shot] = s;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phases 2-3 for views that span several waves, as a persistent kernel: a
+// workgroup of kTileWG lanes (eight waves, two per SIMD) holds K = kTileWG / N
+// shots at once (three PSL(2,7) shots on 504 of its 512 lanes), and each of
+// its K slots takes the next shot from a device counter (w.counter[3]) as soon
+// as its shot ends, so that the SIMDs carry equal numbers of waves and no
+// lane waits for another shot's run to end.  Each shot goes through the
+// operations of global_body in the same order (outputs identical bit for
+// bit); only the partner exchange is staged in two steps:
+//   A: a view publishes its value at the positions with sigma[j] <= j, and at
+//      the positions with sigma[j] >= j combines its own value with the
+//      partner's (a round: S_j = P_j + P'_{sigma j}, global_body's sum);
+//   B: it publishes the combined values at the positions with sigma[j] > j,
+//      which the partner copies into its positions with sigma[j] < j (for a
+//      round the same sum with the operands swapped: IEEE addition is
+//      commutative; for Phase 2, lambda' is symmetric in its two operands).
+// The exchange buffer then holds half of the positions, which leaves LDS for
+// lambda' of the positions with sigma[j] >= j.  Every lane executes every
+// step of the loop, with or without a shot, and S and the check state are
+// replaced by selects only, never under a branch (which would keep two
+// copies of them live).
+
+template <class C>
+constexpr int tile_rank_a(int j) {   // rank of j among the positions published in step A
+    int n = 0;
+    for (int i = 0; i < j; ++i) n += C::sigma[i] <= i ? 1 : 0;
+    return n;
+}
+template <class C>
+constexpr int tile_rank_b(int j) {   // ... in step B
+    int n = 0;
+    for (int i = 0; i < j; ++i) n += C::sigma[i] > i ? 1 : 0;
+    return n;
+}
+template <class C>
+constexpr int tile_buf_slots() {
+    constexpr int D2 = C::D * C::D;
+    return tile_rank_a<C>(D2) > tile_rank_b<C>(D2) ? tile_rank_a<C>(D2) : tile_rank_b<C>(D2);
+}
+
+__device__ __forceinline__ float lds_at(const float *buf, uint32_t byte_off) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(buf) + byte_off);
+}
+
+// Partner values for the positions of one exchange step, B at a time:
+// f(Int<j>, q) for each position j with STEP's reading rule (A: sigma[j] >=
+// j, from row tile_rank_a(sigma[j]); B: sigma[j] < j, from row
+// tile_rank_b(sigma[j])).  The partner views of the lane's view (8 bits per
+// position, the same for every slot) are read from LDS a 16-byte row per
+// sixteen positions, so they hold no registers between exchanges.
+template <class C, int WG, bool STEP_A, int B = 16, class F>
+__device__ __forceinline__ void tile_read(const float *buf, const uint4 *pv4, uint32_t base4, const F &f) {
+    constexpr int D2 = C::D * C::D;
+    static_assert(16 % B == 0, "batches within a 16-position row of the partner table");
+    static_for<0, (D2 + B - 1) / B>([&](auto qq) {
+        constexpr int j0 = B * decltype(qq)::value;
+        const uint4 pw = pv4[j0 / 16];
+        const uint32_t pwk[4] = {pw.x, pw.y, pw.z, pw.w};
+        float Q[B];
+        static_for<0, B>([&](auto ii) {
+            constexpr int i = decltype(ii)::value, j = j0 + i;
+            if constexpr (j < D2 && ((STEP_A && C::sigma[j] >= j) || (!STEP_A && C::sigma[j] < j))) {
+                constexpr int row = STEP_A ? tile_rank_a<C>(C::sigma[j]) : tile_rank_b<C>(C::sigma[j]);
+                const uint32_t col = __builtin_amdgcn_ubfe(pwk[(j % 16) / 4], 8 * (j % 4), 8) * 4u + base4;
+                Q[i] = lds_at(buf, (uint32_t)(row * WG * 4) + col);
+            }
+        });
+        static_for<0, B>([&](auto ii) {
+            constexpr int j = j0 + decltype(ii)::value;
+            if constexpr (j < D2 && ((STEP_A && C::sigma[j] >= j) || (!STEP_A && C::sigma[j] < j)))
+                f(Int<j>{}, Q[j - j0]);
+        });
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// Per-slot words of the persistent kernel, at LDS index sl * N + word (so
+// that a lane reaches its slot's words from its slot's lane offset, with no
+// address of its own): the unsatisfied-check flags of even and odd rounds,
+// the last round that changed a message, the Phase 1 statistics, the slot's
+// round, the finished shot's global iterations, converged flag and
+// fixed-point round, the shot (low, high) and whether the slot awaits a shot.
+enum { TW_F0 = 0, TW_F1, TW_CHG, TW_ITSUM, TW_ITMAX, TW_NCONV, TW_NFIX, TW_NOSD, TW_T, TW_ITG, TW_CONV, TW_FIX,
+       TW_SHOT_LO, TW_SHOT_HI, TW_AWAIT, TW_WORDS };
+
+template <class C, int FORM>
+__device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x) {
+    constexpr int WG = lead::kTileWG;
+    constexpr int D2 = C::D * C::D, NP = (D2 + 1) / 2;
+    constexpr int NX = tile_buf_slots<C>(), NO = owner_slots<C>();
+    constexpr int NPW = (D2 + 15) / 16 * 4;   // words of a view's partner table (whole 16-byte rows)
+    // LDS: the slots' words [WG + 16], four control words ([0] a slot awaits
+    // a shot, [1] slots still decoding), the slots' e_hat bitmaps [WG]
+    // (slot sl's at sl * N; ceil(n/32) <= N words for Delta <= 8), exchange
+    // rows [NX][WG], lambda' rows [NO][WG], the partner views [N][NPW].
+    // Every region but the last starts at a compile-time offset, so that
+    // its addresses are a lane base plus an instruction's immediate offset
+    // (a region at a run-time offset would take a register per row).
+    extern __shared__ float lds_tile[];
+    constexpr int OFF_CTL = WG + 16, OFF_EB = OFF_CTL + 4, OFF_BUF = OFF_EB + WG, OFF_LAM = OFF_BUF + NX * WG,
+                  OFF_PV = OFF_LAM + NO * WG;
+    static_assert(TW_WORDS <= 16 && OFF_PV % 4 == 0, "slot words, 16-byte aligned partner tables");
+    int *sw = reinterpret_cast<int *>(lds_tile);
+    int *ctl = reinterpret_cast<int *>(lds_tile + OFF_CTL);
+    uint32_t *ebits = reinterpret_cast<uint32_t *>(lds_tile + OFF_EB);
+    float *buf = lds_tile + OFF_BUF;
+    float *laml = lds_tile + OFF_LAM;
+    uint32_t *pvt = reinterpret_cast<uint32_t *>(lds_tile + OFF_PV);
+    const int K = WG / a.N;
+    const int ew32 = (a.n + 31) >> 5;
+    const int tid = (int)threadIdx.x;
+    const int sl = tid / a.N;
+    const bool lane_ok = sl < K;
+    // the lane's slot offset sl * N (as a byte offset): the lane's view is
+    // tid - sl * N, its slot's words sw[sl * N + word], its e_hat words
+    // ebits[sl * N + word], its partner columns sl * N + partner view
+    const uint32_t base4 = (uint32_t)(sl * a.N) * 4u;
+    const int v = tid - sl * a.N;
+
+    // partner views of each view (the same for every slot and shot)
+    if (tid < a.N) {
+        uint32_t pa[NPW];
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) pa[k] = 0u;
+#pragma unroll
+        for (int j = 0; j < D2; ++j) {
+            const uint32_t vp = (x.pv[tid * NP + j / 2] >> (16 * (j & 1))) & 0xffffu;
+            pa[j / 4] |= vp << (8 * (j % 4));
+        }
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) pvt[tid * NPW + k] = pa[k];
+    }
+    // the lane's partner table, from its view (no register held for it)
+    uint64_t fown = 0;
+    if (C::NFIX && lane_ok) fown = x.fown[v];
+    for (int i = tid; i < WG + 16; i += WG) sw[i] = -1;   // no shot anywhere
+    __syncthreads();
+    if (tid == 0) {
+        ctl[0] = 1;
+        ctl[1] = K;
+    }
+    if (lane_ok && v == 0) sw[(base4 >> 2) + TW_AWAIT] = 1;
+    __syncthreads();
+    auto owned = [&](int j) { return C::sigma[j] > j || (C::sigma[j] == j && ((fown >> j) & 1ull)); };
+
+    float S[D2];
+#pragma unroll
+    for (int j = 0; j < D2; ++j) S[j] = 0.f;
+    GlobalState<C, FORM> st;
+    st.clear();
+    uint64_t sv = 0;
+    // the lane's LDS addresses are formed from ti and b4, which the loop
+    // re-reads each pass (an asm barrier), so that they are recomputed at
+    // each use (a base register plus an immediate) instead of being kept, one
+    // register per row, across the loop
+    int ti = tid;
+    uint32_t b4 = base4;
+    auto word = [&](int k) -> int & { return sw[(b4 >> 2) + k]; };
+    auto pv4 = [&]() {
+        return reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(pvt) + ((uint32_t)ti * 4u - b4) * NPW);
+    };
+    auto slot_shot = [&]() {
+        return (int64_t)(uint32_t)word(TW_SHOT_LO) | ((int64_t)word(TW_SHOT_HI) << 32);
+    };
+    for (;;) {
+        asm volatile("" : "+v"(ti), "+v"(b4));
+        // ---- slots whose shot ended take the next one (uniform: ctl[0] is
+        // read after a barrier by every lane)
+        if (ctl[0] != 0) {
+            const bool fresh = lane_ok && word(TW_AWAIT) == 1;
+            const int64_t done_shot = slot_shot();
+            if (fresh && done_shot >= 0 && done_shot < a.shots) {   // the outputs of the shot the slot finished
+                uint32_t *eb = ebits + (b4 >> 2);
+                if (a.ehat)
+                    for (int wd = v; wd < a.ehat_words; wd += a.N) {
+                        const uint64_t lo = (2 * wd < ew32) ? eb[2 * wd] : 0u;
+                        const uint64_t hi = (2 * wd + 1 < ew32) ? eb[2 * wd + 1] : 0u;
+                        a.ehat[done_shot * a.ehat_words + wd] = lo | (hi << 32);
+                    }
+                if (v == 0 && a.stats) {
+                    lead::ShotStats s = {};
+                    s.converged = word(TW_CONV);
+                    s.global_iters = word(TW_ITG);
+                    s.local_iters_sum = word(TW_ITSUM);
+                    s.local_iters_max = word(TW_ITMAX);
+                    s.local_converged_views = word(TW_NCONV);
+                    s.local_fixed_views = word(TW_NFIX);
+                    s.local_osd_views = word(TW_NOSD);
+                    s.global_fixed_iter = word(TW_FIX);
+                    reinterpret_cast<lead::ShotStats *>(a.stats)[done_shot] = s;
+                }
+            }
+            __syncthreads();
+            if (ti == 0) ctl[0] = 0;
+            if (fresh) {
+                // the slot's words up to TW_FIX cleared (round 1 next), its
+                // e_hat bitmap cleared, its next shot taken
+                if (v < TW_SHOT_LO) word(v) = v == TW_T ? 1 : 0;
+                for (int i = v; i < ew32; i += a.N) ebits[(b4 >> 2) + i] = 0u;
+                if (v == TW_SHOT_LO) {
+                    const int64_t nx =
+                        (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(w.counter + 3), 1ull);
+                    word(TW_SHOT_LO) = (int)(uint32_t)nx;
+                    word(TW_SHOT_HI) = (int)(nx >> 32);
+                    word(TW_AWAIT) = 0;
+                    if (nx >= a.shots) atomicSub(&ctl[1], 1);
+                }
+            }
+            __syncthreads();
+            int64_t shot = 0;
+            bool go = false;   // the lane takes up a new shot
+            if (fresh) {
+                shot = slot_shot();
+                go = shot < a.shots;
+            }
+            const float *in = w.Lv;
+            if (go) {
+                sv = local_syndrome(a, shot, v);
+                if (!a.global_only) {
+                    const int64_t item = shot * a.N + v;
+                    in = w.Lv + item * D2;
+                    const uint32_t f = w.vflag[item];
+                    const int it_v = (int)(f & 0xffffu);
+                    const int osd_v = (int)((f >> 18) & 1u);
+                    atomicAdd(&word(TW_ITSUM), it_v);
+                    atomicMax(&word(TW_ITMAX), it_v);
+                    atomicAdd(&word(TW_NCONV), (int)((f >> 16) & 1u) & (osd_v ^ 1));   // converged by BP
+                    if ((f >> 17) & 1u) atomicAdd(&word(TW_NFIX), 1);
+                    if (osd_v) atomicAdd(&word(TW_NOSD), 1);
+                }
+            }
+            // Phase 2: lambda' into S (from the lane's own and its partner's
+            // clamped local posteriors), or the channel prior for global BP
+            // alone
+            if (a.global_only) {
+                const int64_t pbase = a.prior_mode == 2 ? shot * a.n : 0;   // LEAD_PRIOR_FULL
+                int vb = v * D2;
+                asm volatile("" : "+v"(vb));   // the qubit ids are loaded here, not kept across the loop
+#pragma unroll
+                for (int j = 0; j < D2; ++j) {
+                    float lj = 0.f;
+                    if (go) lj = (a.prior_mode == 0 ? a.prior[shot] : a.prior[pbase + a.view[vb + j]]) + 0.f;
+                    S[j] = go ? lj : S[j];
+                }
+            } else {
+                // (eight positions at a time: the check state of the other
+                // slots' lanes is live throughout)
+                if (go)
+                    static_for<0, D2 / 8>([&](auto qq) {
+                        static_for<0, 8>([&](auto ii) {
+                            constexpr int j = 8 * decltype(qq)::value + decltype(ii)::value;
+                            if constexpr (C::sigma[j] <= j) buf[tile_rank_a<C>(j) * WG + ti] = in[j];
+                        });
+                        __builtin_amdgcn_sched_barrier(0);
+                    });
+                __syncthreads();
+                tile_read<C, WG, true, 8>(buf, pv4(), b4, [&](auto jj, float q) {
+                    constexpr int j = decltype(jj)::value;
+                    float lj = 0.f;
+                    if (go) lj = aggregate_llr(clampf(in[j], a.clampv), clampf(q, a.clampv), a.alpha, a.clampv);
+                    S[j] = go ? lj : S[j];
+                });
+                __syncthreads();
+                if (go)
+                    static_for<0, D2>([&](auto jj) {
+                        constexpr int j = decltype(jj)::value;
+                        if constexpr (C::sigma[j] > j) buf[tile_rank_b<C>(j) * WG + ti] = S[j];
+                    });
+                __syncthreads();
+                tile_read<C, WG, false, 8>(buf, pv4(), b4, [&](auto jj, float q) {
+                    constexpr int j = decltype(jj)::value;
+                    S[j] = go ? q : S[j];
+                });
+            }
+            if (go) {
+                if (a.lam_out) {
+                    int vb = v * D2;
+                    asm volatile("" : "+v"(vb));
+#pragma unroll
+                    for (int j = 0; j < D2; ++j)
+                        if (owned(j)) a.lam_out[shot * a.n + a.view[vb + j]] = S[j];
+                }
+                static_for<0, D2>([&](auto jj) {
+                    constexpr int j = decltype(jj)::value;
+                    if constexpr (C::sigma[j] >= j) laml[owner_slot<C>(j) * WG + ti] = S[j];
+                });
+            }
+            st.reset_where(go);
+        }
+        if (ctl[1] == 0) break;   // every slot has run out of shots
+
+        // ---- one global round of every slot's shot (Phase 3); the slot's
+        // round number and shot are read from its LDS words
+        bool same;
+        const bool sat = st.check(S, sv, a.beta, a.clampv, same);
+        const int64_t shot = slot_shot();
+        const bool live = lane_ok && shot >= 0 && shot < a.shots;
+        const int t = word(TW_T);
+        if (live && !sat) word(t & 1) = 1;
+        if (live && !same) word(TW_CHG) = t;
+        __syncthreads();
+        if (live) {
+            const bool shot_sat = word(t & 1) == 0, shot_same = word(TW_CHG) != t;
+            bool end = false;
+            int gconv = 0, itg = a.Tg, gfix = 0;
+            if (t > 1 && shot_sat && a.early_exit) {
+                end = true;
+                gconv = 1;
+                itg = t - 1;
+            } else if (t > a.Tg) {   // ran to the cap: S holds round Tg's sums
+                end = true;
+                gconv = shot_sat ? 1 : 0;
+            } else if (t > 1 && a.fixed_stop && shot_same) {
+                end = true;
+                gconv = shot_sat ? 1 : 0;
+                gfix = t;
+            }
+            if (end) {
+                int vb = v * D2;
+                asm volatile("" : "+v"(vb));   // the qubit ids are loaded here, not kept across the loop
+                uint32_t *eb = ebits + (b4 >> 2);
+#pragma unroll
+                for (int j = 0; j < D2; ++j)
+                    if (owned(j)) {
+                        const int qd = a.view[vb + j];
+                        if (a.post) a.post[shot * a.n + qd] = clampf(S[j], a.clampv);
+                        if (signbit_of(S[j])) atomicOr(&eb[qd >> 5], 1u << (qd & 31));
+                    }
+            }
+            if (v == 0) {
+                word((t + 1) & 1) = 0;
+                word(TW_T) = t + 1;
+                if (end) {
+                    word(TW_CONV) = gconv;
+                    word(TW_ITG) = itg;
+                    word(TW_FIX) = gfix;
+                    word(TW_AWAIT) = 1;
+                    ctl[0] = 1;
+                }
+            }
+        }
+        // partial sums of this view, then the exchange (a slot whose shot
+        // ended computes them too, unused)
+        {
+            float lr[D2];
+            static_for<0, D2>([&](auto jj) {
+                constexpr int j = decltype(jj)::value;
+                lr[j] = C::sigma[j] >= j ? laml[owner_slot<C>(j) * WG + ti] : 0.f;
+            });
+            partial_sums<C>(st, lr, fown, S);
+        }
+        static_for<0, D2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            if constexpr (C::sigma[j] <= j) buf[tile_rank_a<C>(j) * WG + ti] = S[j];
+        });
+        __syncthreads();
+        tile_read<C, WG, true>(buf, pv4(), b4, [&](auto jj, float q) { S[decltype(jj)::value] += q; });
+        __syncthreads();
+        static_for<0, D2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            if constexpr (C::sigma[j] > j) buf[tile_rank_b<C>(j) * WG + ti] = S[j];
+        });
+        __syncthreads();
+        tile_read<C, WG, false>(buf, pv4(), b4, [&](auto jj, float q) { S[decltype(jj)::value] = q; });
     }
 }
 

@@ -142,6 +142,19 @@ def test_per_shot_kernel_register_budget(name, t, tmp_path):
     for co in tmp_path.glob("*.co"):
         found.update(_kernel_notes(readelf, co))
     assert "lead_spec_global_2" in found, "lead_spec_global_2 not found in the compiled objects"
+    # the persistent Phases 2-3 kernels (views over several waves): eight
+    # waves per workgroup need 256 VGPRs at most; their round loop keeps no
+    # value in scratch memory (where form 2 on the Z-check views spills, it
+    # spills values of the once-per-shot refill and output steps)
+    if name == "L":
+        for k in ("lead_spec_tile_1", "lead_spec_tile_2"):
+            vgpr, spill, scratch = found[k]
+            print(f"{name} t={t} {k}: {vgpr} VGPRs, {spill} spilled, {scratch} B scratch")
+            assert vgpr <= 256, (k, found[k])
+            if k == "lead_spec_tile_1" or t == 1:
+                assert spill == 0 and scratch == 0, (k, found[k])
+    else:
+        assert not any(k.startswith("lead_spec_tile") for k in found), "one-wave shots need no persistent kernel"
     vgpr, spill, scratch = found["lead_spec_global_2"]
     assert vgpr <= 256 and spill == 0 and scratch == 0, found["lead_spec_global_2"]
     for k in ("lead_spec_local_20", "lead_spec_local_21"):
