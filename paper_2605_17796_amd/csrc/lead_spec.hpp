@@ -1380,16 +1380,17 @@ __device__ __forceinline__ float lds_at(const float *buf, uint32_t byte_off) {
 // Partner values for the positions of one exchange step, B at a time:
 // f(Int<j>, q) for each position j with STEP's reading rule (A: sigma[j] >=
 // j, from row tile_rank_a(sigma[j]); B: sigma[j] < j, from row
-// tile_rank_b(sigma[j])).  The partner views of the lane's view (8 bits per
-// position, the same for every slot) are read from LDS a 16-byte row per
-// sixteen positions, so they hold no registers between exchanges.
-template <class C, int WG, bool STEP_A, int B = 16, class F>
-__device__ __forceinline__ void tile_read(const float *buf, const uint4 *pv4, uint32_t base4, const F &f) {
+// tile_rank_b(sigma[j])).  pr holds the partner views of the lane's view, 8
+// bits per position, one 16-byte row per sixteen positions (read from LDS
+// by the caller ahead of the barrier before the exchange, so that they hold
+// no registers between exchanges and their latency hides behind the wait).
+template <class C, int WG, bool STEP_A, int B = 16, int NR, class F>
+__device__ __forceinline__ void tile_read(const float *buf, const uint4 (&pr)[NR], uint32_t base4, const F &f) {
     constexpr int D2 = C::D * C::D;
-    static_assert(16 % B == 0, "batches within a 16-position row of the partner table");
+    static_assert(16 % B == 0 && NR * 16 >= D2, "batches within a 16-position row of the partner table");
     static_for<0, (D2 + B - 1) / B>([&](auto qq) {
         constexpr int j0 = B * decltype(qq)::value;
-        const uint4 pw = pv4[j0 / 16];
+        const uint4 pw = pr[j0 / 16];
         const uint32_t pwk[4] = {pw.x, pw.y, pw.z, pw.w};
         float Q[B];
         static_for<0, B>([&](auto ii) {
@@ -1491,8 +1492,11 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
     int ti = tid;
     uint32_t b4 = base4;
     auto word = [&](int k) -> int & { return sw[(b4 >> 2) + k]; };
-    auto pv4 = [&]() {
-        return reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(pvt) + ((uint32_t)ti * 4u - b4) * NPW);
+    constexpr int NR = NPW / 4;   // 16-byte rows of a view's partner table
+    auto load_pv = [&](uint4 (&pr)[NR]) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(pvt) + ((uint32_t)ti * 4u - b4) * NPW);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pr[r] = p[r];
     };
     auto slot_shot = [&]() {
         return (int64_t)(uint32_t)word(TW_SHOT_LO) | ((int64_t)word(TW_SHOT_HI) << 32);
@@ -1588,8 +1592,10 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
                         });
                         __builtin_amdgcn_sched_barrier(0);
                     });
+                uint4 pr[NR];
+                load_pv(pr);
                 __syncthreads();
-                tile_read<C, WG, true, 8>(buf, pv4(), b4, [&](auto jj, float q) {
+                tile_read<C, WG, true, 8>(buf, pr, b4, [&](auto jj, float q) {
                     constexpr int j = decltype(jj)::value;
                     float lj = 0.f;
                     if (go) lj = aggregate_llr(clampf(in[j], a.clampv), clampf(q, a.clampv), a.alpha, a.clampv);
@@ -1602,7 +1608,7 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
                         if constexpr (C::sigma[j] > j) buf[tile_rank_b<C>(j) * WG + ti] = S[j];
                     });
                 __syncthreads();
-                tile_read<C, WG, false, 8>(buf, pv4(), b4, [&](auto jj, float q) {
+                tile_read<C, WG, false, 8>(buf, pr, b4, [&](auto jj, float q) {
                     constexpr int j = decltype(jj)::value;
                     S[j] = go ? q : S[j];
                 });
@@ -1633,6 +1639,13 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
         const int t = word(TW_T);
         if (live && !sat) word(t & 1) = 1;
         if (live && !same) word(TW_CHG) = t;
+        // lambda' of the owned positions for this round's partial sums, read
+        // before the barrier so that the wait covers their latency
+        float lr[D2];
+        static_for<0, D2>([&](auto jj) {
+            constexpr int j = decltype(jj)::value;
+            lr[j] = C::sigma[j] >= j ? laml[owner_slot<C>(j) * WG + ti] : 0.f;
+        });
         __syncthreads();
         if (live) {
             const bool shot_sat = word(t & 1) == 0, shot_same = word(TW_CHG) != t;
@@ -1676,27 +1689,22 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
         }
         // partial sums of this view, then the exchange (a slot whose shot
         // ended computes them too, unused)
-        {
-            float lr[D2];
-            static_for<0, D2>([&](auto jj) {
-                constexpr int j = decltype(jj)::value;
-                lr[j] = C::sigma[j] >= j ? laml[owner_slot<C>(j) * WG + ti] : 0.f;
-            });
-            partial_sums<C>(st, lr, fown, S);
-        }
+        partial_sums<C>(st, lr, fown, S);
         static_for<0, D2>([&](auto jj) {
             constexpr int j = decltype(jj)::value;
             if constexpr (C::sigma[j] <= j) buf[tile_rank_a<C>(j) * WG + ti] = S[j];
         });
+        uint4 pr[NR];
+        load_pv(pr);
         __syncthreads();
-        tile_read<C, WG, true>(buf, pv4(), b4, [&](auto jj, float q) { S[decltype(jj)::value] += q; });
+        tile_read<C, WG, true>(buf, pr, b4, [&](auto jj, float q) { S[decltype(jj)::value] += q; });
         __syncthreads();
         static_for<0, D2>([&](auto jj) {
             constexpr int j = decltype(jj)::value;
             if constexpr (C::sigma[j] > j) buf[tile_rank_b<C>(j) * WG + ti] = S[j];
         });
         __syncthreads();
-        tile_read<C, WG, false>(buf, pv4(), b4, [&](auto jj, float q) { S[decltype(jj)::value] = q; });
+        tile_read<C, WG, false>(buf, pr, b4, [&](auto jj, float q) { S[decltype(jj)::value] = q; });
     }
 }
 
