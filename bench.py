@@ -164,10 +164,10 @@ def copy_probe():
 # GPU legs
 # ---------------------------------------------------------------------------
 
-def make_decoder(P, name, max_shots):
+def make_decoder(P, name, max_shots, t=0):
     from lead_inputs import standard
     code = P.Code.from_spec(standard(name))
-    dec = P.Decoder(code, max_shots=max_shots, max_iter_local=ROUNDS[name], max_iter_global=ROUNDS[name],
+    dec = P.Decoder(code, t=t, max_shots=max_shots, max_iter_local=ROUNDS[name], max_iter_global=ROUNDS[name],
                     ms_scale=0.75, alpha=1.0)
     return code, dec
 
@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--code", choices=("M", "L"), default="M",
                     help="with --roofline-only: M = the A5 headline (p = 0.05, 50 + 50 rounds), L = the PSL(2,7) "
                          "code (p = 0.03, 64 + 64 rounds, 5*10^4 shots)")
+    ap.add_argument("--check-type", type=int, choices=(0, 1), default=0,
+                    help="with --roofline-only: the check type decoded (0: Z checks, 1: X checks)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates the HBM byte counters)")
     ap.add_argument("--osd-only", action="store_true",
@@ -346,13 +348,13 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
-    if args.code != "M" and not args.roofline_only:
-        raise SystemExit("--code selects the workload of --roofline-only")
+    if (args.code != "M" or args.check_type != 0) and not args.roofline_only:
+        raise SystemExit("--code and --check-type select the workload of --roofline-only")
     cname = args.code
     shots = args.shots if cname == "M" else min(args.shots, 50_000)
     pflip = P_FLIP if cname == "M" else 0.03
-    code, dec = make_decoder(P, cname, shots)
-    n, m = code.n, code.m()
+    code, dec = make_decoder(P, cname, shots, args.check_type)
+    n, m = code.n, code.m(args.check_type)
     info = code.info
 
     pool_batches = 4
@@ -384,7 +386,7 @@ def main():
     for i in range(rl_reps):
         dec.decode(synd_pool[i % pool_batches], lam, out=out)
         st = out["stats"].cpu().numpy()
-        a, b = edge_updates(st, info.eloc[0], info.order)
+        a, b = edge_updates(st, info.eloc[args.check_type], info.order)
         eu_local += a
         eu_global += b
     pt = dec.phase_times()
@@ -403,7 +405,8 @@ def main():
     g_bytes = global_kernel_bytes_per_shot(n, m, info.order, d2) * shots_per_launch
     hbm_gbs = g_bytes / (kern["global"]["ms_per_launch"] * 1e-3) / 1e9
     if args.roofline_only:
-        print(json.dumps({"roofline_pass": kern, "schedule": best, "code": cname, "p": pflip, "shots": shots}),
+        print(json.dumps({"roofline_pass": kern, "schedule": best, "code": cname, "check_type": args.check_type,
+                          "p": pflip, "shots": shots}),
               flush=True)
         return
     gname = f"lead_spec_global_{best.get('specialized')}"

@@ -324,12 +324,17 @@ std::string source(const Code &c, int t, bool sp) {
         if ((form == kSumProduct) != sp) continue;
         if (form != kCompressed && tt.eloc > kExplicitMaxEdges) continue;
         for (int pm = 0; pm < 2; ++pm)
-            // min-sum with one prior per shot: three waves per SIMD for
-            // views of at most kTwoWaveMaxEdges edges (the queue kernel's
-            // loads in its refill step need them; with a prior per qubit
-            // the priors would not fit)
+            // min-sum with one prior per shot: three waves per SIMD (168
+            // VGPRs) where a view's messages and sums fit them, at most
+            // kThreeWaveMaxState registers (the queue kernel's loads in its
+            // refill step need the third wave; with a prior per qubit the
+            // priors would not fit; the 77-edge A5 X-check views spill at
+            // three waves and run two)
             o << "extern \"C\" __global__ void __launch_bounds__(64"
-              << (form != kSumProduct && pm == 0 && tt.eloc <= kTwoWaveMaxEdges ? ", 3" : "")
+              << (form != kSumProduct && pm == 0 &&
+                          (form == kCompressed ? 4 * tt.r : tt.eloc) + D2 <= kThreeWaveMaxState
+                      ? ", 3"
+                      : "")
               << ") lead_spec_local_" << form << pm
               << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << form
               << ">(a, w); }\n";

@@ -34,6 +34,9 @@ constexpr int kSumProductMaxEdges = 192;
 // kHybridExplicitEdges messages in registers.  Either way it is held to two
 // waves per SIMD (256 VGPRs).
 constexpr int kTwoWaveMaxEdges = 128;
+// The Phase 1 queue kernel runs three waves per SIMD where a view's check
+// state and sums take at most this many registers.
+constexpr int kThreeWaveMaxState = 96;
 constexpr int kHybridExplicitEdges = 72;
 
 // The persistent Phases 2-3 kernel (lead_spec::global_tile_body) for codes

@@ -1031,6 +1031,12 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     // the positions a view may own (sigma[j] >= j) waits in LDS between
     // rounds, not in VGPRs (two waves per SIMD)
     constexpr bool LAML = lam_in_lds<C, BPERM, FORM>();
+    // within one wave: whether the partner addresses are unpacked each
+    // round (the check state, sums and packed addresses plus the round's
+    // temporaries would otherwise exceed 256 VGPRs; the 77-edge A5 X-check
+    // views of form 2), or kept unpacked across the loop (one instruction
+    // per position and round saved)
+    constexpr bool REUNPACK = BPERM && (FORM == 1 ? 4 * C::R : C::E) + D2 + NW + 140 > 256;
     constexpr int NO = LAML ? owner_slots<C>() : 0;
     float *lds = blk.lds;
     float *buf = lds;
@@ -1244,6 +1250,13 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             // is the same sum with the operands swapped (IEEE addition is
             // commutative)
             float Q[D2];
+            // where the view's state leaves no room for the unpacked
+            // partner addresses (one per position) across the loop, they are
+            // unpacked here each round
+            if constexpr (REUNPACK) {
+#pragma unroll
+                for (int k = 0; k < NW; ++k) asm volatile("" : "+v"(pa[k]));
+            }
             static_for<0, D2>([&](auto jj) {
                 constexpr int j = decltype(jj)::value;
                 if constexpr (C::sigma[j] >= j) Q[j] = partner<C, WG, BPERM, j>(S, buf, partner_addr<BPERM, WG, j>(pa));
