@@ -409,7 +409,12 @@ void lead_batch_graph_destroy(lead_batch_graph *graph);
  *   Phases 2-3: one grid holding every item's per-shot blocks (a workgroup
  *   of the largest per-shot block size runs one block of a large code, or
  *   several of a small one, each wave-aligned with its own LDS); the branch
- *   on the item is uniform per workgroup.
+ *   on the item is uniform per workgroup.  Items whose decoders run the
+ *   persistent Phases 2-3 kernel (lead_schedule.global_tiles, codes of more
+ *   than 64 views) get persistent 512-lane workgroups of their own in the
+ *   grid, and the other items' blocks then run eight waves to a workgroup
+ *   (where a per-shot block of another item does not divide 512 lanes, or
+ *   needs the whole register file, no item uses the persistent kernel).
  * The phases are ordered by the stream (no workgroup waits on another).
  * Outputs are those of lead_decode on each item bit for bit.  Every item's
  * decoder must run the kernels compiled for its code (schedule specialized

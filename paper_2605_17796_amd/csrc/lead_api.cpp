@@ -36,7 +36,8 @@ struct lead_batch_fused {
     int n = 0;
     int64_t local_waves = 0, global_wgs = 0;
     std::vector<void *> bufs;               // per request: local posteriors, view flags
-    int64_t *counters = nullptr;            // 2 per request: queue head, local OSD list
+    int64_t *counters = nullptr;            // 4 per request: queue head, local OSD list, -, next shot of
+                                            // the persistent Phases 2-3 kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -606,9 +607,12 @@ lead_status lead_batch_fused_specialize(const lead_code *const *codes, const lea
     std::vector<lead::jit::FusedPart> parts;
     for (int i = 0; i < n; ++i) {
         if (!codes[i] || (types[i] != LEAD_CHECK_Z && types[i] != LEAD_CHECK_X)) return fail(LEAD_E_ARG, "bad request");
+        // the persistent Phases 2-3 kernel wherever the code has it (the
+        // default schedule of a decoder)
         parts.push_back(lead::jit::FusedPart{&codes[i]->c, (int)types[i], (int)forms[i],
-                                             modes[i] == LEAD_PRIOR_PER_SHOT ? 0 : 1});
+                                             modes[i] == LEAD_PRIOR_PER_SHOT ? 0 : 1, true});
     }
+    lead::jit::settle_fused_tiles(parts);
     lead::jit::FusedKernels k;
     std::string err;
     const std::string src = lead::jit::fused_source(parts, k, err);
@@ -1261,8 +1265,11 @@ lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lea
         if (device < 0) device = d->device;
         if (d->device != device) return fail(LEAD_E_ARG, "the fused batch's decoders must share one device");
         parts.push_back(lead::jit::FusedPart{d->code, d->type, d->sched.specialized,
-                                             it.mode == LEAD_PRIOR_PER_SHOT ? 0 : 1});
+                                             it.mode == LEAD_PRIOR_PER_SHOT ? 0 : 1,
+                                             use_tiles(d, d->sched.specialized - 1) &&
+                                                 d->params.stage != LEAD_STAGE_LOCAL});
     }
+    lead::jit::settle_fused_tiles(parts);
     std::string jerr;
     auto k = lead::jit::load_fused(parts, device, jerr);
     if (!k) return fail(LEAD_E_UNSUPPORTED, jerr);
@@ -1274,7 +1281,7 @@ lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lea
         for (void *b : x->bufs) (void)hipFree(b);
         (void)hipFree(x->counters);
     };
-    hipError_t e = hipMalloc(&f->counters, sizeof(int64_t) * 2 * n);
+    hipError_t e = hipMalloc(&f->counters, sizeof(int64_t) * 4 * n);
     int64_t first = 0, items_total = 0;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         const lead_batch_item &it = items[i];
@@ -1304,7 +1311,7 @@ lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lea
         lead::LocalArgs w{};
         w.Lv = Lv;
         w.vflag = vflag;
-        w.counter = f->counters + 2 * i;
+        w.counter = f->counters + 4 * i;
         w.osd_list = nullptr;
         w.items = it.shots * d->N;
         w.chunk = d->sched.local_chunk;
@@ -1312,8 +1319,15 @@ lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lea
         if (!a.global_only) items_total += w.items;
         f->args.it[i] = lead::FusedItem{a, w, lead::SpecArgs{d->d_pv, d->d_fown}};
         f->args.first[i] = first;
-        const int64_t blocks = (it.shots + k->spw[i] - 1) / k->spw[i];
-        first += (blocks + k->sub[i] - 1) / k->sub[i];
+        if (k->tile_shots[i] > 0) {
+            // persistent workgroups taking the request's shots from its
+            // counter [3]: as many as hold them, at most one per compute unit
+            const int64_t need = (it.shots + k->tile_shots[i] - 1) / k->tile_shots[i];
+            first += std::max<int64_t>(1, std::min<int64_t>(need, d->cus));
+        } else {
+            const int64_t blocks = (it.shots + k->spw[i] - 1) / k->spw[i];
+            first += (blocks + k->sub[i] - 1) / k->sub[i];
+        }
     }
     if (e != hipSuccess) {
         cleanup(f.get());
@@ -1330,7 +1344,7 @@ lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lea
     e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = lead::launch_clear_i64(f->counters, 2 * n, cap);
+        hipError_t le = lead::launch_clear_i64(f->counters, 4 * n, cap);
         void *args[] = {&f->args};
         if (le == hipSuccess && items_total > 0)
             le = hipModuleLaunchKernel(k->local, (unsigned)f->local_waves, 1, 1, 64, 1, 1, 0, cap, args, nullptr);

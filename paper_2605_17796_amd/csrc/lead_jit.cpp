@@ -524,6 +524,22 @@ namespace {
 std::map<std::pair<int, std::string>, std::shared_ptr<const FusedKernels>> g_fused;
 }
 
+void settle_fused_tiles(std::vector<FusedPart> &parts) {
+    bool any = false, ok = true;
+    for (FusedPart &p : parts) {
+        p.tiles = p.tiles && p.form != kSumProduct && tile_fits(*p.code, p.t);
+        any = any || p.tiles;
+    }
+    for (const FusedPart &p : parts) {
+        if (p.tiles) continue;
+        const TypeTables &tt = p.code->t[p.t];
+        if (lead::kTileWG % workgroup_for(p.code->order) != 0 || (p.form == kSumProduct && tt.eloc > kTwoWaveMaxEdges))
+            ok = false;
+    }
+    if (any && !ok)
+        for (FusedPart &p : parts) p.tiles = false;
+}
+
 std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, std::string &err) {
     if (parts.empty() || parts.size() > (size_t)lead::kFusedMax) {
         err = "a fused batch holds 1 to " + std::to_string(lead::kFusedMax) + " requests";
@@ -554,9 +570,21 @@ std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, 
             structs << text;
         }
         pname.push_back(it->second);
-        const int wg = workgroup_for(p.code->order);
+        if (p.tiles && (p.form == kSumProduct || !tile_fits(*p.code, p.t))) {
+            err = "a request asks for the persistent kernel its code does not have";
+            return std::string();
+        }
+        const int wg = p.tiles ? lead::kTileWG : workgroup_for(p.code->order);
         k->wg = std::max(k->wg, wg);
         whole_file = whole_file || (p.form == kSumProduct && tt.eloc > kTwoWaveMaxEdges);
+    }
+    // a module with persistent workgroups runs eight waves per workgroup,
+    // one workgroup per compute unit (two waves per SIMD)
+    bool any_tiles = false;
+    for (const FusedPart &p : parts) any_tiles = any_tiles || p.tiles;
+    if (any_tiles && whole_file) {
+        err = "the persistent kernel and a whole-register-file kernel cannot share a workgroup shape";
+        return std::string();
     }
     o << structs.str();
     o << "extern \"C\" __global__ void __launch_bounds__(64) lead_fused_local(lead::FusedArgs f) {\n";
@@ -564,7 +592,7 @@ std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, 
         o << "    if (!f.it[" << i << "].a.global_only) lead_spec::local_body<" << pname[i] << ", " << parts[i].pm << ", "
           << parts[i].form << ">(f.it[" << i << "].a, f.it[" << i << "].w);\n";
     o << "}\n";
-    o << "extern \"C\" __global__ void __launch_bounds__(" << k->wg << (whole_file ? "" : ", 2")
+    o << "extern \"C\" __global__ void __launch_bounds__(" << k->wg << (whole_file || any_tiles ? "" : ", 2")
       << ") lead_fused_global(lead::FusedArgs f) {\n"
          "    extern __shared__ float lds_f[];\n"
          "    const int64_t b = blockIdx.x;\n";
@@ -573,6 +601,19 @@ std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, 
         const Code &c = *p.code;
         const TypeTables &tt = c.t[p.t];
         const int D2 = c.delta * c.delta, wg = workgroup_for(c.order);
+        if (p.tiles) {
+            // the whole workgroup, persistent, for this request
+            k->sub.push_back(1);
+            k->lds_words.push_back(0);
+            k->spw.push_back(1);
+            k->tile_shots.push_back(lead::kTileWG / c.order);
+            k->lds_bytes = std::max(k->lds_bytes, tile_lds_bytes(c, p.t));
+            o << "    " << (i ? "else " : "") << "if (b < f.first[" << i + 1 << "]) {\n"
+              << "        lead_spec::global_tile_body<" << pname[i] << ", " << p.form << ">(f.it[" << i << "].a, f.it["
+              << i << "].w, f.it[" << i << "].x);\n"
+              << "    }\n";
+            continue;
+        }
         if (k->wg % wg != 0) {
             err = "the codes' per-shot workgroups (" + std::to_string(wg) + " and " + std::to_string(k->wg) +
                   " lanes) do not divide one another";
@@ -588,6 +629,7 @@ std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, 
         k->sub.push_back(sub);
         k->lds_words.push_back(words);
         k->spw.push_back(spw);
+        k->tile_shots.push_back(0);
         k->lds_bytes = std::max(k->lds_bytes, sizeof(float) * (size_t)words * sub);
         o << "    " << (i ? "else " : "") << "if (b < f.first[" << i + 1 << "]) {\n";
         if (sub == 1)   // the block is the workgroup: the launch's lane and LDS, as in the per-code kernel

@@ -112,19 +112,26 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
 struct FusedPart {
     const Code *code;
     int t, form, pm;
+    bool tiles;   // Phases 2-3 as the persistent kernel (lead_spec::global_tile_body)
 };
 // Kernels of a fused module: the Phase 1 kernel (64-lane workgroups; each
 // wave drains the queues of the requests in order) and the Phases 2-3
 // kernel (workgroups of `wg` lanes, each running sub[k] per-shot blocks of
-// request k, with lds_words[k] floats of LDS per block).
+// request k, with lds_words[k] floats of LDS per block, or, where
+// tile_shots[k] > 0, persistent workgroups of request k holding that many
+// shots each; those make wg = lead::kTileWG).
 struct FusedKernels {
     hipModule_t module = nullptr;
     hipFunction_t local = nullptr, global = nullptr;
     int wg = 64;
-    std::vector<int> sub, lds_words, spw;
+    std::vector<int> sub, lds_words, spw, tile_shots;
     int local_waves_per_cu = 1;
     size_t lds_bytes = 0;
 };
+// The persistent kernel for the parts that ask for it (tiles), if the module
+// can run it: every other part's per-shot workgroup divides lead::kTileWG
+// and none needs the whole register file; otherwise no part uses it.
+void settle_fused_tiles(std::vector<FusedPart> &parts);
 // Source and kernels of the fused module of `parts` (at most
 // lead::kFusedMax), compiled and loaded on first use; nullptr with the
 // reason in err when a part has no compiled kernels of its form.
