@@ -250,7 +250,8 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
         if (e != hipSuccess) return e;
         void *largs[] = {&a, &w};
         e = hipModuleLaunchKernel(k.local[f][a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1,
-                                  64, 1, 1, 0, s, largs, nullptr);
+                                  64, 1, 1, (unsigned)k.local_lds[f][a.prior_mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], s,
+                                  largs, nullptr);
         // local OSD-0 of the views the queue kernel listed (lanes stride over the list)
         if (e == hipSuccess && a.local_osd)
             e = hipModuleLaunchKernel(k.local_osd, (unsigned)(8 * d->cus), 1, 1, 64, 1, 1, 0, s, largs, nullptr);
@@ -1069,7 +1070,8 @@ hipError_t plain_spec(lead_decoder *d, int64_t shots, const uint64_t *synd, int6
             if ((e = lead::launch_reset_counter(w.counter, s)) != hipSuccess) return e;
             void *largs[] = {&a, &w};
             e = hipModuleLaunchKernel(k.local[f][mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], (unsigned)w.waves, 1, 1, 64, 1,
-                                      1, 0, s, largs, nullptr);
+                                      1, (unsigned)k.local_lds[f][mode == LEAD_PRIOR_PER_SHOT ? 0 : 1], s, largs,
+                                      nullptr);
             if (e == hipSuccess && a.local_osd)
                 e = hipModuleLaunchKernel(k.local_osd, (unsigned)(8 * d->cus), 1, 1, 64, 1, 1, 0, s, largs, nullptr);
             if (e != hipSuccess) return e;
@@ -1347,7 +1349,8 @@ lead_status lead_batch_fused_create(const lead_batch_item *items, int32_t n, lea
         hipError_t le = lead::launch_clear_i64(f->counters, 4 * n, cap);
         void *args[] = {&f->args};
         if (le == hipSuccess && items_total > 0)
-            le = hipModuleLaunchKernel(k->local, (unsigned)f->local_waves, 1, 1, 64, 1, 1, 0, cap, args, nullptr);
+            le = hipModuleLaunchKernel(k->local, (unsigned)f->local_waves, 1, 1, 64, 1, 1, (unsigned)k->local_lds, cap,
+                                       args, nullptr);
         if (le == hipSuccess)
             le = hipModuleLaunchKernel(k->global, (unsigned)f->global_wgs, 1, 1, (unsigned)k->wg, 1, 1,
                                        (unsigned)k->lds_bytes, cap, args, nullptr);

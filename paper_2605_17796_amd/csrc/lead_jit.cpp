@@ -230,6 +230,31 @@ bool osd_fits(const Code &c, int t) {
     return m > 0 && c.n > 0 && RPL * W <= kOsdMaxWords && RPL <= 32;
 }
 
+uint32_t local_lds_mask(const TypeTables &tt) {
+    if (tt.eloc <= kTwoWaveMaxEdges || tt.r > 32) return 0u;
+    // lowest degree first (ties: lowest index), until the rest fit
+    std::vector<int> order(tt.r);
+    for (int i = 0; i < tt.r; ++i) order[i] = i;
+    auto deg = [&](int i) { return __builtin_popcountll(tt.mask[i]); };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg(x) < deg(y); });
+    uint32_t m = 0u;
+    int reg = tt.eloc;
+    for (int i : order) {
+        if (reg <= kLocalRegEdges) break;
+        m |= 1u << i;
+        reg -= deg(i);
+    }
+    return m;
+}
+
+int local_lds_edges(const TypeTables &tt) {
+    const uint32_t m = local_lds_mask(tt);
+    int e = 0;
+    for (int i = 0; i < tt.r; ++i)
+        if ((m >> i) & 1u) e += __builtin_popcountll(tt.mask[i]);
+    return e;
+}
+
 bool tile_fits(const Code &c, int t) {
     const int D2 = c.delta * c.delta;
     if (c.order <= 64 || lead::kTileWG / c.order < 2 || (int)c.t[t].sigma.size() != D2) return false;
@@ -289,6 +314,7 @@ void emit_code_struct(std::ostringstream &o, const Code &c, int t, const std::st
       << "    static constexpr bool SPLIT = " << (tt.eloc > kTwoWaveMaxEdges ? "true" : "false") << ";\n"
 
       << "    static constexpr int HYB = " << hybrid_degree(tt) << ";\n"
+      << "    static constexpr unsigned LDSMASK = " << local_lds_mask(tt) << "u;\n"
       << "    static constexpr bool LAM_LDS = " << (lam_lds_fits(c, t) ? "true" : "false") << ";\n"
       << "    static constexpr uint64_t mask[" << tt.r << "] = {";
     for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";
@@ -334,7 +360,7 @@ std::string source(const Code &c, int t, bool sp) {
               << (form != kSumProduct && pm == 0 &&
                           (form == kCompressed ? 4 * tt.r : tt.eloc) + D2 <= kThreeWaveMaxState
                       ? ", 3"
-                      : "")
+                      : (form == kExplicit && pm == 0 && local_lds_mask(tt) != 0u ? ", 2" : ""))
               << ") lead_spec_local_" << form << pm
               << "(lead::DecodeArgs a, lead::LocalArgs w) { lead_spec::local_body<LeadCode, " << pm << ", " << form
               << ">(a, w); }\n";
@@ -475,9 +501,11 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
         if (e == hipSuccess && form != kSumProduct && tile_fits(c, t))
             e = hipModuleGetFunction(&k->tile[form - 1], k->module, ("lead_spec_tile_" + f).c_str());
         if (e == hipSuccess) k->has[form - 1] = true;
+        if (form == kExplicit) k->local_lds[form - 1][0] = sizeof(float) * 64 * (size_t)local_lds_edges(c.t[t]);
         for (int pm = 0; pm < 2 && e == hipSuccess; ++pm) {
             int nb = 0;
-            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->local[form - 1][pm], 64, 0) == hipSuccess &&
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k->local[form - 1][pm], 64,
+                                                                   k->local_lds[form - 1][pm]) == hipSuccess &&
                 nb > 0)
                 k->local_waves_per_cu[form - 1][pm] = nb;
         }
@@ -570,6 +598,8 @@ std::string fused_source(const std::vector<FusedPart> &parts, FusedKernels &kk, 
             structs << text;
         }
         pname.push_back(it->second);
+        if (p.form == kExplicit && p.pm == 0)
+            k->local_lds = std::max(k->local_lds, sizeof(float) * 64 * (size_t)local_lds_edges(tt));
         if (p.tiles && (p.form == kSumProduct || !tile_fits(*p.code, p.t))) {
             err = "a request asks for the persistent kernel its code does not have";
             return std::string();

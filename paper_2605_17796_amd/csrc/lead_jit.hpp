@@ -37,6 +37,14 @@ constexpr int kTwoWaveMaxEdges = 128;
 // The Phase 1 queue kernel runs three waves per SIMD where a view's check
 // state and sums take at most this many registers.
 constexpr int kThreeWaveMaxState = 96;
+// Views above kTwoWaveMaxEdges edges: the Phase 1 queue kernel of form 2
+// keeps the messages of its lowest-degree checks in LDS, so that at most
+// this many stay in registers and it runs two waves per SIMD.
+constexpr int kLocalRegEdges = 96;
+// The checks (bit c) whose messages that kernel keeps in LDS, and their
+// edges.
+uint32_t local_lds_mask(const TypeTables &tt);
+int local_lds_edges(const TypeTables &tt);
 constexpr int kHybridExplicitEdges = 72;
 
 // The persistent Phases 2-3 kernel (lead_spec::global_tile_body) for codes
@@ -90,6 +98,7 @@ struct Kernels {
                                          // (form 1, and form 2 with the mixed state)
     bool hybrid = false;                 // form 2 keeps the mixed check state
     int local_waves_per_cu[kForms][2] = {{4, 4}, {4, 4}, {4, 4}};
+    size_t local_lds[kForms][2] = {};    // [form - 1][prior mode]: LDS bytes of `local` (messages kept in LDS)
     int best_form() const { return has[2] ? kSumProduct : has[1] ? kExplicit : kCompressed; }
 };
 
@@ -125,6 +134,7 @@ struct FusedKernels {
     hipFunction_t local = nullptr, global = nullptr;
     int wg = 64;
     std::vector<int> sub, lds_words, spw, tile_shots;
+    size_t local_lds = 0;   // LDS bytes of `local` (the largest of the parts')
     int local_waves_per_cu = 1;
     size_t lds_bytes = 0;
 };

@@ -14,6 +14,9 @@
 //                   ascending within a check): their count, and per check
 //                   the degree and the number of its first edge,
 //   C::SPLIT        track the two smallest |mu| in two chains per check,
+//   C::LDSMASK      the checks whose messages the Phase 1 queue kernel of
+//                   form 2 keeps in LDS (views whose messages do not all fit
+//                   beside the sums in 256 VGPRs; 0: none),
 //   C::HYB          degree from which the per-shot kernel keeps a check's
 //                   compressed state in form 2 (0: none),
 //   C::LAM_LDS      the per-shot kernel's LDS has room for lambda' when a
@@ -433,6 +436,66 @@ struct Hybrid {
     }
 };
 
+// Phase 1 state for views whose messages do not all fit beside the sums in
+// the 256 VGPRs of two waves per SIMD: the checks in C::LDSMASK keep their
+// messages in the wave's LDS (column lane of rows lm[e * 64], e numbering
+// those checks' edges), the others one register per message.  Each check is
+// updated exactly as in Explicit (its old messages read from LDS into
+// registers, the new ones written back), so the bits do not change; the LDS
+// messages start as zeros (the caller clears its column) and stay finite.
+template <class C>
+constexpr bool in_lds(int c) { return ((C::LDSMASK >> c) & 1u) != 0; }
+template <class C>
+constexpr int split_base(int c, bool lds) {   // edges before check c in its group
+    int n = 0;
+    for (int i = 0; i < c; ++i) n += in_lds<C>(i) == lds ? C::deg[i] : 0;
+    return n;
+}
+
+template <class C>
+struct ExplicitSplit {
+    static constexpr int R = C::R;
+    static constexpr int ER = split_base<C>(C::R, false), EL = split_base<C>(C::R, true);
+    float m[ER > 0 ? ER : 1];
+    float *lm;   // this lane's LDS column
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int e = 0; e < ER; ++e) m[e] = 0.f;
+    }
+    __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
+                                          bool &same, float keep = 1.f) {
+        bool sat = true;
+        uint32_t diff = 0u;   // see Compressed::check
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if constexpr (in_lds<C>(c)) {
+                constexpr int lb = split_base<C>(c, true), DEG = C::deg[c];
+                float ml[DEG];
+                static_for<0, DEG>([&](auto kk) { ml[decltype(kk)::value] = lm[(lb + decltype(kk)::value) * 64]; });
+                explicit_update<C, c, 0, DEG>(S, sv, beta, clampv, keep, ml, sat, diff);
+                static_for<0, DEG>([&](auto kk) { lm[(lb + decltype(kk)::value) * 64] = ml[decltype(kk)::value]; });
+            } else {
+                explicit_update<C, c, split_base<C>(c, false), (ER > 0 ? ER : 1)>(S, sv, beta, clampv, keep, m, sat,
+                                                                                  diff);
+            }
+        });
+        same = diff == 0u;
+        return sat;
+    }
+    __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
+        static_for<0, R>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            for_edges<C, c>([&](auto jj, auto kk) {
+                constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
+                float mk;
+                if constexpr (in_lds<C>(c)) mk = lm[(split_base<C>(c, true) + k) * 64];
+                else mk = m[split_base<C>(c, false) + k];
+                S[j] = __builtin_fmaf(mk, keep, S[j]);
+            });
+        });
+    }
+};
+
 // Sum-product check update with one register per message (same storage and
 // fixed-point test as Explicit).  Per check: mu_k = clamp(S_j - m_k), f_k =
 // phi(|mu_k|); the message to edge k has magnitude phi(sum_{k' != k} f_k')
@@ -537,6 +600,18 @@ struct Pick<C, 3> {
 };
 template <class C, int FORM>
 using CheckState = typename Pick<C, FORM>::type;
+// The Phase 1 queue kernel's state: form 2 with one prior per shot keeps the
+// messages of the checks in C::LDSMASK in LDS (ExplicitSplit) where that
+// mask is set (with a prior per qubit the kernel runs one wave per SIMD
+// anyway).
+template <class C, int FORM, int PM, bool SPLITLDS = (FORM == 2 && PM == 0 && C::LDSMASK != 0u)>
+struct LocalPick {
+    using type = CheckState<C, FORM>;
+};
+template <class C, int FORM, int PM>
+struct LocalPick<C, FORM, PM, true> {
+    using type = ExplicitSplit<C>;
+};
 
 // The Phases 2-3 kernel keeps the mixed storage where C::HYB is set (views
 // whose one-register-per-message state would take more than half the
@@ -757,7 +832,13 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     float S[D2];
 #pragma unroll
     for (int j = 0; j < NL; ++j) lam[j] = 0.f;
-    CheckState<C, FORM> st;
+    typename LocalPick<C, FORM, PM>::type st;
+    if constexpr (FORM == 2 && PM == 0 && C::LDSMASK != 0u) {
+        extern __shared__ float lds_local[];
+        st.lm = lds_local + lane;
+#pragma unroll
+        for (int e = 0; e < ExplicitSplit<C>::EL; ++e) st.lm[e * 64] = 0.f;
+    }
     st.clear();
     float keep = 0.f;
     for (;;) {

@@ -70,3 +70,25 @@ def test_tiles_stage_global_and_fixed_point_off():
         for key in ("ehat", "post", "lam", "stats"):
             assert np.array_equal(got[key], ref[key]), (kw, key)
         log(f"[tiles] {kw}: persistent kernel equals the per-shot kernel on {shots} shots")
+
+
+@pytest.mark.parametrize("t", [0, 1])
+def test_forms_equal_on_psl27(t):
+    """Form 1 (compressed check state in both phases) and form 2 (the Phase 1
+    queue kernel with the messages of the lowest-degree checks in LDS, the
+    persistent Phases 2-3 kernel with the mixed state) give the same bits,
+    lambda' (the Phase 1 posteriors aggregated) included."""
+    import paper_2605_17796_amd as P
+    torch = torch_dev()
+    spec, oc = code_pair("L")
+    shots = 1500
+    code, dec = gpu_decoder(spec, t=t, max_iter_local=64, max_iter_global=24, max_shots=shots)
+    ps = uniform_p(shots, 0.01, 0.05, 90 + t)
+    e = bitflip_packed(shots, oc.n, ps, 90 + t)
+    synd = dec.syndrome(torch.from_numpy(e.view(np.int64)).cuda())
+    prior = torch.from_numpy(channel_llr(ps).astype(np.float32)).cuda()
+    r1 = _decode(dec, synd, prior, P.LEAD_PRIOR_PER_SHOT, 1, 1)
+    r2 = _decode(dec, synd, prior, P.LEAD_PRIOR_PER_SHOT, 1, 2)
+    for key in ("ehat", "post", "lam", "stats"):
+        assert np.array_equal(r1[key], r2[key]), key
+    log(f"[tiles] PSL(2,7) t={t}: forms 1 and 2 identical on {shots} shots (64 local rounds)")

@@ -128,9 +128,10 @@ def test_per_shot_kernel_register_budget(name, t, tmp_path):
     its Phase 1 queue kernel runs two waves per SIMD, not three), with the
     mixed check state and lambda' in LDS for the PSL(2,7)
     views (156 edges on the Z checks, 182 on the X checks).  The Phase 1 queue
-    kernels of form 2 (one register per message) use no scratch memory:
-    within 256 VGPRs for A5, within the 512 registers of one wave per SIMD
-    for PSL(2,7) (what does not fit the VGPRs goes to accumulation
+    kernels of form 2 use no scratch memory: within 256 VGPRs for A5 and,
+    with the messages of the lowest-degree checks in LDS, for PSL(2,7) with a
+    prior per shot; within the 512 registers of one wave per SIMD with a
+    prior per qubit (what does not fit the VGPRs goes to accumulation
     registers)."""
     import os, subprocess, sys
     readelf = "/opt/rocm/llvm/bin/llvm-readelf"
@@ -162,7 +163,7 @@ def test_per_shot_kernel_register_budget(name, t, tmp_path):
     for k in ("lead_spec_local_20", "lead_spec_local_21"):
         vgpr, spill, scratch = found[k]
         print(f"{name} t={t} {k}: {vgpr} VGPRs, {spill} moved to accumulation registers, {scratch} B scratch")
-        assert scratch == 0 and vgpr <= (256 if name == "M" else 512), (k, found[k])
+        assert scratch == 0 and vgpr <= (256 if name == "M" or k == "lead_spec_local_20" else 512), (k, found[k])
         if name == "M":
             assert spill == 0, (k, found[k])
     # the checks kept compressed in form 2: none for the 56- and 36-edge A5
