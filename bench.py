@@ -46,6 +46,12 @@ VALU_PEAK_GOPS = 256 * 64 * 2.4
 # Lane operations counted per edge update of min-sum (check update of one
 # edge plus its share of the variable update).
 OPS_PER_EDGE_UPDATE = 10
+# Fixed-point exit of the decoders: local BP runs only.  Ending a run whose
+# messages reproduce themselves changes no output; in Phase 1 it ends most
+# of the views that run to the cap, in global BP few runs (the A5 headline:
+# Phases 2-3 take about as long with the exit as without), and testing it
+# there costs a comparison per message and round.
+FIXED_POINT = 2
 CSRC = os.path.join(ROOT, "paper_2605_17796_amd", "csrc")
 # sources of the kernels compiled for the code (device code and its generator)
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("lead_spec.hpp", "lead_device.hpp", "lead_args.hpp", "lead_jit.cpp")]
@@ -168,7 +174,7 @@ def make_decoder(P, name, max_shots, t=0):
     from lead_inputs import standard
     code = P.Code.from_spec(standard(name))
     dec = P.Decoder(code, t=t, max_shots=max_shots, max_iter_local=ROUNDS[name], max_iter_global=ROUNDS[name],
-                    ms_scale=0.75, alpha=1.0)
+                    fixed_point_stop=FIXED_POINT, ms_scale=0.75, alpha=1.0)
     return code, dec
 
 
@@ -280,7 +286,7 @@ def osd_only():
         code = P.Code.from_spec(standard(name))
         for order in (0, 3):
             dec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS[name], max_iter_global=ROUNDS[name],
-                            global_post=1, osd_order=order)
+                            fixed_point_stop=FIXED_POINT, global_post=1, osd_order=order)
             if name == "M":
                 synd = syndromes(torch, dec, code.n, shots, P_FLIP, seed=1000)
                 lam = torch.full((shots,), float(channel_llr(P_FLIP)), dtype=torch.float32, device="cuda")
@@ -391,7 +397,8 @@ def main():
         eu_global += b
     pt = dec.phase_times()
     dec.time_phases(False)
-    dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], ms_scale=0.75, alpha=1.0)
+    dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], fixed_point_stop=FIXED_POINT,
+                   ms_scale=0.75, alpha=1.0)
     if pt["global_launches"] == 0:
         raise SystemExit(f"the schedule {best} does not run the work-queue form, which the roofline pass times")
     d2 = info.delta ** 2
@@ -409,7 +416,8 @@ def main():
                           "p": pflip, "shots": shots}),
               flush=True)
         return
-    gname = f"lead_spec_global_{best.get('specialized')}"
+    # (form 2 with the fixed-point exit off runs its variant without the test)
+    gname = f"lead_spec_global_{best.get('specialized')}" + ("n" if best.get("specialized") == 2 else "")
     lname = f"lead_spec_local_{best.get('specialized')}0"
     traffic = traffic_local = None
     issued = None
@@ -429,7 +437,8 @@ def main():
                           "achieved": round(v * 64 / (kern["global"]["ms_per_launch"] * 1e-3) / 1e12, 3),
                           "frac": round(v * 64 / (kern["global"]["ms_per_launch"] * 1e-3) / 1e9 / VALU_PEAK_GOPS, 4),
                           "per_counted_op": round(v * 64 / kern["global"]["ops_per_launch"], 3)}
-    form = {1: "compressed check state", 2: "one register per message"}.get(best.get("specialized"), "")
+    form = {1: "compressed check state",
+            2: "one register per message, no fixed-point test"}.get(best.get("specialized"), "")
     roof = {"bound": "alu", "achieved": round(kern["global"]["achieved"], 3), "peak": round(VALU_PEAK_GOPS / 1000, 2),
             "unit": "TOP/s", "frac": round(kern["global"]["frac"], 4), "traffic": traffic,
             "kernel": f"{gname} (Phases 2-3 compiled for the A5 code, {form}; {shots_per_launch:.0f} shots per launch)",
@@ -512,7 +521,7 @@ def main():
     base_leg = None
     if not args.no_baseline_decoder:
         gdec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
-                         ms_scale=0.75, alpha=1.0, stage=2)
+                         fixed_point_stop=FIXED_POINT, ms_scale=0.75, alpha=1.0, stage=2)
         gout = gdec.alloc_outputs(shots)
         gdec.decode(synd_pool[0], lam, out=gout)
         gw, _ = timed(torch, lambda i: gdec.decode(synd_pool[i % pool_batches], lam, out=gout), 2)
@@ -535,7 +544,7 @@ def main():
     if not args.no_variants:
         variants = {}
         sdec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
-                         alpha=1.0, bp=1)
+                         fixed_point_stop=FIXED_POINT, alpha=1.0, bp=1)
         sout = sdec.alloc_outputs(shots)
         sdec.decode(synd_pool[0], lam, out=sout)
         sw, _ = timed(torch, lambda i: sdec.decode(synd_pool[i % pool_batches], lam, out=sout), 2)
@@ -545,7 +554,7 @@ def main():
                                           "mean_global_iters": round(float(sst[:, 1].mean()), 2)}
         del sdec, sout
         odec = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
-                         ms_scale=0.75, alpha=1.0, local_post=1)
+                         fixed_point_stop=FIXED_POINT, ms_scale=0.75, alpha=1.0, local_post=1)
         oout = odec.alloc_outputs(shots)
         odec.decode(synd_pool[0], lam, out=oout)
         ow, _ = timed(torch, lambda i: odec.decode(synd_pool[i % pool_batches], lam, out=oout), 2)
@@ -561,7 +570,7 @@ def main():
                         ("bp_osd_cs3_A5_p005", {"stage": P.LEAD_STAGE_GLOBAL, "osd_order": 3}),
                         ("local_and_global_osd_cs3_A5_p005", {"local_post": 1, "osd_order": 3})):
             gd2 = P.Decoder(code, max_shots=shots, max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"],
-                            ms_scale=0.75, alpha=1.0, global_post=1, **kw)
+                            fixed_point_stop=FIXED_POINT, ms_scale=0.75, alpha=1.0, global_post=1, **kw)
             go2 = gd2.alloc_outputs(shots)
             gd2.decode(synd_pool[0], lam, out=go2)
             w2, _ = timed(torch, lambda i: gd2.decode(synd_pool[i % pool_batches], lam, out=go2), 2)
@@ -575,14 +584,16 @@ def main():
         lam02 = torch.full((shots,), float(channel_llr(0.02)), dtype=torch.float32, device="cuda")
         sweep = []
         for alpha in (1.0, 0.5, 0.1, 0.01):
-            dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=alpha)
+            dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], fixed_point_stop=FIXED_POINT,
+                           ms_scale=0.75, alpha=alpha)
             dec.decode(s02, lam02, out=out)
             aw, _ = timed(torch, lambda i: dec.decode(s02, lam02, out=out), 1)
             ast = out["stats"].cpu().numpy()
             sweep.append({"alpha": alpha, "shots_per_s": round(shots / aw, 1),
                           "converged": round(float(ast[:, 0].mean()), 4),
                           "mean_global_iters": round(float(ast[:, 1].mean()), 2)})
-        dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], ms_scale=0.75, alpha=1.0)
+        dec.set_params(max_iter_local=ROUNDS["M"], max_iter_global=ROUNDS["M"], fixed_point_stop=FIXED_POINT,
+                       ms_scale=0.75, alpha=1.0)
         variants["alpha_sweep_A5_p002"] = sweep
         # A5 at the four bit-flip rates of the mid-code workload (10^5 shots each)
         sweep_p = []
@@ -602,8 +613,8 @@ def main():
         from lead_inputs.noise_device import depolarizing_packed_device
         lshots = args.large_shots
         lcode = P.Code.from_spec(__import__("lead_inputs").standard("L"))
-        ldecs = [P.Decoder(lcode, t=t, max_shots=lshots, max_iter_local=ROUNDS["L"], max_iter_global=ROUNDS["L"])
-                 for t in (0, 1)]
+        ldecs = [P.Decoder(lcode, t=t, max_shots=lshots, max_iter_local=ROUNDS["L"], max_iter_global=ROUNDS["L"],
+                           fixed_point_stop=FIXED_POINT) for t in (0, 1)]
         lo_ = ldecs[0].alloc_outputs(lshots, post=False)
         dep = []
         for pi, pdep in enumerate((0.01, 0.02, 0.03, 0.04, 0.05)):
@@ -743,6 +754,8 @@ def main():
                    "shots_per_step": shots,
                    "form": "batched: captured graph of lead_decode (kernels compiled for the code), "
                            + ("schedule from --schedule" if args.schedule else "autotuned schedule"),
+                   "fixed_point_exit": {0: "off", 1: "local and global BP runs",
+                                        2: "local BP runs (outputs as without it)"}[FIXED_POINT],
                    "schedule": best},
         "roofline": roof,
         "decode_stats": {"converged": round(float((st[:, 0] == 1).mean()), 4),

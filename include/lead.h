@@ -137,7 +137,10 @@ typedef struct {
                                  themselves bit for bit (every later iteration
                                  would repeat it); results and reported
                                  iteration counts are identical to running to
-                                 the cap                                       */
+                                 the cap.  2: local BP runs only (global BP
+                                 then runs kernels without the per-message
+                                 comparison, and reports global_fixed_iter =
+                                 0).  0: off.  Other values: LEAD_E_ARG     */
     int32_t local_post;       /* 1: a local BP run that ends with H_v e_v != s_v
                                  is followed by OSD on its view (ordered
                                  statistics decoding: variables ranked by

@@ -128,6 +128,7 @@ lead_status check_params(const lead_params *p) {
     if (p->stage != LEAD_STAGE_FULL && p->stage != LEAD_STAGE_LOCAL && p->stage != LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_ARG, "bad stage");
     if (p->bp != LEAD_BP_MINSUM && p->bp != LEAD_BP_SUMPRODUCT) return fail(LEAD_E_ARG, "bad bp");
+    if (p->fixed_point_stop < 0 || p->fixed_point_stop > 2) return fail(LEAD_E_ARG, "fixed_point_stop must be 0, 1 or 2");
     if (p->local_post != 0 && p->local_post != 1) return fail(LEAD_E_ARG, "bad local_post");
     if (p->local_post && p->stage == LEAD_STAGE_GLOBAL)
         return fail(LEAD_E_UNSUPPORTED, "stage GLOBAL has no local phase to post-process");
@@ -267,14 +268,16 @@ hipError_t launch_spec(const lead_decoder *d, lead::DecodeArgs a, lead::LocalArg
         if (a.global_only) e = lead::launch_reset_counter(w.counter, s);
         const int64_t need = (a.shots + k.tile_shots - 1) / k.tile_shots;
         const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(need, d->cus));
+        // (the kernel without the fixed-point test when global BP runs without it)
+        hipFunction_t fn = !a.fixed_stop_g && k.tile_nf[f] ? k.tile_nf[f] : k.tile[f];
         if (e == hipSuccess)
-            e = hipModuleLaunchKernel(k.tile[f], (unsigned)grid, 1, 1, (unsigned)lead::kTileWG, 1, 1,
-                                      (unsigned)k.tile_lds, s, gargs, nullptr);
+            e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)lead::kTileWG, 1, 1, (unsigned)k.tile_lds, s,
+                                      gargs, nullptr);
     } else {
         const size_t lds = spec_global_lds(d, f);
         const int64_t grid = (a.shots + k.spw - 1) / k.spw;
-        e = hipModuleLaunchKernel(k.global[f], (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs,
-                                  nullptr);
+        hipFunction_t fn = !a.fixed_stop_g && k.global_nf[f] ? k.global_nf[f] : k.global[f];
+        e = hipModuleLaunchKernel(fn, (unsigned)grid, 1, 1, (unsigned)k.wg, 1, 1, (unsigned)lds, s, gargs, nullptr);
     }
     if (e == hipSuccess && ev) e = hipEventRecord((*ev)[2], s);
     return e;
@@ -347,7 +350,8 @@ lead::DecodeArgs base_args(const lead_decoder *d) {
     a.early_exit = d->params.early_exit ? 1 : 0;
     a.stage = d->params.stage;
     a.boost = d->params.boost ? 1 : 0;
-    a.fixed_stop = d->params.fixed_point_stop ? 1 : 0;
+    a.fixed_stop = d->params.fixed_point_stop != 0 ? 1 : 0;   // 1 or 2: local BP runs
+    a.fixed_stop_g = d->params.fixed_point_stop == 1 ? 1 : 0;  // 1: global BP runs too
     a.local_osd = d->params.local_post ? 1 : 0;
     a.osd_order = d->params.osd_order;
     for (int c = 0; c < lead::kMaxChecks; ++c) a.mask[c] = c < d->r ? d->mask[c] : 0;

@@ -42,7 +42,9 @@ struct DecodeArgs {
     int64_t synd_words, ehat_words;
     int32_t prior_mode, spw, N, n, r, own_max;
     float alpha, beta, clampv;
-    int32_t Tl, Tg, early_exit, stage, boost, fixed_stop;
+    int32_t Tl, Tg, early_exit, stage, boost;
+    int32_t fixed_stop;        // fixed-point exit of local BP runs (Phase 1)
+    int32_t fixed_stop_g;      // ... of global BP runs (Phase 3, global BP alone)
     int32_t global_only;       // no Phase 1; lambda' = the channel prior
     int32_t local_osd;         // OSD-0 after local BP runs that miss the local syndrome
     int32_t osd_order;         // order of the OSDs' combination sweep (0: OSD-0)

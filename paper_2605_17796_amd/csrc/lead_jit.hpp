@@ -81,6 +81,11 @@ struct Kernels {
     hipFunction_t global[kForms] = {};   // [form - 1]: Phases 2-3
     hipFunction_t round[kForms] = {};    // [form - 1]: one global round (plain form)
     hipFunction_t tile[kForms] = {};     // [form - 1]: persistent Phases 2-3 (views over several waves)
+    // [form - 1]: `global` / `tile` without the fixed-point test of global
+    // BP (no per-message comparison; compiled for the explicit form, the
+    // per-shot one only where `tile` is not)
+    hipFunction_t global_nf[kForms] = {};
+    hipFunction_t tile_nf[kForms] = {};
     int tile_shots = 0;                  // shots per workgroup of `tile`
     size_t tile_lds = 0;                 // its LDS bytes
     hipFunction_t local_osd = nullptr;   // OSD-0 on the views listed by the queue kernel

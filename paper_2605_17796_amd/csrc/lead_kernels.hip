@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(WG) decode_kernel(DecodeArgs a, LocalArgs w) {
                 done = true;
                 gconv = 1;
                 itg = t - 1;
-            } else if (a.fixed_stop && shf[L.sl * 8 + SF_CHG] != t) {
+            } else if (a.fixed_stop_g && shf[L.sl * 8 + SF_CHG] != t) {
                 // no check state of the shot changed: S stays S^{t-1} for
                 // every remaining iteration
                 done = true;
@@ -631,7 +631,7 @@ __global__ void __launch_bounds__(WG) round_kernel(RoundArgs ra) {
             if (shot_sat && a.early_exit) {
                 done = true;
                 if (L.v == 0) { stat[0] = 1; stat[1] = 1; stat[2] = t - 1; }
-            } else if (a.fixed_stop && shf[L.sl * 8 + SF_CHG] == 0) {
+            } else if (a.fixed_stop_g && shf[L.sl * 8 + SF_CHG] == 0) {
                 done = true;
                 if (L.v == 0) { stat[0] = 1; stat[1] = shot_sat ? 1 : 0; stat[2] = a.Tg; stat[3] = t; }
             }

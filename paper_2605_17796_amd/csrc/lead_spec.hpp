@@ -88,7 +88,7 @@ __device__ __forceinline__ void for_edges(const F &f) {
 // differ, both minima clamp to the same value and the position does not
 // matter) and the new min-sum state.  sat &= [S_j < 0] satisfies the check;
 // diff gains the bits that differ between the old and the new state.
-template <class C, int c>
+template <class C, int c, bool FP = true>
 __device__ __forceinline__ void compressed_update(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                                   float keep, float &m1, float &m2, uint32_t &am, uint32_t &q,
                                                   bool &sat, uint32_t &diff) {
@@ -118,16 +118,21 @@ __device__ __forceinline__ void compressed_update(const float (&S)[C::D * C::D],
     constexpr uint32_t all = (uint32_t)((1ull << C::deg[c]) - 1ull);
     uint32_t nq = flip ? (sg ^ all) : sg;
     uint32_t b1u = __float_as_uint(beta * fminf(n1, clampv)), b2u = __float_as_uint(beta * fminf(n2, clampv));
-    // every outgoing message unchanged (the position of the smallest
-    // matters only when the two magnitudes differ)
-    const uint32_t dterm = (nq ^ q) | (b1u ^ __float_as_uint(m1)) | (b2u ^ __float_as_uint(m2)) |
-                           (b1u == b2u ? 0u : nam ^ am);
-    diff |= dterm;
-    // the new state is written from operands that depend on the
-    // comparison: the old values are then dead when the new ones are
-    // written and can share their registers (no copies at the loop
-    // back-edge)
-    asm("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam) : "v"(dterm));
+    if constexpr (FP) {
+        // every outgoing message unchanged (the position of the smallest
+        // matters only when the two magnitudes differ)
+        const uint32_t dterm = (nq ^ q) | (b1u ^ __float_as_uint(m1)) | (b2u ^ __float_as_uint(m2)) |
+                               (b1u == b2u ? 0u : nam ^ am);
+        diff |= dterm;
+        // the new state is written from operands that depend on the
+        // comparison: the old values are then dead when the new ones are
+        // written and can share their registers (no copies at the loop
+        // back-edge)
+        asm("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam) : "v"(dterm));
+    } else {
+        // formed here all the same (see explicit_update)
+        asm volatile("" : "+v"(nq), "+v"(b1u), "+v"(b2u), "+v"(nam));
+    }
     q = nq;
     m1 = __uint_as_float(b1u);
     m2 = __uint_as_float(b2u);
@@ -160,7 +165,9 @@ struct Compressed {
     }
     // Check update of every check of the view from the sums S of the
     // previous iteration.  Returns whether [S_j < 0] satisfies every check;
-    // `same` tells whether every outgoing message is unchanged bit for bit.
+    // `same` tells whether every outgoing message is unchanged bit for bit
+    // (FP = false: no comparison, same = false).
+    template <bool FP = true>
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
         bool sat = true;
@@ -171,9 +178,9 @@ struct Compressed {
         uint32_t diff = 0u;
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            compressed_update<C, c>(S, sv, beta, clampv, keep, m1[c], m2[c], am[c], q[c], sat, diff);
+            compressed_update<C, c, FP>(S, sv, beta, clampv, keep, m1[c], m2[c], am[c], q[c], sat, diff);
         });
-        same = diff == 0u;
+        same = FP && diff == 0u;
         return sat;
     }
     // The state as WORDS 32-bit words at p[i * stride] (plain per-round form).
@@ -212,8 +219,12 @@ struct Compressed {
 };
 
 // Check update of check c with one register per message: the messages of
-// its edges are m[b], m[b + 1], ... (b fixed by the caller's layout).
-template <class C, int c, int b, int E>
+// its edges are m[b], m[b + 1], ... (b fixed by the caller's layout).  With
+// FP the bits that differ between each old and new message go to diff; the
+// old message is then still read after the new one is formed, so the two
+// take different registers (a copy per message at the loop back-edge).
+// Without FP the new message overwrites the old one in place.
+template <class C, int c, int b, int E, bool FP = true>
 __device__ __forceinline__ void explicit_update(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                                 float keep, float (&m)[E], bool &sat, uint32_t &diff) {
     constexpr int D2 = C::D * C::D;
@@ -275,9 +286,13 @@ __device__ __forceinline__ void explicit_update(const float (&S)[C::D * C::D], u
         constexpr int j = decltype(jj)::value, k = decltype(kk)::value;
         const uint32_t sel = fabsf(mu[j]) == n1 ? b2 : b1;
         const uint32_t nm = __builtin_amdgcn_bitop3_b32(sel, __float_as_uint(mu[j]), kSign, 0x78);   // sel ^ (mu & sign)
-        diff = __builtin_amdgcn_bitop3_b32(diff, nm, __float_as_uint(m[b + k]), 0xf6);   // diff | (nm ^ old)
+        if constexpr (FP) diff = __builtin_amdgcn_bitop3_b32(diff, nm, __float_as_uint(m[b + k]), 0xf6);   // diff | (nm ^ old)
         m[b + k] = __uint_as_float(nm);
     });
+    // without the comparison the new messages are formed here all the same
+    // (not next to their use in the partial sums, which would keep every
+    // check's mu live until then)
+    if constexpr (!FP) for_edges<C, c>([&m](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
     asm volatile("" : "+v"(diff));
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -301,15 +316,16 @@ struct Explicit {
 #pragma unroll
         for (int e = 0; e < E; ++e) m[e] = z ? 0.f : m[e];
     }
+    template <bool FP = true>
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
         bool sat = true;
         uint32_t diff = 0u;   // see Compressed::check
         static_for<0, R>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            explicit_update<C, c, C::base[c], E>(S, sv, beta, clampv, keep, m, sat, diff);
+            explicit_update<C, c, C::base[c], E, FP>(S, sv, beta, clampv, keep, m, sat, diff);
         });
-        same = diff == 0u;
+        same = FP && diff == 0u;
         return sat;
     }
     template <int c, int k>
@@ -377,6 +393,7 @@ struct Hybrid {
             q[c] = z ? 0u : q[c];
         }
     }
+    template <bool FP = true>
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
         bool sat = true;
@@ -385,12 +402,12 @@ struct Hybrid {
             constexpr int c = decltype(cc)::value;
             if constexpr (hyb_compressed<C>(c)) {
                 constexpr int i = hyb_index<C>(c);
-                compressed_update<C, c>(S, sv, beta, clampv, keep, m1[i], m2[i], am[i], q[i], sat, diff);
+                compressed_update<C, c, FP>(S, sv, beta, clampv, keep, m1[i], m2[i], am[i], q[i], sat, diff);
             } else {
-                explicit_update<C, c, hyb_base<C>(c), EX>(S, sv, beta, clampv, keep, m, sat, diff);
+                explicit_update<C, c, hyb_base<C>(c), EX, FP>(S, sv, beta, clampv, keep, m, sat, diff);
             }
         });
-        same = diff == 0u;
+        same = FP && diff == 0u;
         return sat;
     }
     static constexpr int WORDS = EX + 4 * NC;
@@ -511,6 +528,7 @@ struct ExplicitSP {
 #pragma unroll
         for (int e = 0; e < E; ++e) m[e] = 0.f;
     }
+    template <bool FP = true>
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float, float clampv,
                                           bool &same, float keep = 1.f) {
         constexpr int D2 = C::D * C::D;
@@ -556,7 +574,7 @@ struct ExplicitSP {
             asm volatile("" : "+v"(diff));
             __builtin_amdgcn_sched_barrier(0);
         });
-        same = diff == 0u;
+        same = FP && diff == 0u;
         return sat;
     }
     template <int c, int k>
@@ -1101,7 +1119,7 @@ struct Blk {
     }
 };
 
-template <class C, int WG, bool BPERM, int FORM, bool PLAIN = false>
+template <class C, int WG, bool BPERM, int FORM, bool PLAIN = false, bool FP = true>
 __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x,
                                             const lead::PlainArgs &pl = lead::PlainArgs{},
                                             const Blk blk = Blk::of_launch()) {
@@ -1272,22 +1290,22 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
     for (int t = t0; t <= t1; ++t) {
         // computed by every lane (see local_body); done lanes discard it
         bool same;
-        const bool sat = st.check(S, sv, a.beta, a.clampv, same);
-        bool shot_sat, shot_same;
+        const bool sat = st.template check<FP>(S, sv, a.beta, a.clampv, same);
+        bool shot_sat, shot_same = false;
         if constexpr (BPERM) {
             // the shot's flags are ballots over its lanes: no LDS, no barrier
-            const uint64_t unsat = __ballot(!done && !sat), chg = __ballot(!done && !same);
+            const uint64_t unsat = __ballot(!done && !sat);
             shot_sat = (unsat & smask) == 0ull;
-            shot_same = (chg & smask) == 0ull;
+            if constexpr (FP) shot_same = (__ballot(!done && !same) & smask) == 0ull;
         } else {
             // more than 64 views: one shot per workgroup (its live lanes
             // have sl = 0), whose flags every lane reads, so that the end of
             // its run is known to all lanes without a second barrier
             if (!done && !sat) shf[(t & 1)] = 1;
-            if (!done && !same) shf[SF_CHG] = t;
+            if (FP && !done && !same) shf[SF_CHG] = t;
             __syncthreads();
             shot_sat = shf[(t & 1)] == 0;
-            shot_same = shf[SF_CHG] != t;
+            if constexpr (FP) shot_same = shf[SF_CHG] != t;
         }
         // (one shot per workgroup, !BPERM: the loop ends right here for
         // every lane, and the outputs are written after it, from the same S)
@@ -1297,7 +1315,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
                 gconv = 1;
                 itg = t - 1;
                 if constexpr (BPERM) emit();
-            } else if (a.fixed_stop && shot_same) {
+            } else if (FP && a.fixed_stop_g && shot_same) {
                 done = true;
                 gconv = shot_sat ? 1 : 0;
                 itg = a.Tg;
@@ -1309,7 +1327,7 @@ __device__ __forceinline__ void global_body(const DecodeArgs &a, const LocalArgs
             if (__ballot(!done) == 0ull) break;
         } else {
             // the live lanes' own decision above, taken by every lane
-            if (!wdone && t > 1 && ((shot_sat && a.early_exit) || (a.fixed_stop && shot_same))) wdone = true;
+            if (!wdone && t > 1 && ((shot_sat && a.early_exit) || (FP && a.fixed_stop_g && shot_same))) wdone = true;
             if (wdone) break;
             if (tid == 0) shf[((t + 1) & 1)] = 0;
         }
@@ -1513,7 +1531,7 @@ __device__ __forceinline__ void tile_read(const float *buf, const uint4 (&pr)[NR
 enum { TW_F0 = 0, TW_F1, TW_CHG, TW_ITSUM, TW_ITMAX, TW_NCONV, TW_NFIX, TW_NOSD, TW_T, TW_ITG, TW_CONV, TW_FIX,
        TW_SHOT_LO, TW_SHOT_HI, TW_AWAIT, TW_WORDS };
 
-template <class C, int FORM>
+template <class C, int FORM, bool FP = true>
 __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const LocalArgs &w, const SpecArgs &x) {
     constexpr int WG = lead::kTileWG;
     constexpr int D2 = C::D * C::D, NP = (D2 + 1) / 2;
@@ -1727,12 +1745,12 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
         // ---- one global round of every slot's shot (Phase 3); the slot's
         // round number and shot are read from its LDS words
         bool same;
-        const bool sat = st.check(S, sv, a.beta, a.clampv, same);
+        const bool sat = st.template check<FP>(S, sv, a.beta, a.clampv, same);
         const int64_t shot = slot_shot();
         const bool live = lane_ok && shot >= 0 && shot < a.shots;
         const int t = word(TW_T);
         if (live && !sat) word(t & 1) = 1;
-        if (live && !same) word(TW_CHG) = t;
+        if (FP && live && !same) word(TW_CHG) = t;
         // lambda' of the owned positions for this round's partial sums, read
         // before the barrier so that the wait covers their latency
         float lr[D2];
@@ -1742,7 +1760,7 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
         });
         __syncthreads();
         if (live) {
-            const bool shot_sat = word(t & 1) == 0, shot_same = word(TW_CHG) != t;
+            const bool shot_sat = word(t & 1) == 0, shot_same = FP && word(TW_CHG) != t;
             bool end = false;
             int gconv = 0, itg = a.Tg, gfix = 0;
             if (t > 1 && shot_sat && a.early_exit) {
@@ -1752,7 +1770,7 @@ __device__ __forceinline__ void global_tile_body(const DecodeArgs &a, const Loca
             } else if (t > a.Tg) {   // ran to the cap: S holds round Tg's sums
                 end = true;
                 gconv = shot_sat ? 1 : 0;
-            } else if (t > 1 && a.fixed_stop && shot_same) {
+            } else if (t > 1 && FP && a.fixed_stop_g && shot_same) {
                 end = true;
                 gconv = shot_sat ? 1 : 0;
                 gfix = t;

@@ -300,7 +300,11 @@ def test_plain_form_bit_identical(name, t, shots, p, T, kw):
                                             ("L", 8, 0.02, 64)])
 def test_fixed_point_stop_is_exact(name, shots, p, T):
     """Ending a BP run whose message state reproduces itself gives exactly the
-    outputs and reported counts of running every iteration to the cap."""
+    outputs and reported counts of running every iteration to the cap: the
+    test on local and global runs (fixed_point_stop = 1), on local runs only
+    (2: the Phases 2-3 kernel compiled without the per-message comparison)
+    and none (0), on the compiled kernels and in the plain form."""
+    import paper_2605_17796_amd as P
     spec, oc = code_pair(name)
     torch = torch_dev()
     code, dec = gpu_decoder(spec, max_iter_local=T, max_iter_global=T, fixed_point_stop=1)
@@ -309,14 +313,26 @@ def test_fixed_point_stop_is_exact(name, shots, p, T):
     lam = torch.from_numpy(lamv).cuda()
     a = dec.decode(synd, lam, lam=True)
     pa = dec.decode(synd, lam, lam=True, plain=True)
+    dec.set_params(max_iter_local=T, max_iter_global=T, fixed_point_stop=2)
+    c = dec.decode(synd, lam, lam=True)
+    pc = dec.decode(synd, lam, lam=True, plain=True)
     dec.set_params(max_iter_local=T, max_iter_global=T, fixed_point_stop=0)
     b = dec.decode(synd, lam, lam=True)
     torch.cuda.synchronize()
     for k in ("ehat", "post", "lam"):
         assert torch.equal(a[k], b[k]), k
         assert torch.equal(pa[k], b[k]), k
-    assert torch.equal(a["stats"][:, :5], b["stats"][:, :5])
-    assert torch.equal(pa["stats"][:, :5], b["stats"][:, :5])
+        assert torch.equal(c[k], b[k]), k
+        assert torch.equal(pc[k], b[k]), k
+    for r in (a, pa, c, pc):
+        assert torch.equal(r["stats"][:, :5], b["stats"][:, :5])
+    # the local fixed-view counts of 1 and 2 agree; 2 reports no global fixed point
+    for r in (c, pc):
+        assert torch.equal(r["stats"][:, 5], a["stats"][:, 5])
+        assert int(r["stats"][:, 6].abs().sum()) == 0
+    assert int(b["stats"][:, 5:7].abs().sum()) == 0
+    with pytest.raises(P.LeadError):
+        dec.set_params(max_iter_local=T, max_iter_global=T, fixed_point_stop=3)
     st = a["stats"].cpu().numpy()
     log(f"[fixed] {name} p={p}: local views stopped at a fixed point {st[:, 5].sum() / (shots * code.info.order):.3f}, "
         f"shots with a global fixed point {(st[:, 6] > 0).mean():.3f} (mean iteration "
