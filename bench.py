@@ -369,36 +369,48 @@ def main():
     out = dec.alloc_outputs(shots)
     torch.cuda.synchronize()
 
-    # ---- schedule of the headline: the autotuner's choice (or --schedule)
-    if args.schedule is not None or args.roofline_only:
-        best = dict(DEFAULT_SCHEDULE if args.schedule is None else json.loads(args.schedule))
-        dec.set_schedule(**best)
-        best = dec.get_schedule()
-    else:
-        best = dec.autotune(synd_pool[0], lam)
-
-    # ---- roofline pass: eager decodes with that schedule; HIP events on the
+    # ---- roofline pass: eager decodes with a schedule; HIP events on the
     #      decode stream around every Phase 1 and Phases 2-3 launch.  The
     #      fixed-point exit is off in this pass: a run it ends reports the cap
     #      as its iteration count, and the edge updates counted from the
     #      statistics must be ones the kernels execute
-    dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], ms_scale=0.75, alpha=1.0,
-                   fixed_point_stop=0)
-    dec.decode(synd_pool[0], lam, out=out)
-    torch.cuda.synchronize()
     rl_reps = 2 if args.roofline_only else 4
-    dec.time_phases(True)
-    eu_local = eu_global = 0.0
-    for i in range(rl_reps):
-        dec.decode(synd_pool[i % pool_batches], lam, out=out)
-        st = out["stats"].cpu().numpy()
-        a, b = edge_updates(st, info.eloc[args.check_type], info.order)
-        eu_local += a
-        eu_global += b
-    pt = dec.phase_times()
-    dec.time_phases(False)
-    dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], fixed_point_stop=FIXED_POINT,
-                   ms_scale=0.75, alpha=1.0)
+
+    def roofline_pass():
+        dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], ms_scale=0.75, alpha=1.0,
+                       fixed_point_stop=0)
+        dec.decode(synd_pool[0], lam, out=out)
+        torch.cuda.synchronize()
+        dec.time_phases(True)
+        eu = [0.0, 0.0]
+        for i in range(rl_reps):
+            dec.decode(synd_pool[i % pool_batches], lam, out=out)
+            st = out["stats"].cpu().numpy()
+            a, b = edge_updates(st, info.eloc[args.check_type], info.order)
+            eu[0] += a
+            eu[1] += b
+        pt = dec.phase_times()
+        dec.time_phases(False)
+        dec.set_params(max_iter_local=ROUNDS[cname], max_iter_global=ROUNDS[cname], fixed_point_stop=FIXED_POINT,
+                       ms_scale=0.75, alpha=1.0)
+        return eu[0], eu[1], pt
+
+    # ---- schedule of the headline: the autotuner's choice (or --schedule).
+    #      The roofline pass runs before the autotuner's trial decodes, on
+    #      the default schedule (the state of the profiled runs), and again
+    #      on the autotuner's choice only where that differs
+    if args.schedule is not None or args.roofline_only:
+        best = dict(DEFAULT_SCHEDULE if args.schedule is None else json.loads(args.schedule))
+        dec.set_schedule(**best)
+        best = dec.get_schedule()
+        eu_local, eu_global, pt = roofline_pass()
+    else:
+        dec.set_schedule(**DEFAULT_SCHEDULE)
+        rl_sched = dec.get_schedule()
+        eu_local, eu_global, pt = roofline_pass()
+        best = dec.autotune(synd_pool[0], lam)
+        if best != rl_sched:
+            eu_local, eu_global, pt = roofline_pass()
     if pt["global_launches"] == 0:
         raise SystemExit(f"the schedule {best} does not run the work-queue form, which the roofline pass times")
     d2 = info.delta ** 2
