@@ -135,7 +135,9 @@ typedef struct {
     int32_t boost;            /* 1: Phase-1 confidence boost (Alg. 1)             */
     int32_t fixed_point_stop; /* 1: end a BP run whose messages reproduce
                                  themselves bit for bit (every later iteration
-                                 would repeat it); results and reported
+                                 would repeat it; local runs are tested at
+                                 even iterations, global runs at every one);
+                                 results and reported
                                  iteration counts are identical to running to
                                  the cap.  2: local BP runs only (global BP
                                  then runs kernels without the per-message

@@ -192,7 +192,8 @@ __device__ __forceinline__ void load_priors(const DecodeArgs &a, int64_t shot, i
 // iteration t (which also tests S^{t-1}) and, unless the run ends, the
 // variable update S^t.  A run ends at the first t > 1 whose S^{t-1} satisfies
 // the local syndrome (early exit), when the messages stop changing (a fixed
-// point: every later iteration repeats S^{t-1}), or at t = Tl + 1 (the cap,
+// point: every later iteration repeats S^{t-1}; tested at even t), or at
+// t = Tl + 1 (the cap,
 // where the test is the final syndrome test).  On return `fin` tells whether
 // the run ended; conv, it, fixed describe it.
 template <int D, int RMAX, int WG, int PM>
@@ -211,7 +212,7 @@ __device__ __forceinline__ bool local_step(const DecodeArgs &a, float *bl, uint6
         it = t - 1;
         return true;
     }
-    if (t > 1 && same && a.fixed_stop) {
+    if ((t & 1) == 0 && same && a.fixed_stop) {   // tested at even t, as in the compiled kernels
         conv = sat ? 1 : 0;
         it = a.Tl;
         fixed = 1;

@@ -479,6 +479,7 @@ struct ExplicitSplit {
 #pragma unroll
         for (int e = 0; e < ER; ++e) m[e] = 0.f;
     }
+    template <bool FP = true>
     __device__ __forceinline__ bool check(const float (&S)[C::D * C::D], uint64_t sv, float beta, float clampv,
                                           bool &same, float keep = 1.f) {
         bool sat = true;
@@ -489,14 +490,14 @@ struct ExplicitSplit {
                 constexpr int lb = split_base<C>(c, true), DEG = C::deg[c];
                 float ml[DEG];
                 static_for<0, DEG>([&](auto kk) { ml[decltype(kk)::value] = lm[(lb + decltype(kk)::value) * 64]; });
-                explicit_update<C, c, 0, DEG>(S, sv, beta, clampv, keep, ml, sat, diff);
+                explicit_update<C, c, 0, DEG, FP>(S, sv, beta, clampv, keep, ml, sat, diff);
                 static_for<0, DEG>([&](auto kk) { lm[(lb + decltype(kk)::value) * 64] = ml[decltype(kk)::value]; });
             } else {
-                explicit_update<C, c, split_base<C>(c, false), (ER > 0 ? ER : 1)>(S, sv, beta, clampv, keep, m, sat,
-                                                                                  diff);
+                explicit_update<C, c, split_base<C>(c, false), (ER > 0 ? ER : 1), FP>(S, sv, beta, clampv, keep, m,
+                                                                                      sat, diff);
             }
         });
-        same = diff == 0u;
+        same = FP && diff == 0u;
         return sat;
     }
     __device__ __forceinline__ void accumulate(float (&S)[C::D * C::D], float keep = 1.f) const {
@@ -835,6 +836,16 @@ __device__ __forceinline__ uint64_t osd_local(const float (&L)[C::D * C::D], con
 // variable update gives S^0 = lambda exactly).  Only the output stores are
 // divergent.  Updating S or the check states under a divergent branch would
 // make the compiler keep the old and the new copies of them live at once.
+// Items are tested for a fixed point at even t (the rule of the precompiled
+// kernels too).  With one register per message and one prior per shot
+// (ALT) the loop runs two iterations per pass, the first without the test
+// (new messages overwrite the old ones in place), the second with it, and
+// hands out items only before the first, so that every item starts at an
+// odd pass step: the comparison, its copies at the back-edge and the
+// hand-out cost once per two iterations; a lane whose run ends in the first
+// iteration idles in the second.  Elsewhere (the LDS-resident messages of
+// the largest views, a prior per qubit, the other forms) one iteration per
+// pass, each compiled with the comparison.
 template <class C, int PM, int FORM>
 __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs &w) {
     constexpr int D2 = C::D * C::D;
@@ -859,6 +870,49 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     }
     st.clear();
     float keep = 0.f;
+    constexpr bool ALT = FORM == 2 && PM == 0 && C::LDSMASK == 0u;
+    // One iteration of the item in each lane: the variable update, then the
+    // check update with or without the fixed-point test.
+    auto step = [&](auto fp_tag) {
+        constexpr bool FPT = decltype(fp_tag)::value == 1;
+#pragma unroll
+        for (int j = 0; j < D2; ++j) S[j] = lam[PM == 0 ? 0 : j];
+        st.accumulate(S, keep);
+        bool same;
+        const bool sat = st.template check<FPT>(S, sv, a.beta, a.clampv, same, keep);
+        keep = 1.f;
+        int conv = 0, it = 0, fixed = 0;
+        bool fin = false;
+        if (t > a.Tl) {
+            conv = sat ? 1 : 0;
+            it = a.Tl;
+            fin = true;
+        } else if (t > 1 && sat && a.early_exit) {
+            conv = 1;
+            it = t - 1;
+            fin = true;
+        } else if (FPT && (t & 1) == 0 && same && a.fixed_stop) {
+            conv = sat ? 1 : 0;
+            it = a.Tl;
+            fixed = 1;
+            fin = true;
+        }
+        if (valid && fin) {
+            float *out = w.Lv + item * D2;
+            float Lc[D2];
+#pragma unroll
+            for (int j = 0; j < D2; ++j) Lc[j] = clampf(S[j], a.clampv);
+#pragma unroll
+            for (int j = 0; j < D2; ++j) out[j] = Lc[j];
+            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
+            // a view that missed its local syndrome is post-processed by
+            // local_osd_body with every lane busy, not here with one
+            if (a.local_osd && !conv)
+                w.osd_list[atomicAdd(reinterpret_cast<unsigned long long *>(w.counter + 1), 1ull)] = (uint32_t)item;
+            valid = false;
+        }
+        ++t;
+    };
     for (;;) {
         uint64_t need = __ballot(!valid);
         while (need && queue_open) {
@@ -897,43 +951,11 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
             need = __ballot(!valid);
         }
         if (__ballot(valid) == 0ull) break;
-#pragma unroll
-        for (int j = 0; j < D2; ++j) S[j] = lam[PM == 0 ? 0 : j];
-        st.accumulate(S, keep);
-        bool same;
-        const bool sat = st.check(S, sv, a.beta, a.clampv, same, keep);
-        keep = 1.f;
-        int conv = 0, it = 0, fixed = 0;
-        bool fin = false;
-        if (t > a.Tl) {
-            conv = sat ? 1 : 0;
-            it = a.Tl;
-            fin = true;
-        } else if (t > 1 && sat && a.early_exit) {
-            conv = 1;
-            it = t - 1;
-            fin = true;
-        } else if (t > 1 && same && a.fixed_stop) {
-            conv = sat ? 1 : 0;
-            it = a.Tl;
-            fixed = 1;
-            fin = true;
+        if constexpr (ALT) {
+            step(Int<0>{});   // odd t: no fixed-point test
+            if (__ballot(valid) == 0ull) continue;
         }
-        if (valid && fin) {
-            float *out = w.Lv + item * D2;
-            float Lc[D2];
-#pragma unroll
-            for (int j = 0; j < D2; ++j) Lc[j] = clampf(S[j], a.clampv);
-#pragma unroll
-            for (int j = 0; j < D2; ++j) out[j] = Lc[j];
-            w.vflag[item] = (uint32_t)it | ((uint32_t)conv << 16) | ((uint32_t)fixed << 17);
-            // a view that missed its local syndrome is post-processed by
-            // local_osd_body with every lane busy, not here with one
-            if (a.local_osd && !conv)
-                w.osd_list[atomicAdd(reinterpret_cast<unsigned long long *>(w.counter + 1), 1ull)] = (uint32_t)item;
-            valid = false;
-        }
-        ++t;
+        step(Int<1>{});
     }
 }
 
