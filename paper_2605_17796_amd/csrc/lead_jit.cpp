@@ -230,9 +230,10 @@ bool osd_fits(const Code &c, int t) {
     return m > 0 && c.n > 0 && RPL * W <= kOsdMaxWords && RPL <= 32;
 }
 
-uint32_t local_lds_mask(const TypeTables &tt) {
-    if (tt.eloc <= kTwoWaveMaxEdges || tt.r > 32) return 0u;
-    // lowest degree first (ties: lowest index), until the rest fit
+namespace {
+// The lowest-degree checks (ties: lowest index) whose messages go to LDS
+// until at most reg_max stay in registers, and their edges.
+uint32_t lds_mask_for(const TypeTables &tt, int reg_max) {
     std::vector<int> order(tt.r);
     for (int i = 0; i < tt.r; ++i) order[i] = i;
     auto deg = [&](int i) { return __builtin_popcountll(tt.mask[i]); };
@@ -240,20 +241,32 @@ uint32_t local_lds_mask(const TypeTables &tt) {
     uint32_t m = 0u;
     int reg = tt.eloc;
     for (int i : order) {
-        if (reg <= kLocalRegEdges) break;
+        if (reg <= reg_max) break;
         m |= 1u << i;
         reg -= deg(i);
     }
     return m;
 }
-
-int local_lds_edges(const TypeTables &tt) {
-    const uint32_t m = local_lds_mask(tt);
+int mask_edges(const TypeTables &tt, uint32_t m) {
     int e = 0;
     for (int i = 0; i < tt.r; ++i)
         if ((m >> i) & 1u) e += __builtin_popcountll(tt.mask[i]);
     return e;
 }
+}  // namespace
+
+bool local_alt(const TypeTables &tt) {
+    if (tt.r > 32) return tt.eloc <= kTwoWaveMaxEdges;
+    if (tt.eloc <= kTwoWaveMaxEdges) return true;
+    return 64 * 4 * mask_edges(tt, lds_mask_for(tt, kLocalAltRegEdges)) <= kLocalAltLdsBytes;
+}
+
+uint32_t local_lds_mask(const TypeTables &tt) {
+    if (tt.eloc <= kTwoWaveMaxEdges || tt.r > 32) return 0u;
+    return lds_mask_for(tt, local_alt(tt) ? kLocalAltRegEdges : kLocalRegEdges);
+}
+
+int local_lds_edges(const TypeTables &tt) { return mask_edges(tt, local_lds_mask(tt)); }
 
 bool tile_fits(const Code &c, int t) {
     const int D2 = c.delta * c.delta;
@@ -315,6 +328,7 @@ void emit_code_struct(std::ostringstream &o, const Code &c, int t, const std::st
 
       << "    static constexpr int HYB = " << hybrid_degree(tt) << ";\n"
       << "    static constexpr unsigned LDSMASK = " << local_lds_mask(tt) << "u;\n"
+      << "    static constexpr bool LOCAL_ALT = " << (local_alt(tt) ? "true" : "false") << ";\n"
       << "    static constexpr bool LAM_LDS = " << (lam_lds_fits(c, t) ? "true" : "false") << ";\n"
       << "    static constexpr uint64_t mask[" << tt.r << "] = {";
     for (int i = 0; i < tt.r; ++i) o << (i ? ", " : "") << "0x" << std::hex << tt.mask[i] << std::dec << "ull";

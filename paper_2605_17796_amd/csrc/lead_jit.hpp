@@ -41,10 +41,18 @@ constexpr int kThreeWaveMaxState = 96;
 // keeps the messages of its lowest-degree checks in LDS, so that at most
 // this many stay in registers and it runs two waves per SIMD.
 constexpr int kLocalRegEdges = 96;
+// ... at most kLocalAltRegEdges where the LDS that then takes (64 lanes per
+// wave) lets eight waves share a CU's 160 KB: the kernel then runs its
+// iterations in pairs, the first without the fixed-point comparison (more
+// live registers than one iteration per pass).
+constexpr int kLocalAltRegEdges = 80;
+constexpr int kLocalAltLdsBytes = 20 * 1024;
 // The checks (bit c) whose messages that kernel keeps in LDS, and their
-// edges.
+// edges; whether it runs its iterations in pairs (LOCAL_ALT of the code
+// struct).
 uint32_t local_lds_mask(const TypeTables &tt);
 int local_lds_edges(const TypeTables &tt);
+bool local_alt(const TypeTables &tt);
 constexpr int kHybridExplicitEdges = 72;
 
 // The persistent Phases 2-3 kernel (lead_spec::global_tile_body) for codes

@@ -837,15 +837,17 @@ __device__ __forceinline__ uint64_t osd_local(const float (&L)[C::D * C::D], con
 // divergent.  Updating S or the check states under a divergent branch would
 // make the compiler keep the old and the new copies of them live at once.
 // Items are tested for a fixed point at even t (the rule of the precompiled
-// kernels too).  With one register per message and one prior per shot
-// (ALT) the loop runs two iterations per pass, the first without the test
-// (new messages overwrite the old ones in place), the second with it, and
-// hands out items only before the first, so that every item starts at an
-// odd pass step: the comparison, its copies at the back-edge and the
-// hand-out cost once per two iterations; a lane whose run ends in the first
-// iteration idles in the second.  Elsewhere (the LDS-resident messages of
-// the largest views, a prior per qubit, the other forms) one iteration per
-// pass, each compiled with the comparison.
+// kernels too).  In form 2 with one prior per shot, where the code allows it
+// (C::LOCAL_ALT: the views' messages in registers, or enough of them in LDS
+// that two iterations fit the registers of two waves per SIMD), the loop
+// runs two iterations per pass, the first without the test (new messages
+// overwrite the old ones in place), the second with it, and hands out items
+// only before the first, so that every item starts at an odd pass step: the
+// comparison, its copies at the back-edge and the hand-out cost once per two
+// iterations; a lane whose run ends in the first iteration idles in the
+// second.  Elsewhere (a prior per qubit, the other forms, views whose LDS
+// share would not leave room for eight waves per CU) one iteration per pass,
+// each compiled with the comparison.
 template <class C, int PM, int FORM>
 __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs &w) {
     constexpr int D2 = C::D * C::D;
@@ -870,7 +872,7 @@ __device__ __forceinline__ void local_body(const DecodeArgs &a, const LocalArgs 
     }
     st.clear();
     float keep = 0.f;
-    constexpr bool ALT = FORM == 2 && PM == 0 && C::LDSMASK == 0u;
+    constexpr bool ALT = FORM == 2 && PM == 0 && C::LOCAL_ALT;
     // One iteration of the item in each lane: the variable update, then the
     // check update with or without the fixed-point test.
     auto step = [&](auto fp_tag) {
