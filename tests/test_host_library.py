@@ -179,3 +179,12 @@ def test_per_shot_kernel_register_budget(name, t, tmp_path):
     src = "".join(p.read_text() for p in tmp_path.glob("*.hip"))
     hyb = {("M", 0): 0, ("M", 1): 0, ("L", 0): 11, ("L", 1): 1}[(name, t)]
     assert f"HYB = {hyb};" in src
+    # the Phase 1 queue kernel of form 2: the checks whose messages live in
+    # LDS, and whether it runs its iterations in pairs (A5: every message in
+    # registers; PSL(2,7) Z checks: the checks of degree <= 10 and the first
+    # of degree 12, 78 messages, in LDS, 20 KB per wave; X checks: pairs would
+    # need 27 KB per wave, so the nine of degree 9 and the first of degree 12
+    # go to LDS and the kernel tests every pass)
+    lds, alt = {("M", 0): (0, "true"), ("M", 1): (0, "true"), ("L", 0): (0xFFA8, "true"),
+                ("L", 1): (0x770F, "false")}[(name, t)]
+    assert f"LDSMASK = {lds}u;" in src and f"LOCAL_ALT = {alt};" in src
