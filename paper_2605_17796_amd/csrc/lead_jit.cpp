@@ -394,10 +394,10 @@ std::string source(const Code &c, int t, bool sp) {
             o << "extern \"C\" __global__ void __launch_bounds__(" << lead::kTileWG << ") lead_spec_tile_" << form
               << "(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { lead_spec::global_tile_body<LeadCode, "
               << form << ">(a, w, x); }\n";
-        // the explicit form without the fixed-point test of global BP: the
-        // decode's Phases 2-3 kernel when that test is off
-        if (form == kExplicit) {
-            if (tile_fits(c, t))
+        // the explicit and sum-product forms without the fixed-point test of
+        // global BP: the decode's Phases 2-3 kernel when that test is off
+        if (form == kExplicit || form == kSumProduct) {
+            if (form == kExplicit && tile_fits(c, t))
                 o << "extern \"C\" __global__ void __launch_bounds__(" << lead::kTileWG << ") lead_spec_tile_" << form
                   << "n(lead::DecodeArgs a, lead::LocalArgs w, lead::SpecArgs x) { "
                      "lead_spec::global_tile_body<LeadCode, " << form << ", false>(a, w, x); }\n";
@@ -527,8 +527,8 @@ std::shared_ptr<const Kernels> load(const Code &c, int t, int device, bool sp, s
         if (e == hipSuccess) e = hipModuleGetFunction(&k->round[form - 1], k->module, ("lead_spec_round_" + f).c_str());
         if (e == hipSuccess && form != kSumProduct && tile_fits(c, t))
             e = hipModuleGetFunction(&k->tile[form - 1], k->module, ("lead_spec_tile_" + f).c_str());
-        if (e == hipSuccess && form == kExplicit)
-            e = tile_fits(c, t)
+        if (e == hipSuccess && (form == kExplicit || form == kSumProduct))
+            e = form == kExplicit && tile_fits(c, t)
                     ? hipModuleGetFunction(&k->tile_nf[form - 1], k->module, ("lead_spec_tile_" + f + "n").c_str())
                     : hipModuleGetFunction(&k->global_nf[form - 1], k->module, ("lead_spec_global_" + f + "n").c_str());
         if (e == hipSuccess) k->has[form - 1] = true;

@@ -91,7 +91,7 @@ struct Kernels {
     hipFunction_t tile[kForms] = {};     // [form - 1]: persistent Phases 2-3 (views over several waves)
     // [form - 1]: `global` / `tile` without the fixed-point test of global
     // BP (no per-message comparison; compiled for the explicit form, the
-    // per-shot one only where `tile` is not)
+    // per-shot one only where `tile` is not, and for sum-product)
     hipFunction_t global_nf[kForms] = {};
     hipFunction_t tile_nf[kForms] = {};
     int tile_shots = 0;                  // shots per workgroup of `tile`

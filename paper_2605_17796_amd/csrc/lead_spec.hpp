@@ -567,11 +567,16 @@ struct ExplicitSP {
                 const float ex = (uint32_t)j == amax ? rest : fmax == __builtin_inff() ? fmax : fmax + (rest - f[j]);
                 uint32_t mag = __float_as_uint(phi(ex));
                 const uint32_t sgn = (__float_as_uint(mu[j]) & kSign) ^ px;
-                const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + k]);
-                diff |= dterm;
-                asm("" : "+v"(mag) : "v"(dterm));
+                if constexpr (FP) {
+                    const uint32_t dterm = mag ^ sgn ^ __float_as_uint(m[b + k]);
+                    diff |= dterm;
+                    asm("" : "+v"(mag) : "v"(dterm));
+                }
                 m[b + k] = __uint_as_float(mag | sgn);
             });
+            // without the comparison the new messages are formed here all
+            // the same (see explicit_update)
+            if constexpr (!FP) for_edges<C, c>([&](auto, auto kk) { asm volatile("" : "+v"(m[b + decltype(kk)::value])); });
             asm volatile("" : "+v"(diff));
             __builtin_amdgcn_sched_barrier(0);
         });

@@ -39,6 +39,33 @@ def test_sum_product_matches_oracle(name, t, p, T, alpha, min_well):
     assert well >= min_well
 
 
+@pytest.mark.parametrize("name,p,T", [("T", 0.05, 32), ("M", 0.05, 50)])
+def test_sum_product_fixed_point_variants_equal(name, p, T):
+    """The fixed-point exit on both stages (1), on local runs only (2: the
+    Phases 2-3 kernel compiled without the comparison) and off (0) give the
+    same outputs bit for bit; only the fixed-point statistics differ."""
+    torch = torch_dev()
+    spec, oc = code_pair(name)
+    code, dec = gpu_decoder(spec, max_iter_local=T, max_iter_global=T, bp=SP, fixed_point_stop=1)
+    e, _, lamv = bitflip_inputs(oc, 400, p, seed=83)
+    s = torch.from_numpy(_gpu_syndrome(dec, e).view(np.int64)).cuda()
+    lam = torch.from_numpy(lamv).cuda()
+    runs = {}
+    for fp in (1, 2, 0):
+        dec.set_params(max_iter_local=T, max_iter_global=T, bp=SP, fixed_point_stop=fp)
+        runs[fp] = dec.decode(s, lam, lam=True)
+    torch.cuda.synchronize()
+    for fp in (2, 0):
+        for k in ("ehat", "post", "lam"):
+            assert torch.equal(runs[fp][k], runs[1][k]), (fp, k)
+        assert torch.equal(runs[fp]["stats"][:, :5], runs[1]["stats"][:, :5]), fp
+    assert torch.equal(runs[2]["stats"][:, 5], runs[1]["stats"][:, 5])
+    assert int(runs[2]["stats"][:, 6].abs().sum()) == 0 and int(runs[0]["stats"][:, 5:7].abs().sum()) == 0
+    st = runs[1]["stats"].cpu().numpy()
+    log(f"[sum-product] {name} p={p}: fixed_point_stop 1/2/0 bit-identical; shots with a global fixed point "
+        f"{(st[:, 6] > 0).mean():.3f}")
+
+
 def test_sum_product_batched_and_served_equal_alone():
     import paper_2605_17796_amd as P
     torch = torch_dev()
